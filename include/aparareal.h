@@ -1,0 +1,117 @@
+/*
+ * aparareal.h -- C ABI of the MI355X (gfx950) asymptotic parareal library.
+ *
+ * Problem (Haut & Wingate, Sec. 1, eq. full eqn; Sec. 6.1, eq. RSW equations):
+ *     du/dt + (1/eps) L u = N(u) + D u,   u = (v1, v2, h) periodic on [0, 2 pi),
+ *     L = [[0, -1, F^{-1/2} d/dx], [1, 0, 0], [F^{-1/2} d/dx, 0, 0]],
+ *     D = -nu d^4/dx^4 (hyperviscosity, damping),
+ *     N(u) = -(v1 dv1/dx, v1 dv2/dx, d(h v1)/dx).
+ * Fourier pseudo-spectral discretisation on x_j = 2 pi j / N with the 2/3 rule
+ * (retained wavenumbers |k| <= floor(N/3)); every input state is projected onto
+ * that band first.
+ *
+ * Conventions for every call below:
+ *   - Arrays are DEVICE pointers (HIP global memory, e.g. torch CUDA tensors)
+ *     unless marked host.  Physical states are float64, row-major
+ *     [batch][3][N] with fields in the order (v1, v2, h) and x_j = 2 pi j / N.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *     default stream); outputs are valid once that stream has completed.
+ *     Calls return after enqueueing; host-side argument errors are reported
+ *     before anything is enqueued.
+ *   - The caller owns every array it passes.  The library owns the context
+ *     (coefficient tables, device scratch) and the server.
+ *   - Return value: AP_OK (0) or a negative AP_E* code; the thread-local
+ *     message of the last failure is aparareal_last_error().
+ *   - precision: AP_PREC_FP32 runs the propagators (FFTs, nonlinear term,
+ *     exponential integrator, time average) in FP32 with FP64 inputs/outputs
+ *     and FP64 parareal correction; AP_PREC_FP64 runs everything in FP64.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef APARAREAL_H
+#define APARAREAL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  AP_OK = 0,
+  AP_PENDING = 1,     /* serving: request not finished yet                     */
+  AP_EINVAL = -1,     /* bad argument (size, parameter, NULL pointer)          */
+  AP_ENOMEM = -2,     /* device allocation failed / request exceeds budget     */
+  AP_EDEVICE = -3,    /* a HIP runtime call failed                             */
+  AP_ENOTFOUND = -4,  /* unknown serving ticket                                */
+  AP_ENUMERIC = -5,   /* non-finite state or residual                          */
+  AP_EBUSY = -6       /* server shutting down                                  */
+};
+
+enum { AP_PREC_FP32 = 0, AP_PREC_FP64 = 1 };
+
+typedef struct ap_ctx ap_ctx;
+
+/* Message of the last failed call on this host thread ("" if none).          */
+const char* aparareal_last_error(void);
+
+/* Create a context for grid size N (power of two, 64 <= N <= 2048), small
+ * parameter eps > 0, F > 0 (the Froude-type constant of Sec. 6.1) and
+ * hyperviscosity nu >= 0 on the current HIP device.  NULL on error.          */
+ap_ctx* aparareal_create(int N, double eps, double F, double nu);
+
+/* Release the context and its device memory (synchronises the device).      */
+int aparareal_destroy(ap_ctx* ctx);
+
+/* Dealiased nonlinear term N(u) (Sec. 6.1, operator table; sign taken from
+ * the RSW equations): U_in, N_out physical [batch][3][N].                     */
+int aparareal_nonlinear(ap_ctx* ctx, const double* U_in, double* N_out, int batch,
+                        int precision, void* stream);
+
+/* Fine propagator (ETDRK4 of Cox & Matthews, the fine integrator of Sec. 6.2):
+ * `steps` exponential RK4 steps of length dT/steps applied to every state of
+ * the batch at once (the parallel "parfor" over slices of Alg. 4).
+ * U_in, U_out physical [batch][3][N]; U_out may not alias U_in.               */
+int aparareal_fine_batch(ap_ctx* ctx, const double* U_in, double* U_out, int batch,
+                         double dT, int steps, int precision, void* stream);
+
+/* Kernel-weighted time average of the nonlinear term (Sec. 2, eq. numerical
+ * average; Alg. 1): Nbar(u) = (1/M) sum_{m<M} rho(m/M) exp(s_m L) N(exp(-s_m L) u),
+ * s_m = m T0 / M (fast time), rho the smooth bump of Sec. 2.
+ * U_in, Nbar_out physical [batch][3][N]; M >= 2, T0 > 0.                      */
+int aparareal_average(ap_ctx* ctx, const double* U_in, double* Nbar_out, int batch,
+                      double T0, int M_avg, int precision, void* stream);
+
+/* Asymptotic coarse step G (Alg. 2): half dissipative step, explicit midpoint
+ * step of the averaged nonlinear flow, half dissipative step, rotation by
+ * exp(-(dT/eps) L).  T0 <= 0 selects T0 = dT/eps (average over one coarse
+ * step, Sec. 4).  U_in, U_out physical [batch][3][N].                         */
+int aparareal_coarse(ap_ctx* ctx, const double* U_in, double* U_out, int batch,
+                     double dT, int M_avg, double T0, int precision, void* stream);
+
+typedef struct {
+  double T;          /* final time; slices of length dT = T / slices             */
+  int slices;        /* Ns >= 1                                                   */
+  int K;             /* parareal iterations after the coarse initial guess >= 0  */
+  double dt_fine;    /* requested fine step; fine steps per slice = ceil(dT/dt)  */
+  int M_avg;         /* averaging samples M >= 2                                 */
+  double T0;         /* fast-time averaging window; <= 0 selects dT/eps          */
+  double tol;        /* > 0: stop once the residual drops to tol (host sync per  */
+                     /* iteration); <= 0: run exactly K iterations               */
+  int precision;     /* AP_PREC_FP32 or AP_PREC_FP64                              */
+} ap_solve_params;
+
+/* Parareal solve (Sec. 3, eq. HMM parareal iteration; Alg. 4):
+ *   U_n^0 = G(U_{n-1}^0);  U_n^k = Fine(U_{n-1}^{k-1}) + (G(U_{n-1}^k) - G(U_{n-1}^{k-1}))
+ * with the correction evaluated in FP64 and G(U^{k-1}) reused from the previous
+ * sweep.  u0 physical [3][N]; U_out physical [slices+1][3][N] holds U_0..U_Ns
+ * after the last iteration; resid (device, float64 [K]) receives
+ * r^k = max_n ||U_n^k - U_n^{k-1}||_2 / ||U_n^k||_2 over the 3N grid values
+ * (entries of iterations skipped by `tol` are set to -1).                     */
+int aparareal_solve(ap_ctx* ctx, const double* u0, const ap_solve_params* params,
+                    double* U_out, double* resid, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APARAREAL_H */

@@ -1,0 +1,160 @@
+"""ctypes binding of libaparareal.so (argument marshalling only).
+
+Every array is a torch CUDA tensor (float64, contiguous) whose device pointer is
+handed to the library together with torch's current stream; all computation
+happens in the library's HIP kernels.  The library must be built
+(``python -m paper_1303_6615_amd.build``); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+from .build import LIB_PATH, ROOT
+
+HEADER = os.path.join(ROOT, "include", "aparareal.h")
+
+AP_OK, AP_PENDING = 0, 1
+AP_PREC_FP32, AP_PREC_FP64 = 0, 1
+ERRORS = {-1: "AP_EINVAL", -2: "AP_ENOMEM", -3: "AP_EDEVICE", -4: "AP_ENOTFOUND",
+          -5: "AP_ENUMERIC", -6: "AP_EBUSY"}
+
+
+class APError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("slices", ctypes.c_int), ("K", ctypes.c_int),
+                ("dt_fine", ctypes.c_double), ("M_avg", ctypes.c_int), ("T0", ctypes.c_double),
+                ("tol", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+_lib = None
+_vp, _dp, _i, _d = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+
+_SIGNATURES = {
+    "aparareal_last_error": (ctypes.c_char_p, []),
+    "aparareal_create": (_vp, [_i, _d, _d, _d]),
+    "aparareal_destroy": (_i, [_vp]),
+    "aparareal_nonlinear": (_i, [_vp, _dp, _dp, _i, _i, _vp]),
+    "aparareal_fine_batch": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
+    "aparareal_average": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
+    "aparareal_coarse": (_i, [_vp, _dp, _dp, _i, _d, _i, _d, _i, _vp]),
+    "aparareal_solve": (_i, [_vp, _dp, ctypes.POINTER(SolveParams), _dp, _dp, _vp]),
+}
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/aparareal.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(aparareal_\w+)\s*\(", text)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1303_6615_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise APError(rc, lib().aparareal_last_error().decode())
+    return rc
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _states(x, n: int, name: str):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if x.dim() < 2 or x.shape[-2:] != (3, n):
+        raise ValueError(f"{name} must have shape [..., 3, {n}], got {tuple(x.shape)}")
+    return x
+
+
+class Context:
+    """One library context: grid size N, eps, F, nu on the current device."""
+
+    def __init__(self, N: int, eps: float, F: float = 1.0, nu: float = 0.0):
+        self.N, self.eps, self.F, self.nu = int(N), float(eps), float(F), float(nu)
+        h = lib().aparareal_create(self.N, self.eps, self.F, self.nu)
+        if not h:
+            raise APError(-1, lib().aparareal_last_error().decode())
+        self._h = ctypes.c_void_p(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().aparareal_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- batched propagators -------------------------------------------------
+    def _batched(self, fn, U, *args, out=None):
+        import torch
+        U = _states(U, self.N, "U")
+        out = torch.empty_like(U) if out is None else _states(out, self.N, "out")
+        batch = U.numel() // (3 * self.N)
+        _check(fn(self._h, ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                  batch, *args, _stream(torch)))
+        return out
+
+    def nonlinear(self, U, precision: int = AP_PREC_FP64, out=None):
+        return self._batched(lib().aparareal_nonlinear, U, precision, out=out)
+
+    def fine_batch(self, U, dT: float, steps: int, precision: int = AP_PREC_FP32, out=None):
+        return self._batched(lib().aparareal_fine_batch, U, float(dT), int(steps), precision, out=out)
+
+    def average(self, U, T0: float, M: int, precision: int = AP_PREC_FP32, out=None):
+        return self._batched(lib().aparareal_average, U, float(T0), int(M), precision, out=out)
+
+    def coarse(self, U, dT: float, M: int, T0: float = 0.0, precision: int = AP_PREC_FP32, out=None):
+        return self._batched(lib().aparareal_coarse, U, float(dT), int(M), float(T0), precision, out=out)
+
+    # -- the parareal solve ----------------------------------------------------
+    def solve(self, u0, T: float, slices: int, K: int, dt_fine: float, M: int, T0: float = 0.0,
+              tol: float = 0.0, precision: int = AP_PREC_FP32, out=None, resid=None):
+        """Returns (U [slices+1, 3, N], resid [K]) as CUDA float64 tensors."""
+        import torch
+        u0 = _states(u0, self.N, "u0")
+        if u0.numel() != 3 * self.N:
+            raise ValueError("u0 must hold one state [3, N]")
+        p = SolveParams(float(T), int(slices), int(K), float(dt_fine), int(M), float(T0),
+                        float(tol), int(precision))
+        if out is None:
+            out = torch.empty((slices + 1, 3, self.N), dtype=torch.float64, device=u0.device)
+        if resid is None:
+            resid = torch.empty((max(K, 1),), dtype=torch.float64, device=u0.device)
+        _check(lib().aparareal_solve(self._h, ctypes.c_void_p(u0.data_ptr()), ctypes.byref(p),
+                                     ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(resid.data_ptr()), _stream(torch)))
+        return out, resid[:K]
