@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark: asymptotic parareal solves of the 1D rotating shallow water system
+on one MI355X.
+
+One step = one complete parareal solve (coarse initial sweep, then K iterations
+of [fine batch over every slice, serial coarse sweep with the FP64
+correction, residual], run as one pipelined persistent launch) of the default
+workload
+    N = 256, eps = 0.01, nu = 1e-5, F = 1, T = 2, 64 slices, K = 8,
+    fine ETDRK4 dt = eps/20 (63 steps per slice), M = 32 averaging samples,
+    T0 = dT/eps, FP32 propagators with FP64 correction,
+    seeded k^-2 initial spectrum up to k = 32, max|h| = 0.1.
+Inputs are resident on the device before timing starts.
+
+Metric: fine grid-point-steps per second of whole-solve wall time
+(K x slices x fine steps x N per solve).  The JSON line also carries the
+roofline of the dominant kernel (algorithmic flops per launch over its
+event-timed average duration) and the FP64 CPU oracle timed on one full
+solve of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg):
+    """The FP64 oracle on one full solve of the workload, BLAS limited to one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        U, res, _ = O.parareal_solve(cfg.initial_state(), cfg.nx, cfg.eps, cfg.F, cfg.nu, cfg.T,
+                                     cfg.slices, cfg.K, cfg.fine_steps, cfg.Mbar, cfg.window)
+        dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(U))
+    return {"value": cfg.fine_gp_steps() / dt, "unit": "fine grid-point-steps/s", "cores": 1,
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"one full parareal solve of {cfg.name} (numpy FP64, single thread)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the parallel-in-time "
+              "dimension is the batch dimension of the single-GPU kernels.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1303_6615_amd import metrics
+    from paper_1303_6615_amd.binding import Context
+    from paper_1303_6615_amd.inputs import C1, C2, C3
+
+    cfg = {"c1": C1, "c2": C2, "c3": C3}[args.workload]
+    torch.cuda.set_device(0)
+    ctx = Context(cfg.nx, cfg.eps, cfg.F, cfg.nu)
+    u0 = torch.tensor(cfg.initial_state(), device="cuda")
+    out = torch.empty((cfg.slices + 1, 3, cfg.nx), dtype=torch.float64, device="cuda")
+    resid = torch.empty((cfg.K,), dtype=torch.float64, device="cuda")
+
+    def step():
+        ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=cfg.precision,
+                  out=out, resid=resid)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    r = resid.cpu().numpy()
+    if not np.all(np.isfinite(r)) or not np.all(np.isfinite(out.cpu().numpy())):
+        raise SystemExit("non-finite result")
+
+    total_gp = cfg.fine_gp_steps() * args.steps
+    value = total_gp / elapsed
+    # per-kernel algorithmic flops per launch
+    fine_f = metrics.fine_flops(cfg.nx, cfg.slices, cfg.fine_steps)
+    sweep_f = metrics.sweep_flops(cfg.nx, cfg.Mbar, cfg.slices)
+    flops = {
+        "fine": fine_f,
+        "sweep": sweep_f,
+        # the persistent launch runs all K fine batches and K+1 coarse sweeps
+        "pipeline": cfg.K * fine_f + (cfg.K + 1) * sweep_f,
+    }
+    kern = {}
+    tot_ms = sum(ms for (_, ms) in prof.values())
+    for name, (n, ms) in prof.items():
+        if n == 0:
+            continue
+        d = {"launches": n, "avg_ms": round(ms / n, 5), "share": round(ms / tot_ms, 4)}
+        if name in flops:
+            d["tflops"] = round(flops[name] / (ms / n * 1e-3) / 1e12, 4)
+        kern[name] = d
+    dominant = max((k for k in kern if k in flops), key=lambda k: kern[k]["share"])
+    avg_s = prof[dominant][1] / prof[dominant][0] * 1e-3
+    achieved = flops[dominant] / avg_s / 1e12
+    kernel_names = {"fine": f"k_fine<float,{cfg.nx}>", "sweep": f"k_sweep<float,{cfg.nx}>",
+                    "pipeline": f"k_pipeline<float,{cfg.nx}>"}
+    if cfg.precision == 1:
+        kernel_names = {k: v.replace("float", "double") for k, v in kernel_names.items()}
+    peak = metrics.PEAK_FP32_TFLOPS if cfg.precision == 0 else metrics.PEAK_FP64_TFLOPS
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 6), "traffic": None,
+                "kernel": kernel_names[dominant], "flops_per_launch": flops[dominant],
+                "avg_launch_ms": round(avg_s * 1e3, 5)}
+    line = {
+        "metric": "fine grid-point-steps/s at 1 GPU",
+        "value": round(value, 1),
+        "unit": "fine grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32" if cfg.precision == 0 else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "N": cfg.nx, "eps": cfg.eps, "nu": cfg.nu, "F": cfg.F,
+                   "T": cfg.T, "slices": cfg.slices, "K": cfg.K, "fine_steps": cfg.fine_steps,
+                   "M_avg": cfg.Mbar, "T0": cfg.window,
+                   "precision": "fp32 propagators, fp64 correction" if cfg.precision == 0 else "fp64",
+                   "parallelism": "time slices as batch, 1 GPU"},
+        "roofline": roofline,
+        "kernels": kern,
+        "final_residual": float(r[-1]) if r.size else None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -103,12 +103,50 @@ typedef struct {
 /* Parareal solve (Sec. 3, eq. HMM parareal iteration; Alg. 4):
  *   U_n^0 = G(U_{n-1}^0);  U_n^k = Fine(U_{n-1}^{k-1}) + (G(U_{n-1}^k) - G(U_{n-1}^{k-1}))
  * with the correction evaluated in FP64 and G(U^{k-1}) reused from the previous
- * sweep.  u0 physical [3][N]; U_out physical [slices+1][3][N] holds U_0..U_Ns
+ * sweep.  With tol <= 0 the K iterations run as one pipelined persistent
+ * launch (iteration k+1 starts on a slice as soon as its inputs exist);
+ * results are identical to the iteration-by-iteration order.  u0 physical [3][N]; U_out physical [slices+1][3][N] holds U_0..U_Ns
  * after the last iteration; resid (device, float64 [K]) receives
  * r^k = max_n ||U_n^k - U_n^{k-1}||_2 / ||U_n^k||_2 over the 3N grid values
  * (entries of iterations skipped by `tol` are set to -1).                     */
 int aparareal_solve(ap_ctx* ctx, const double* u0, const ap_solve_params* params,
                     double* U_out, double* resid, void* stream);
+
+/* Kernel timing (diagnostics, no effect on results).  While enabled, the
+ * library brackets each of its own kernel launches with a pair of HIP events
+ * recorded on the launch stream and accumulates the elapsed time per kernel
+ * class.  aparareal_profile(ctx, 1) resets the counters and enables;
+ * aparareal_profile(ctx, 0) disables.  aparareal_profile_read waits for the
+ * recorded events (host synchronisation) and returns the number of launches
+ * and their total milliseconds for one class.                                */
+enum {
+  AP_K_FINE = 0,        /* fine ETDRK4 batch                                     */
+  AP_K_SWEEP = 1,       /* serial coarse sweep with parareal correction          */
+  AP_K_TO_MODAL = 2,    /* physical -> modal boundary transform                  */
+  AP_K_TO_PHYSICAL = 3, /* modal -> physical boundary transform                  */
+  AP_K_RESID = 4,       /* residual reduction                                    */
+  AP_K_NONLINEAR = 5,
+  AP_K_AVERAGE = 6,
+  AP_K_COARSE = 7,
+  AP_K_PIPELINE = 8,    /* persistent pipelined parareal iteration (all jobs)    */
+  AP_K_CLASSES = 9
+};
+int aparareal_profile(ap_ctx* ctx, int enable);
+int aparareal_profile_read(ap_ctx* ctx, int kernel_class, int* launches, double* total_ms);
+
+/* Order in which the pipelined solve hands out its jobs (host only, no device
+ * needed; for inspection and tests).  Writes (type, k, n) triples to the host
+ * array `out` [3 * (2K+1) * slices]: type 0 = coarse step C(k,n) of iteration
+ * level k = 0..K, type 1 = fine slice F(k,n) = Fine(U_{n-1}^k), k = 0..K-1;
+ * n = 1..slices.  `steps` fine steps per slice and M_avg samples set the
+ * estimated ready times that order the list.  Returns the job count or AP_EINVAL. */
+int aparareal_pipeline_schedule(int slices, int K, int steps, int M_avg, int* out);
+
+/* Stall record of the context's last pipelined solve (waits for it): host
+ * info[3] = (stalled, job index, flag index).  A stall means a job saw no
+ * progress on a dependency for 0.5 s; the launch then ends early and the
+ * solve's residuals are NaN.  It does not occur in correct operation.        */
+int aparareal_pipeline_status(ap_ctx* ctx, int* info);
 
 #ifdef __cplusplus
 }

@@ -45,7 +45,14 @@ _SIGNATURES = {
     "aparareal_average": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
     "aparareal_coarse": (_i, [_vp, _dp, _dp, _i, _d, _i, _d, _i, _vp]),
     "aparareal_solve": (_i, [_vp, _dp, ctypes.POINTER(SolveParams), _dp, _dp, _vp]),
+    "aparareal_profile": (_i, [_vp, _i]),
+    "aparareal_pipeline_schedule": (_i, [_i, _i, _i, _i, ctypes.POINTER(_i)]),
+    "aparareal_pipeline_status": (_i, [_vp, ctypes.POINTER(_i)]),
+    "aparareal_profile_read": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
 }
+
+KERNEL_CLASSES = {0: "fine", 1: "sweep", 2: "to_modal", 3: "to_physical", 4: "resid",
+                  5: "nonlinear", 6: "average", 7: "coarse", 8: "pipeline"}
 
 
 def header_symbols() -> list[str]:
@@ -68,6 +75,14 @@ def lib() -> ctypes.CDLL:
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def pipeline_schedule(slices: int, K: int, steps: int, M: int) -> list[tuple[int, int, int]]:
+    """Job order of the pipelined solve as (type, k, n) triples (host only)."""
+    n = (2 * K + 1) * slices
+    buf = (ctypes.c_int * (3 * n))()
+    cnt = _check(lib().aparareal_pipeline_schedule(slices, K, steps, M, buf))
+    return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(cnt)]
 
 
 def _check(rc: int) -> int:
@@ -139,6 +154,25 @@ class Context:
 
     def coarse(self, U, dT: float, M: int, T0: float = 0.0, precision: int = AP_PREC_FP32, out=None):
         return self._batched(lib().aparareal_coarse, U, float(dT), int(M), float(T0), precision, out=out)
+
+    # -- kernel timing ----------------------------------------------------------
+    def profile(self, enable: bool = True):
+        _check(lib().aparareal_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{class name: (launches, total ms)} for every kernel class (syncs)."""
+        out = {}
+        for cls, name in KERNEL_CLASSES.items():
+            n, ms = ctypes.c_int(0), ctypes.c_double(0.0)
+            _check(lib().aparareal_profile_read(self._h, cls, ctypes.byref(n), ctypes.byref(ms)))
+            out[name] = (n.value, ms.value)
+        return out
+
+    def pipeline_status(self) -> tuple[int, int, int]:
+        """(stalled, job, flag) of the last pipelined solve (synchronises)."""
+        buf = (ctypes.c_int * 3)()
+        _check(lib().aparareal_pipeline_status(self._h, buf))
+        return buf[0], buf[1], buf[2]
 
     # -- the parareal solve ----------------------------------------------------
     def solve(self, u0, T: float, slices: int, K: int, dt_fine: float, M: int, T0: float = 0.0,

@@ -3,8 +3,11 @@
     python -m paper_1303_6615_amd.build [-v]
 
 Every HIP source is compiled with packed-FP32 instruction selection disabled
-(``-Xclang -target-feature -Xclang -packed-fp32-ops``); translation units are
-compiled in parallel and linked into one shared library next to this file.
+(``-Xclang -target-feature -Xclang -packed-fp32-ops``) and with FMA fusion
+limited to single source expressions (``-ffp-contract=on``), so that a job's
+arithmetic rounds the same way in every kernel that runs it; translation
+units are compiled in parallel and linked into one shared library next to
+this file.
 """
 from __future__ import annotations
 
@@ -26,6 +29,9 @@ ARCH = "gfx950"
 COMMON = [
     "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FMA fusion only within one source expression (plus explicit fma calls):
+    # the same job then rounds identically in every kernel that inlines it
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -1,0 +1,318 @@
+// Workgroup-level engine: LDS layout, and the per-workgroup jobs of the
+// parareal path (one fine slice; one coarse step with the FP64 correction).
+//
+// LDS layout for S state slots (T = float or double, P = N/2):
+//   tw   [N]            exp(-2 pi i t / N), staged once per kernel when it
+//                       fits next to one state slot (else read from global)
+//   spec [S][3][P+1]    field half spectra (tail k > Kd kept zero)
+//   a, b [S][3][P]      ping-pong FFT buffers (contiguous); they double as the FP64
+//                       reduction scratch [2][NT] between nonlinear evaluations
+#pragma once
+#include "launch.hpp"
+#include "rsw_device.hpp"
+
+namespace ap {
+
+constexpr size_t kLdsBudget = 156 * 1024;   // of gfx950's 160 KiB per workgroup
+
+template <typename T, int NX>
+constexpr bool twiddles_in_lds() {
+  return NX * sizeof(cx<T>) + Lds<T, NX>::per_state() <= kLdsBudget;
+}
+
+template <typename T, int NX, int NT>
+constexpr int max_slots() {
+  const size_t fixed = twiddles_in_lds<T, NX>() ? NX * sizeof(cx<T>) : 0;
+  const size_t per = Lds<T, NX>::per_state();
+  const size_t s = (kLdsBudget - fixed) / per;
+  return s >= 32 ? 32 : (s < 1 ? 1 : int(s));
+}
+
+template <typename T, int NX, int NT, int S>
+struct Engine {
+  using G = Geo<NX>;
+  static constexpr int P = G::P;
+  static constexpr int KP = G::KP;
+  static constexpr int MPT = (KP + NT - 1) / NT;
+  static constexpr bool TW_LDS = twiddles_in_lds<T, NX>();
+  static_assert(2 * Lds<T, NX>::work_elems(S) * sizeof(cx<T>) >= 2 * NT * sizeof(double), "reduction scratch");
+  static constexpr size_t lds_bytes() { return (TW_LDS ? NX * sizeof(cx<T>) : 0) + Lds<T, NX>::bytes(S); }
+  static_assert(lds_bytes() <= 160 * 1024, "LDS budget of gfx950 exceeded");
+  const cx<T>* tw;
+  cx<T>* spec;
+  cx<T>* a;
+  cx<T>* b;
+  double* red;
+
+  __device__ __forceinline__ Engine(unsigned char* smem, const cx<T>* __restrict__ tw_global) {
+    cx<T>* base = reinterpret_cast<cx<T>*>(smem);
+    if constexpr (TW_LDS) {
+      for (int i = threadIdx.x; i < NX; i += NT) base[i] = tw_global[i];
+      tw = base;
+      base += NX;
+    } else {
+      tw = tw_global;
+    }
+    spec = base;
+    a = spec + Lds<T, NX>::spec_elems(S);
+    b = a + Lds<T, NX>::work_elems(S);
+    red = reinterpret_cast<double*>(a);
+    zero_spec_tail<T, NX, NT>(spec, S);
+    __syncthreads();
+  }
+  static __device__ __forceinline__ int mode(int j) { return threadIdx.x + j * NT; }
+  static __device__ __forceinline__ bool valid(int j) { return mode(j) < KP; }
+  __device__ __forceinline__ cx<T>* nonlinear(int ns) { return nonlinear_core<T, NX, NT>(spec, a, b, ns, tw); }
+
+  // FP64 block sum of (x, y) over the workgroup; result valid in every thread.
+  // The scratch lives in `a`, so wait for readers of the last FFT result first.
+  __device__ __forceinline__ double2 block_sum2(double x, double y) {
+    __syncthreads();
+    red[threadIdx.x] = x;
+    red[NT + threadIdx.x] = y;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) {
+        red[threadIdx.x] += red[threadIdx.x + off];
+        red[NT + threadIdx.x] += red[NT + threadIdx.x + off];
+      }
+      __syncthreads();
+    }
+    const double2 r = make_double2(red[0], red[NT]);
+    __syncthreads();
+    return r;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> rot_in(cx<T> c, cx<T> e, int alpha_idx) {
+  // exp(-i alpha omega s) with e = exp(-i omega s): alpha=+1 -> e, -1 -> conj(e), 0 -> 1
+  return alpha_idx == 2 ? c * e : (alpha_idx == 0 ? c * conj(e) : c);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> rot_out(cx<T> c, cx<T> e, int alpha_idx) {
+  return alpha_idx == 2 ? c * conj(e) : (alpha_idx == 0 ? c * e : c);
+}
+
+// ------------------------------------------------------------ fine ETDRK4 ---
+// One slice: `steps` ETDRK4 steps from src (modal FP64) to dst.
+// Coefficient tables [8][3][KP]: E_hi, E_lo, E2_hi, E2_lo, Q, f1, 2*f2, f3.
+// The state and the step accumulator u+ = E u + f1 N(u) + 2f2 (N(a) + N(b))
+// + f3 N(c) stay in FP64 in both precisions (E from the FP64 table): slowly
+// varying modes change by less than half an FP32 ulp per step, so an FP32
+// state would drop those increments coherently step after step.  With
+// T = float the stage states a, b, c, the nonlinear evaluations and the
+// products f*N run in FP32.
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, const cx<double>* __restrict__ src,
+                                         cx<double>* __restrict__ dst, int steps,
+                                         const cx<double>* __restrict__ coef64, const cx<T>* __restrict__ coef,
+                                         const Basis<T>* __restrict__ basis) {
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int KP = E_::KP;
+  constexpr int MPT = E_::MPT;
+  cx<double> c[MPT][3], cE[MPT][3];
+  cx<T> cE2[MPT][3], cQ[MPT][3], cf1[MPT][3], cf2[MPT][3], cf3[MPT][3];
+  Basis<T> bs[MPT];
+#pragma unroll
+  for (int j = 0; j < MPT; ++j) {
+    const int k = E_::valid(j) ? E_::mode(j) : KP - 1;
+    bs[j] = basis[k];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+      const int o = al * KP + k;
+      c[j][al] = src[o];
+      cE[j][al] = coef64[0 * 3 * KP + o];
+      cE2[j][al] = coef[2 * 3 * KP + o];
+      cQ[j][al] = coef[4 * 3 * KP + o];
+      cf1[j][al] = coef[5 * 3 * KP + o];
+      cf2[j][al] = coef[6 * 3 * KP + o];
+      cf3[j][al] = coef[7 * 3 * KP + o];
+    }
+  }
+  auto neval = [&](cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3]) {
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+      if (E_::valid(j)) put_fields<T, NX>(en.spec, 0, E_::mode(j), x[j], bs[j]);
+    __syncthreads();
+    cx<T>* R = en.nonlinear(1);
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+      if (E_::valid(j)) get_N<T, NX>(R, 0, E_::mode(j), bs[j], en.tw, n[j]);
+  };
+  cx<T> Nx[MPT][3], st[MPT][3], E2c[MPT][3], Nu[MPT][3];
+  cx<double> acc[MPT][3];
+  for (int step = 0; step < steps; ++step) {
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+#pragma unroll
+      for (int al = 0; al < 3; ++al) st[j][al] = cvt<T>(c[j][al]);
+    neval(st, Nu);
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        E2c[j][al] = cE2[j][al] * st[j][al];
+        st[j][al] = cfma(cQ[j][al], Nu[j][al], E2c[j][al]);                                   // a
+        acc[j][al] = cE[j][al] * c[j][al] + cvt<double>(cf1[j][al] * Nu[j][al]);
+      }
+    neval(st, Nx);                                                                            // N(a)
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        acc[j][al] = acc[j][al] + cvt<double>(cf2[j][al] * Nx[j][al]);
+        const cx<T> a_ = st[j][al];
+        st[j][al] = cfma(cQ[j][al], Nx[j][al], E2c[j][al]);                                   // b
+        E2c[j][al] = cE2[j][al] * a_;                                                         // E2 a
+      }
+    neval(st, Nx);                                                                            // N(b)
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        acc[j][al] = acc[j][al] + cvt<double>(cf2[j][al] * Nx[j][al]);
+        st[j][al] = cfma(cQ[j][al], T(2) * Nx[j][al] - Nu[j][al], E2c[j][al]);                // c
+      }
+    neval(st, Nx);                                                                            // N(c)
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+#pragma unroll
+      for (int al = 0; al < 3; ++al) c[j][al] = acc[j][al] + cvt<double>(cf3[j][al] * Nx[j][al]);
+  }
+#pragma unroll
+  for (int j = 0; j < MPT; ++j)
+    if (E_::valid(j))
+      for (int al = 0; al < 3; ++al) dst[al * KP + E_::mode(j)] = c[j][al];
+}
+
+// ----------------------------------------------------------- time average ---
+// Nbar of the owned-mode state y -> acc, with min(S, M-1) samples in flight.
+// Samples are accumulated in increasing m in every thread (fixed order).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void nbar_owned(Engine<T, NX, NT, S>& en,
+                                           const cx<T> (&y)[Engine<T, NX, NT, S>::MPT][3],
+                                           cx<T> (&acc)[Engine<T, NX, NT, S>::MPT][3],
+                                           const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT], const AvgTab<T>& av) {
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int KP = E_::KP;
+#pragma unroll
+  for (int j = 0; j < E_::MPT; ++j)
+    for (int al = 0; al < 3; ++al) acc[j][al] = czero<T>();
+  for (int m0 = 1; m0 < av.M; m0 += S) {
+    const int ns = min(S, av.M - m0);
+    for (int s = 0; s < ns; ++s) {
+      const cx<T>* rot = av.rot + size_t(m0 + s) * KP;
+#pragma unroll
+      for (int j = 0; j < E_::MPT; ++j) {
+        if (!E_::valid(j)) continue;
+        const int k = E_::mode(j);
+        const cx<T> e = rot[k];
+        cx<T> x[3];
+        for (int al = 0; al < 3; ++al) x[al] = rot_in(y[j][al], e, al);
+        put_fields<T, NX>(en.spec, s, k, x, bs[j]);
+      }
+    }
+    __syncthreads();
+    cx<T>* R = en.nonlinear(ns);
+    for (int s = 0; s < ns; ++s) {
+      const cx<T>* rot = av.rot + size_t(m0 + s) * KP;
+      const T wm = av.w[m0 + s];
+#pragma unroll
+      for (int j = 0; j < E_::MPT; ++j) {
+        if (!E_::valid(j)) continue;
+        const int k = E_::mode(j);
+        const cx<T> e = rot[k];
+        cx<T> n[3];
+        get_N<T, NX>(R, s, k, bs[j], en.tw, n);
+        for (int al = 0; al < 3; ++al) acc[j][al] = acc[j][al] + wm * rot_out(n[al], e, al);
+      }
+    }
+  }
+}
+
+// One asymptotic coarse step on owned-mode registers u -> g (Alg. 2).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void coarse_owned(Engine<T, NX, NT, S>& en,
+                                             const cx<T> (&u)[Engine<T, NX, NT, S>::MPT][3],
+                                             cx<T> (&g)[Engine<T, NX, NT, S>::MPT][3],
+                                             const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT],
+                                             const CoarseTab<T>& ct) {
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int MPT = E_::MPT;
+  cx<T> w[MPT][3], y[MPT][3], kk[MPT][3];
+  T hd[MPT];
+  cx<T> rT[MPT];
+#pragma unroll
+  for (int j = 0; j < MPT; ++j) {
+    const int k = E_::valid(j) ? E_::mode(j) : 0;
+    hd[j] = ct.hd[k];
+    rT[j] = ct.rotT[k];
+    for (int al = 0; al < 3; ++al) w[j][al] = hd[j] * u[j][al];
+  }
+  nbar_owned<T, NX, NT, S>(en, w, kk, bs, ct.avg);
+  const T half = T(0.5) * ct.dT;
+#pragma unroll
+  for (int j = 0; j < MPT; ++j)
+    for (int al = 0; al < 3; ++al) y[j][al] = w[j][al] + half * kk[j][al];
+  nbar_owned<T, NX, NT, S>(en, y, kk, bs, ct.avg);
+#pragma unroll
+  for (int j = 0; j < MPT; ++j)
+    for (int al = 0; al < 3; ++al) {
+      const cx<T> v = hd[j] * (w[j][al] + ct.dT * kk[j][al]);
+      g[j][al] = al == 2 ? v * rT[j] : (al == 0 ? v * conj(rT[j]) : v);
+    }
+}
+
+// One coarse job of the parareal iteration on modal FP64 states:
+//   g = G(uprev);  gnew <- g
+//   gold == nullptr (k = 0):  unew <- g
+//   otherwise:                unew <- fold + (g - gold)     (FP64)
+//   uold != nullptr: *part = (sum |unew - uold|^2, sum |unew|^2) with Parseval
+//   weights (1 for k = 0, 2 otherwise).
+// Every location is read before it is written by the same thread, so unew may
+// alias uold and gnew may alias gold (the in-place serial sweep).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void coarse_job(Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct,
+                                           const Basis<T>* __restrict__ basis, const cx<double>* uprev,
+                                           cx<double>* unew, cx<double>* gnew, const cx<double>* gold,
+                                           const cx<double>* fold, const cx<double>* uold, double2* part) {
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int KP = E_::KP;
+  constexpr int MPT = E_::MPT;
+  cx<T> u[MPT][3], g[MPT][3];
+  Basis<T> bs[MPT];
+#pragma unroll
+  for (int j = 0; j < MPT; ++j) {
+    const int k = E_::valid(j) ? E_::mode(j) : 0;
+    bs[j] = basis[k];
+    for (int al = 0; al < 3; ++al) u[j][al] = E_::valid(j) ? cvt<T>(uprev[al * KP + k]) : czero<T>();
+  }
+  coarse_owned<T, NX, NT, S>(en, u, g, bs, ct);
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int j = 0; j < MPT; ++j) {
+    if (!E_::valid(j)) continue;
+    const int k = E_::mode(j);
+    const double wgt = k == 0 ? 1.0 : 2.0;
+    for (int al = 0; al < 3; ++al) {
+      const int o = al * KP + k;
+      const cx<double> gn = cvt<double>(g[j][al]);
+      cx<double> un = gn;
+      if (gold) un = fold[o] + (gn - gold[o]);
+      if (uold) {
+        const cx<double> d = un - uold[o];
+        num += wgt * (d.x * d.x + d.y * d.y);
+        den += wgt * (un.x * un.x + un.y * un.y);
+      }
+      gnew[o] = gn;
+      unew[o] = un;
+    }
+  }
+  if (uold) {
+    const double2 r = en.block_sum2(num, den);
+    if (threadIdx.x == 0) *part = r;
+  }
+}
+
+}  // namespace ap

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <string>
@@ -144,8 +145,28 @@ struct ap_ctx {
   std::map<uint64_t, std::unique_ptr<FineTables>> fine_cache;
   std::map<std::tuple<uint64_t, uint64_t, int>, std::unique_ptr<AvgTables>> avg_cache;
   DevBuf ws_in, ws_out, ws_U, ws_F, ws_G, ws_part;
+  // pipelined solve: per-level states, flags, job list and descriptor
+  DevBuf pp_U, pp_F, pp_G, pp_part, pp_flags, pp_jobs, pp_prob;
+  std::tuple<int, int, int, int> pp_jobs_key{-1, -1, -1, -1};
+  int pp_njobs = 0;
+  std::vector<ap::PipeJob> pp_jobs_host;
+  std::vector<unsigned char> pp_prob_host;
+  int* pp_diag = nullptr;   // stall record of the last pipelined launch
   hipStream_t last_stream = nullptr;
   bool has_last = false;
+  // kernel timing (aparareal_profile)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> ev_pending;
+  int prof_count[AP_K_CLASSES] = {};
+  double prof_ms[AP_K_CLASSES] = {};
+  ~ap_ctx() {
+    for (auto& t : ev_pending) {
+      ev_pool.push_back(std::get<1>(t));
+      ev_pool.push_back(std::get<2>(t));
+    }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -166,6 +187,30 @@ hipError_t order_stream(ap_ctx* c, hipStream_t s) {
   c->last_stream = s;
   c->has_last = true;
   return hipSuccess;
+}
+
+hipEvent_t take_event(ap_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch `fn` (returning hipError_t); with profiling on, bracket it with events.
+template <typename Fn>
+hipError_t timed(ap_ctx* c, int cls, hipStream_t s, Fn&& fn) {
+  if (!c->prof_on) return fn();
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return fn();
+  (void)hipEventRecord(a, s);
+  hipError_t e = fn();
+  (void)hipEventRecord(b, s);
+  c->ev_pending.emplace_back(cls, a, b);
+  return e;
 }
 
 // grow a workspace buffer, draining outstanding work first
@@ -312,14 +357,165 @@ int batch_prologue(ap_ctx* c, const double* in, void* out, int batch, int precis
   const size_t need = size_t(batch) * state_bytes(c);
   if ((e = ensure(c, c->ws_in, need)) != hipSuccess) return hip_fail(e, "workspace");
   if ((e = ensure(c, c->ws_out, need)) != hipSuccess) return hip_fail(e, "workspace");
-  e = ap::launch_to_modal(c->N, in, c->ws_in.as<cx<double>>(), batch, c->tabs, s);
+  e = timed(c, AP_K_TO_MODAL, s, [&] { return ap::launch_to_modal(c->N, in, c->ws_in.as<cx<double>>(), batch, c->tabs, s); });
   if (e != hipSuccess) return hip_fail(e, "to_modal launch");
   return AP_OK;
 }
 
 int batch_epilogue(ap_ctx* c, double* out, int batch, hipStream_t s) {
-  hipError_t e = ap::launch_to_physical(c->N, c->ws_out.as<cx<double>>(), out, batch, c->tabs, s);
+  hipError_t e = timed(c, AP_K_TO_PHYSICAL, s,
+                       [&] { return ap::launch_to_physical(c->N, c->ws_out.as<cx<double>>(), out, batch, c->tabs, s); });
   if (e != hipSuccess) return hip_fail(e, "to_physical launch");
+  return AP_OK;
+}
+
+// Jobs of the pipelined solve in a topological order: by estimated ready time
+// t(C(k,n)) = n tc + k tf, t(F(k,n)) = (n-1) tc + k tf (tc, tf: nonlinear
+// evaluations per coarse step / fine slice), coarse before fine on ties.  Every
+// dependency of a job has a smaller t or is a coarse job of equal t, so the
+// ticket order lets the earliest unfinished job always run.
+std::vector<ap::PipeJob> pipeline_jobs(int prob, int Ns, int K, int steps, int M) {
+  struct Item {
+    long long t;
+    ap::PipeJob j;
+  };
+  const long long tc = 2LL * (M - 1) > 0 ? 2LL * (M - 1) : 1, tf = 4LL * steps;
+  std::vector<Item> it;
+  it.reserve(size_t(2 * K + 1) * Ns);
+  for (int k = 0; k <= K; ++k)
+    for (int n = 1; n <= Ns; ++n) it.push_back({n * tc + k * tf, {prob, 0, k, n}});
+  for (int k = 0; k < K; ++k)
+    for (int n = 1; n <= Ns; ++n) it.push_back({(n - 1) * tc + k * tf, {prob, 1, k, n}});
+  std::stable_sort(it.begin(), it.end(), [](const Item& a, const Item& b) {
+    if (a.t != b.t) return a.t < b.t;
+    if (a.j.type != b.j.type) return a.j.type < b.j.type;
+    if (a.j.k != b.j.k) return a.j.k < b.j.k;
+    return a.j.n < b.j.n;
+  });
+  std::vector<ap::PipeJob> out;
+  out.reserve(it.size());
+  for (auto& x : it) out.push_back(x.j);
+  return out;
+}
+
+int solve_sweeps(ap_ctx* c, const double* u0, const ap_solve_params* p, double* U_out, double* resid,
+                 hipStream_t s, int steps, FineTables* ft, AvgTables* at) {
+  const int Ns = p->slices;
+  const size_t sb = state_bytes(c);
+  hipError_t e;
+  if ((e = ensure(c, c->ws_U, sb * (Ns + 1))) != hipSuccess ||
+      (e = ensure(c, c->ws_F, sb * (Ns + 1))) != hipSuccess ||
+      (e = ensure(c, c->ws_G, sb * (Ns + 1))) != hipSuccess ||
+      (e = ensure(c, c->ws_part, sizeof(double2) * size_t(Ns) * std::max(1, p->K))) != hipSuccess)
+    return hip_fail(e, "solve workspace");
+  const bool f64 = p->precision == AP_PREC_FP64;
+  const ap::CoarseTab<double>* c64 = f64 ? &at->c64 : nullptr;
+  const ap::CoarseTab<float>* c32 = f64 ? nullptr : &at->c32;
+  cx<double>* U = c->ws_U.as<cx<double>>();
+  cx<double>* Fn = c->ws_F.as<cx<double>>();
+  cx<double>* G = c->ws_G.as<cx<double>>();
+  double2* part = c->ws_part.as<double2>();
+  const size_t st = size_t(3) * c->KP;
+  e = timed(c, AP_K_TO_MODAL, s, [&] { return ap::launch_to_modal(c->N, u0, U, 1, c->tabs, s); });
+  if (e != hipSuccess) return hip_fail(e, "to_modal");
+  e = timed(c, AP_K_SWEEP, s, [&] { return ap::launch_sweep(c->N, U, Fn, G, part, Ns, 1, c64, c32, c->tabs, s); });
+  if (e != hipSuccess) return hip_fail(e, "initial sweep");
+  for (int k = 0; k < p->K; ++k) {
+    e = timed(c, AP_K_FINE, s, [&] {
+      return ap::launch_fine(c->N, f64, U, Fn + st, Ns, steps, ft->coef64.as<cx<double>>(),
+                             ft->coef32.as<cx<float>>(), c->tabs, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "fine batch");
+    e = timed(c, AP_K_SWEEP, s,
+              [&] { return ap::launch_sweep(c->N, U, Fn, G, part + size_t(k) * Ns, Ns, 0, c64, c32, c->tabs, s); });
+    if (e != hipSuccess) return hip_fail(e, "correction sweep");
+    e = timed(c, AP_K_RESID, s,
+              [&] { return ap::launch_resid(part + size_t(k) * Ns, Ns, 1, resid + k, nullptr, s); });
+    if (e != hipSuccess) return hip_fail(e, "resid");
+    if (p->tol > 0.0) {
+      double r = 0.0;
+      if ((e = hipMemcpyAsync(&r, resid + k, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+          (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "residual readback");
+      if (!std::isfinite(r)) return fail(AP_ENUMERIC, "non-finite parareal residual");
+      if (r <= p->tol && k + 1 < p->K) {
+        std::vector<double> rest(size_t(p->K - k - 1), -1.0);
+        if ((e = hipMemcpyAsync(resid + k + 1, rest.data(), rest.size() * sizeof(double), hipMemcpyHostToDevice,
+                                s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+          return hip_fail(e, "residual fill");
+        break;
+      }
+    }
+  }
+  e = timed(c, AP_K_TO_PHYSICAL, s, [&] { return ap::launch_to_physical(c->N, U, U_out, Ns + 1, c->tabs, s); });
+  if (e != hipSuccess) return hip_fail(e, "to_physical");
+  return AP_OK;
+}
+
+int solve_pipelined(ap_ctx* c, const double* u0, const ap_solve_params* p, double* U_out, double* resid,
+                    hipStream_t s, int steps, FineTables* ft, AvgTables* at) {
+  const int Ns = p->slices, K = p->K;
+  const size_t sb = state_bytes(c);
+  // job flags, ticket, stall record [3], per-workgroup progress [2][256]
+  const int nflags = (2 * K + 1) * Ns + 4 + 2 * 256;
+  hipError_t e;
+  if ((e = ensure(c, c->pp_U, sb * size_t(K + 1) * (Ns + 1))) != hipSuccess ||
+      (e = ensure(c, c->pp_F, sb * size_t(std::max(K, 1)) * (Ns + 1))) != hipSuccess ||
+      (e = ensure(c, c->pp_G, sb * size_t(K + 1) * (Ns + 1))) != hipSuccess ||
+      (e = ensure(c, c->pp_part, sizeof(double2) * size_t(Ns) * std::max(1, K))) != hipSuccess ||
+      (e = ensure(c, c->pp_flags, sizeof(int) * size_t(nflags))) != hipSuccess ||
+      (e = ensure(c, c->pp_prob, sizeof(ap::PipeProb<double>))) != hipSuccess)
+    return hip_fail(e, "pipeline workspace");
+  const auto key = std::make_tuple(Ns, K, steps, p->M_avg);
+  if (key != c->pp_jobs_key) {
+    c->pp_jobs_host = pipeline_jobs(0, Ns, K, steps, p->M_avg);
+    c->pp_njobs = int(c->pp_jobs_host.size());
+    if ((e = ensure(c, c->pp_jobs, sizeof(ap::PipeJob) * c->pp_jobs_host.size())) != hipSuccess ||
+        (e = hipMemcpy(c->pp_jobs.p, c->pp_jobs_host.data(), sizeof(ap::PipeJob) * c->pp_jobs_host.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "job list upload");
+    c->pp_jobs_key = key;
+  }
+  const bool f64 = p->precision == AP_PREC_FP64;
+  cx<double>* U = c->pp_U.as<cx<double>>();
+  int* flags = c->pp_flags.as<int>();
+  int* ticket = flags + (2 * K + 1) * Ns;
+  int* abort = ticket + 1;
+  c->pp_prob_host.resize(sizeof(ap::PipeProb<double>));
+  if (f64) {
+    ap::PipeProb<double> pr{U, c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(), c->pp_part.as<double2>(),
+                            flags, Ns, K, steps, ft->coef64.as<cx<double>>(), ft->coef64.as<cx<double>>(), at->c64};
+    std::memcpy(c->pp_prob_host.data(), &pr, sizeof(pr));
+  } else {
+    ap::PipeProb<float> pr{U, c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(), c->pp_part.as<double2>(),
+                           flags, Ns, K, steps, ft->coef64.as<cx<double>>(), ft->coef32.as<cx<float>>(), at->c32};
+    std::memcpy(c->pp_prob_host.data(), &pr, sizeof(pr));
+  }
+  if ((e = hipMemcpyAsync(c->pp_prob.p, c->pp_prob_host.data(), c->pp_prob_host.size(), hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return hip_fail(e, "problem descriptor upload");
+  const size_t st = size_t(3) * c->KP;
+  e = timed(c, AP_K_TO_MODAL, s, [&] { return ap::launch_to_modal(c->N, u0, U, 1, c->tabs, s); });
+  if (e != hipSuccess) return hip_fail(e, "to_modal");
+  if (K > 0 && (e = hipMemcpyAsync(U + size_t(K) * (Ns + 1) * st, U, sb, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(e, "initial state copy");
+  if ((e = ap::launch_zero_ints(flags, nflags, s)) != hipSuccess) return hip_fail(e, "flag reset");
+  c->pp_diag = abort;
+  const int grid = std::min(c->pp_njobs, 256);
+  e = timed(c, AP_K_PIPELINE, s, [&] {
+    return ap::launch_pipeline(c->N, f64, c->pp_jobs.p, c->pp_njobs, c->pp_prob.p, ticket, abort, abort + 3, grid,
+                               c->tabs, s);
+  });
+  if (e != hipSuccess) return hip_fail(e, "pipeline launch");
+  if (K > 0) {
+    e = timed(c, AP_K_RESID, s,
+              [&] { return ap::launch_resid(c->pp_part.as<double2>(), Ns, K, resid, abort, s); });
+    if (e != hipSuccess) return hip_fail(e, "resid");
+  }
+  cx<double>* UK = U + size_t(K) * (Ns + 1) * st;
+  e = timed(c, AP_K_TO_PHYSICAL, s, [&] { return ap::launch_to_physical(c->N, UK, U_out, Ns + 1, c->tabs, s); });
+  if (e != hipSuccess) return hip_fail(e, "to_physical");
   return AP_OK;
 }
 
@@ -394,8 +590,10 @@ int aparareal_nonlinear(ap_ctx* c, const double* U_in, double* N_out, int batch,
   hipStream_t s = static_cast<hipStream_t>(stream);
   int rc = batch_prologue(c, U_in, N_out, batch, precision, s);
   if (rc || batch == 0) return rc;
-  hipError_t e = ap::launch_nonlinear(c->N, precision == AP_PREC_FP64, c->ws_in.as<cx<double>>(),
-                                      c->ws_out.as<cx<double>>(), batch, c->tabs, s);
+  hipError_t e = timed(c, AP_K_NONLINEAR, s, [&] {
+    return ap::launch_nonlinear(c->N, precision == AP_PREC_FP64, c->ws_in.as<cx<double>>(),
+                                c->ws_out.as<cx<double>>(), batch, c->tabs, s);
+  });
   if (e != hipSuccess) return hip_fail(e, "nonlinear launch");
   return batch_epilogue(c, N_out, batch, s);
 }
@@ -411,8 +609,10 @@ int aparareal_fine_batch(ap_ctx* c, const double* U_in, double* U_out, int batch
   FineTables* ft = nullptr;
   if ((rc = fine_tables(c, dT / steps, &ft))) return rc;
   const bool f64 = precision == AP_PREC_FP64;
-  hipError_t e = ap::launch_fine(c->N, f64, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(), batch, steps,
-                                 ft->coef64.as<cx<double>>(), ft->coef32.as<cx<float>>(), c->tabs, s);
+  hipError_t e = timed(c, AP_K_FINE, s, [&] {
+    return ap::launch_fine(c->N, f64, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(), batch, steps,
+                           ft->coef64.as<cx<double>>(), ft->coef32.as<cx<float>>(), c->tabs, s);
+  });
   if (e != hipSuccess) return hip_fail(e, "fine launch");
   return batch_epilogue(c, U_out, batch, s);
 }
@@ -427,8 +627,10 @@ int aparareal_average(ap_ctx* c, const double* U_in, double* N_out, int batch, d
   AvgTables* at = nullptr;
   if ((rc = avg_tables(c, 0.0, T0, M_avg, &at))) return rc;
   const bool f64 = precision == AP_PREC_FP64;
-  hipError_t e = ap::launch_average(c->N, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(), batch,
-                                    f64 ? &at->c64.avg : nullptr, f64 ? nullptr : &at->c32.avg, c->tabs, s);
+  hipError_t e = timed(c, AP_K_AVERAGE, s, [&] {
+    return ap::launch_average(c->N, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(), batch,
+                              f64 ? &at->c64.avg : nullptr, f64 ? nullptr : &at->c32.avg, c->tabs, s);
+  });
   if (e != hipSuccess) return hip_fail(e, "average launch");
   return batch_epilogue(c, N_out, batch, s);
 }
@@ -446,8 +648,10 @@ int aparareal_coarse(ap_ctx* c, const double* U_in, double* U_out, int batch, do
   AvgTables* at = nullptr;
   if ((rc = avg_tables(c, dT, win, M_avg, &at))) return rc;
   const bool f64 = precision == AP_PREC_FP64;
-  hipError_t e = ap::launch_coarse(c->N, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(), batch,
-                                   f64 ? &at->c64 : nullptr, f64 ? nullptr : &at->c32, c->tabs, s);
+  hipError_t e = timed(c, AP_K_COARSE, s, [&] {
+    return ap::launch_coarse(c->N, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(), batch,
+                             f64 ? &at->c64 : nullptr, f64 ? nullptr : &at->c32, c->tabs, s);
+  });
   if (e != hipSuccess) return hip_fail(e, "coarse launch");
   return batch_epilogue(c, U_out, batch, s);
 }
@@ -466,6 +670,7 @@ int aparareal_solve(ap_ctx* c, const double* u0, const ap_solve_params* p, doubl
   if (!(p->dt_fine > 0.0) || !std::isfinite(p->dt_fine)) return fail(AP_EINVAL, "dt_fine must be > 0");
   if (p->M_avg < 2) return fail(AP_EINVAL, "M_avg must be >= 2");
   if (!std::isfinite(p->T0) || !std::isfinite(p->tol)) return fail(AP_EINVAL, "T0, tol must be finite");
+  if (size_t(2 * p->K + 1) * size_t(p->slices) > (size_t(1) << 30)) return fail(AP_EINVAL, "problem too large");
   const int Ns = p->slices;
   const double dT = p->T / Ns;
   const double ratio = dT / p->dt_fine;
@@ -479,48 +684,70 @@ int aparareal_solve(ap_ctx* c, const double* u0, const ap_solve_params* p, doubl
   AvgTables* at = nullptr;
   if ((rc = fine_tables(c, h, &ft))) return rc;
   if ((rc = avg_tables(c, dT, win, p->M_avg, &at))) return rc;
-  const size_t sb = state_bytes(c);
-  if ((e = ensure(c, c->ws_U, sb * (Ns + 1))) != hipSuccess ||
-      (e = ensure(c, c->ws_F, sb * (Ns + 1))) != hipSuccess ||
-      (e = ensure(c, c->ws_G, sb * (Ns + 1))) != hipSuccess ||
-      (e = ensure(c, c->ws_part, sizeof(double2) * size_t(Ns) * std::max(1, p->K))) != hipSuccess)
-    return hip_fail(e, "solve workspace");
-  const bool f64 = p->precision == AP_PREC_FP64;
-  const ap::CoarseTab<double>* c64 = f64 ? &at->c64 : nullptr;
-  const ap::CoarseTab<float>* c32 = f64 ? nullptr : &at->c32;
-  cx<double>* U = c->ws_U.as<cx<double>>();
-  cx<double>* Fn = c->ws_F.as<cx<double>>();
-  cx<double>* G = c->ws_G.as<cx<double>>();
-  double2* part = c->ws_part.as<double2>();
-  const size_t st = size_t(3) * c->KP;
-  if ((e = ap::launch_to_modal(c->N, u0, U, 1, c->tabs, s)) != hipSuccess) return hip_fail(e, "to_modal");
-  if ((e = ap::launch_sweep(c->N, U, Fn, G, part, Ns, 1, c64, c32, c->tabs, s)) != hipSuccess)
-    return hip_fail(e, "initial sweep");
-  for (int k = 0; k < p->K; ++k) {
-    e = ap::launch_fine(c->N, f64, U, Fn + st, Ns, steps, ft->coef64.as<cx<double>>(), ft->coef32.as<cx<float>>(),
-                        c->tabs, s);
-    if (e != hipSuccess) return hip_fail(e, "fine batch");
-    e = ap::launch_sweep(c->N, U, Fn, G, part + size_t(k) * Ns, Ns, 0, c64, c32, c->tabs, s);
-    if (e != hipSuccess) return hip_fail(e, "correction sweep");
-    if ((e = ap::launch_resid(part + size_t(k) * Ns, Ns, resid + k, s)) != hipSuccess) return hip_fail(e, "resid");
-    if (p->tol > 0.0) {
-      double r = 0.0;
-      if ((e = hipMemcpyAsync(&r, resid + k, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-          (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(e, "residual readback");
-      if (!std::isfinite(r)) return fail(AP_ENUMERIC, "non-finite parareal residual");
-      if (r <= p->tol && k + 1 < p->K) {
-        std::vector<double> rest(size_t(p->K - k - 1), -1.0);
-        if ((e = hipMemcpyAsync(resid + k + 1, rest.data(), rest.size() * sizeof(double), hipMemcpyHostToDevice,
-                                s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-          return hip_fail(e, "residual fill");
-        break;
-      }
+  if (p->tol > 0.0) return solve_sweeps(c, u0, p, U_out, resid, s, steps, ft, at);
+  return solve_pipelined(c, u0, p, U_out, resid, s, steps, ft, at);
+}
+
+int aparareal_pipeline_status(ap_ctx* c, int* info) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!info) return fail(AP_EINVAL, "null info");
+  info[0] = info[1] = info[2] = 0;
+  if (!c->pp_diag) return AP_OK;
+  hipError_t e = c->has_last ? hipStreamSynchronize(c->last_stream) : hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(info, c->pp_diag, 3 * sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "pipeline status");
+  return AP_OK;
+}
+
+int aparareal_pipeline_schedule(int slices, int K, int steps, int M_avg, int* out) {
+  if (slices < 1 || K < 0 || steps < 1 || M_avg < 2 || !out) return fail(AP_EINVAL, "bad schedule query");
+  if (size_t(2 * K + 1) * size_t(slices) > (size_t(1) << 30)) return fail(AP_EINVAL, "problem too large");
+  const std::vector<ap::PipeJob> jobs = pipeline_jobs(0, slices, K, steps, M_avg);
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    out[3 * i] = jobs[i].type;
+    out[3 * i + 1] = jobs[i].k;
+    out[3 * i + 2] = jobs[i].n;
+  }
+  return int(jobs.size());
+}
+
+int aparareal_profile(ap_ctx* c, int enable) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (enable) {
+    for (auto& t : c->ev_pending) {
+      c->ev_pool.push_back(std::get<1>(t));
+      c->ev_pool.push_back(std::get<2>(t));
+    }
+    c->ev_pending.clear();
+    for (int i = 0; i < AP_K_CLASSES; ++i) {
+      c->prof_count[i] = 0;
+      c->prof_ms[i] = 0.0;
     }
   }
-  if ((e = ap::launch_to_physical(c->N, U, U_out, Ns + 1, c->tabs, s)) != hipSuccess)
-    return hip_fail(e, "to_physical");
+  c->prof_on = enable != 0;
+  return AP_OK;
+}
+
+int aparareal_profile_read(ap_ctx* c, int cls, int* launches, double* total_ms) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (cls < 0 || cls >= AP_K_CLASSES || !launches || !total_ms) return fail(AP_EINVAL, "bad profile query");
+  for (auto& t : c->ev_pending) {
+    hipEvent_t a = std::get<1>(t), b = std::get<2>(t);
+    hipError_t e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e != hipSuccess) return hip_fail(e, "profile events");
+    c->prof_count[std::get<0>(t)] += 1;
+    c->prof_ms[std::get<0>(t)] += ms;
+    c->ev_pool.push_back(a);
+    c->ev_pool.push_back(b);
+  }
+  c->ev_pending.clear();
+  *launches = c->prof_count[cls];
+  *total_ms = c->prof_ms[cls];
   return AP_OK;
 }
 

@@ -8,47 +8,33 @@
 //   k_average                  : kernel-weighted time average (eq. numerical
 //                                average; Alg. 1), samples in flight together
 //   k_coarse                   : one asymptotic coarse step per state (Alg. 2)
-//   k_sweep                    : the serial coarse sweep of one parareal
-//                                iteration with the FP64 correction
-//                                U_n = Fine_n + (G_new - G_old) and the residual
-//                                partial sums (eq. HMM parareal iteration; Alg. 4)
-//   k_resid                    : r^k = max_n sqrt(num_n / den_n)
-#include "launch.hpp"
-#include "rsw_device.hpp"
+//   k_sweep                    : one serial coarse sweep of a parareal iteration
+//                                with the FP64 correction (eq. HMM parareal
+//                                iteration), used by the tolerance-driven solve
+//   k_pipeline                 : the whole iteration as one persistent launch:
+//                                coarse steps C(k,n) and fine slices F(k,n) of all
+//                                iterations k are jobs taken in a topological
+//                                order from one ticket counter, each waiting on
+//                                the done flags of the jobs it reads
+//   k_resid_rows               : r^k = max_n sqrt(num_n / den_n) per iteration
+#include "engine.hpp"
 
 namespace ap {
-
-// ------------------------------------------------------------ helpers -----
-template <int NX, int NT>
-struct Own {
-  static constexpr int KP = Geo<NX>::KP;
-  static constexpr int MPT = (KP + NT - 1) / NT;
-  static __device__ __forceinline__ int mode(int j) { return threadIdx.x + j * NT; }
-  static __device__ __forceinline__ bool valid(int j) { return mode(j) < KP; }
-};
-
-template <typename T>
-__device__ __forceinline__ cx<T> rot_in(cx<T> c, cx<T> e, int alpha_idx) {
-  // exp(-i alpha omega s) with e = exp(-i omega s): alpha=+1 -> e, -1 -> conj(e), 0 -> 1
-  return alpha_idx == 2 ? c * e : (alpha_idx == 0 ? c * conj(e) : c);
-}
-template <typename T>
-__device__ __forceinline__ cx<T> rot_out(cx<T> c, cx<T> e, int alpha_idx) {
-  return alpha_idx == 2 ? c * conj(e) : (alpha_idx == 0 ? c * e : c);
-}
 
 // ------------------------------------------------- boundary transforms -----
 // physical [B][3][N] float64 -> modal [B][3][KP] complex float64 (projected)
 template <int NX, int NT>
 __global__ void __launch_bounds__(NT) k_to_modal(const double* __restrict__ phys, cx<double>* __restrict__ modal,
-                                                 const cx<double>* __restrict__ tw,
+                                                 const cx<double>* __restrict__ tw_g,
                                                  const Basis<double>* __restrict__ basis) {
   using G = Geo<NX>;
   using T = double;
   constexpr int P = G::P;
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* a = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* a = tw + NX;
   cx<T>* b = a + 3 * P;
+  for (int i = threadIdx.x; i < NX; i += NT) tw[i] = tw_g[i];
   const double* src = phys + size_t(blockIdx.x) * 3 * NX;
   for (int i = threadIdx.x; i < 3 * P; i += NT) {
     const int f = i / P, n = i - f * P;
@@ -66,9 +52,7 @@ __global__ void __launch_bounds__(NT) k_to_modal(const double* __restrict__ phys
       const cx<T> zk = R[f * P + k], zc = conj(R[f * P + kc]);
       X[f] = half_over_n * ((zk + zc) - mul_i(w * (zk - zc)));
     }
-    if (k == 0) {  // real signals: the mean is real
-      X[0].y = X[1].y = X[2].y = T(0);
-    }
+    if (k == 0) X[0].y = X[1].y = X[2].y = T(0);   // real signals: the mean is real
     cx<T> c[3];
     fields_to_modal<T>(X[0], X[1], X[2], basis[k], c);
     for (int al = 0; al < 3; ++al) dst[al * G::KP + k] = c[al];
@@ -78,27 +62,28 @@ __global__ void __launch_bounds__(NT) k_to_modal(const double* __restrict__ phys
 // modal [B][3][KP] -> physical [B][3][N]
 template <int NX, int NT>
 __global__ void __launch_bounds__(NT) k_to_physical(const cx<double>* __restrict__ modal, double* __restrict__ phys,
-                                                    const cx<double>* __restrict__ tw,
+                                                    const cx<double>* __restrict__ tw_g,
                                                     const Basis<double>* __restrict__ basis) {
   using G = Geo<NX>;
   using T = double;
   constexpr int P = G::P;
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* spec = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* a = spec + 3 * (P + 1);
-  cx<T>* b = a + 3 * P;
+  // spec [3][P+1] shares the second FFT buffer: it is dead once the
+  // pre-processed spectra are in `a`.
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* a = tw + NX;
+  cx<T>* spec = a + 3 * P;
+  cx<T>* b = spec;
+  for (int i = threadIdx.x; i < NX; i += NT) tw[i] = tw_g[i];
   zero_spec_tail<T, NX, NT>(spec, 1);
   const cx<double>* src = modal + size_t(blockIdx.x) * 3 * G::KP;
   const T s = T(0.70710678118654752440);
   for (int k = threadIdx.x; k < G::KP; k += NT) {
     const cx<T> c0 = src[k], c1 = src[G::KP + k], c2 = src[2 * G::KP + k];
     const Basis<T> bs = basis[k];
-    const cx<T> v1 = s * (c0 + c2);
-    const cx<T> v2 = mul_i((bs.iw * s) * (c0 - c2) + bs.aw * c1);
-    const cx<T> h = (bs.aw * s) * (c2 - c0) + bs.iw * c1;
-    spec[k] = v1;
-    spec[(P + 1) + k] = v2;
-    spec[2 * (P + 1) + k] = h;
+    spec[k] = s * (c0 + c2);
+    spec[(P + 1) + k] = mul_i((bs.iw * s) * (c0 - c2) + bs.aw * c1);
+    spec[2 * (P + 1) + k] = (bs.aw * s) * (c2 - c0) + bs.iw * c1;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 3 * P; i += NT) {
@@ -122,349 +107,227 @@ __global__ void __launch_bounds__(NT) k_to_physical(const cx<double>* __restrict
 template <typename T, int NX, int NT>
 __global__ void __launch_bounds__(NT) k_nonlinear(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Nout,
                                                   const cx<T>* __restrict__ tw, const Basis<T>* __restrict__ basis) {
-  using G = Geo<NX>;
-  using O = Own<NX, NT>;
+  using E_ = Engine<T, NX, NT, 1>;
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* spec = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* a = spec + Lds<T, NX>::spec_elems(1);
-  cx<T>* b = a + Lds<T, NX>::work_elems(1);
-  zero_spec_tail<T, NX, NT>(spec, 1);
-  const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * G::KP;
-  cx<double>* dst = Nout + size_t(blockIdx.x) * 3 * G::KP;
+  E_ en(smem_raw, tw);
+  const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * E_::KP;
+  cx<double>* dst = Nout + size_t(blockIdx.x) * 3 * E_::KP;
 #pragma unroll
-  for (int j = 0; j < O::MPT; ++j) {
-    if (!O::valid(j)) continue;
-    const int k = O::mode(j);
+  for (int j = 0; j < E_::MPT; ++j) {
+    if (!E_::valid(j)) continue;
+    const int k = E_::mode(j);
     cx<T> c[3];
-    for (int al = 0; al < 3; ++al) c[al] = cvt<T>(src[al * G::KP + k]);
-    put_fields<T, NX>(spec, 0, k, c, basis[k]);
+    for (int al = 0; al < 3; ++al) c[al] = cvt<T>(src[al * E_::KP + k]);
+    put_fields<T, NX>(en.spec, 0, k, c, basis[k]);
   }
   __syncthreads();
-  cx<T>* R = nonlinear_core<T, NX, NT>(spec, a, b, 1, tw);
+  cx<T>* R = en.nonlinear(1);
 #pragma unroll
-  for (int j = 0; j < O::MPT; ++j) {
-    if (!O::valid(j)) continue;
-    const int k = O::mode(j);
+  for (int j = 0; j < E_::MPT; ++j) {
+    if (!E_::valid(j)) continue;
+    const int k = E_::mode(j);
     cx<T> n[3];
-    get_N<T, NX>(R, 0, k, basis[k], tw, n);
-    for (int al = 0; al < 3; ++al) dst[al * G::KP + k] = cvt<double>(n[al]);
+    get_N<T, NX>(R, 0, k, basis[k], en.tw, n);
+    for (int al = 0; al < 3; ++al) dst[al * E_::KP + k] = cvt<double>(n[al]);
   }
 }
 
-// ------------------------------------------------------------ fine ETDRK4 ---
-// Coefficient tables [8][3][KP] per precision: E_hi, E_lo, E2_hi, E2_lo, Q, f1,
-// 2*f2, f3 for each (alpha, k).  The state and the step accumulator
-// u+ = E u + f1 N(u) + 2f2 (N(a) + N(b)) + f3 N(c) are kept in FP64 in both
-// precisions (E from the FP64 table): the slowly varying modes change by less
-// than half an FP32 ulp per step, so an FP32 state would drop those increments
-// coherently step after step.  With T = float the stage states a, b, c, the
-// nonlinear evaluations and the products f*N run in FP32.
+// ------------------------------------------------------------ fine batch ---
 template <typename T, int NX, int NT>
 __global__ void __launch_bounds__(NT) k_fine(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
                                              int steps, const cx<double>* __restrict__ coef64,
                                              const cx<T>* __restrict__ coef, const cx<T>* __restrict__ tw,
                                              const Basis<T>* __restrict__ basis) {
-  using G = Geo<NX>;
-  using O = Own<NX, NT>;
-  constexpr int KP = G::KP;
-  constexpr int MPT = O::MPT;
+  using E_ = Engine<T, NX, NT, 1>;
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* spec = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* a_buf = spec + Lds<T, NX>::spec_elems(1);
-  cx<T>* b_buf = a_buf + Lds<T, NX>::work_elems(1);
-  zero_spec_tail<T, NX, NT>(spec, 1);
-
-  const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * KP;
-  cx<double>* dst = Uout + size_t(blockIdx.x) * 3 * KP;
-
-  cx<double> c[MPT][3], cE[MPT][3];
-  cx<T> cE2[MPT][3], cQ[MPT][3], cf1[MPT][3], cf2[MPT][3], cf3[MPT][3];
-  Basis<T> bs[MPT];
-#pragma unroll
-  for (int j = 0; j < MPT; ++j) {
-    const int k = O::mode(j) < KP ? O::mode(j) : KP - 1;
-    bs[j] = basis[k];
-#pragma unroll
-    for (int al = 0; al < 3; ++al) {
-      const int o = al * KP + k;
-      c[j][al] = src[o];
-      cE[j][al] = coef64[0 * 3 * KP + o];
-      cE2[j][al] = coef[2 * 3 * KP + o];
-      cQ[j][al] = coef[4 * 3 * KP + o];
-      cf1[j][al] = coef[5 * 3 * KP + o];
-      cf2[j][al] = coef[6 * 3 * KP + o];
-      cf3[j][al] = coef[7 * 3 * KP + o];
-    }
-  }
-
-  // N of the modal state x (per owned mode) -> n
-  auto neval = [&](cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3]) {
-#pragma unroll
-    for (int j = 0; j < MPT; ++j)
-      if (O::valid(j)) put_fields<T, NX>(spec, 0, O::mode(j), x[j], bs[j]);
-    __syncthreads();
-    cx<T>* R = nonlinear_core<T, NX, NT>(spec, a_buf, b_buf, 1, tw);
-#pragma unroll
-    for (int j = 0; j < MPT; ++j)
-      if (O::valid(j)) get_N<T, NX>(R, 0, O::mode(j), bs[j], tw, n[j]);
-  };
-
-  cx<T> Nx[MPT][3], st[MPT][3], E2c[MPT][3], Nu[MPT][3];
-  cx<double> acc[MPT][3];
-  for (int step = 0; step < steps; ++step) {
-#pragma unroll
-    for (int j = 0; j < MPT; ++j)
-#pragma unroll
-      for (int al = 0; al < 3; ++al) st[j][al] = cvt<T>(c[j][al]);
-    neval(st, Nu);
-#pragma unroll
-    for (int j = 0; j < MPT; ++j)
-#pragma unroll
-      for (int al = 0; al < 3; ++al) {
-        E2c[j][al] = cE2[j][al] * st[j][al];
-        st[j][al] = cfma(cQ[j][al], Nu[j][al], E2c[j][al]);                                   // a
-        acc[j][al] = cE[j][al] * c[j][al] + cvt<double>(cf1[j][al] * Nu[j][al]);
-      }
-    neval(st, Nx);                                                                            // N(a)
-#pragma unroll
-    for (int j = 0; j < MPT; ++j)
-#pragma unroll
-      for (int al = 0; al < 3; ++al) {
-        acc[j][al] = acc[j][al] + cvt<double>(cf2[j][al] * Nx[j][al]);
-        const cx<T> a_ = st[j][al];
-        st[j][al] = cfma(cQ[j][al], Nx[j][al], E2c[j][al]);                                   // b
-        E2c[j][al] = cE2[j][al] * a_;                                                         // E2 a
-      }
-    neval(st, Nx);                                                                            // N(b)
-#pragma unroll
-    for (int j = 0; j < MPT; ++j)
-#pragma unroll
-      for (int al = 0; al < 3; ++al) {
-        acc[j][al] = acc[j][al] + cvt<double>(cf2[j][al] * Nx[j][al]);
-        st[j][al] = cfma(cQ[j][al], T(2) * Nx[j][al] - Nu[j][al], E2c[j][al]);                // c
-      }
-    neval(st, Nx);                                                                            // N(c)
-#pragma unroll
-    for (int j = 0; j < MPT; ++j)
-#pragma unroll
-      for (int al = 0; al < 3; ++al) c[j][al] = acc[j][al] + cvt<double>(cf3[j][al] * Nx[j][al]);
-  }
-#pragma unroll
-  for (int j = 0; j < MPT; ++j)
-    if (O::valid(j))
-      for (int al = 0; al < 3; ++al) dst[al * KP + O::mode(j)] = c[j][al];
+  E_ en(smem_raw, tw);
+  const size_t st = size_t(3) * E_::KP;
+  fine_job<T, NX, NT, 1>(en, Uin + blockIdx.x * st, Uout + blockIdx.x * st, steps, coef64, coef, basis);
 }
 
-// ----------------------------------------------------------- time average ---
-// Nbar of the owned-mode state y (registers) -> acc, S samples in flight.
-template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void nbar_owned(const cx<T> (&y)[Own<NX, NT>::MPT][3], cx<T> (&acc)[Own<NX, NT>::MPT][3],
-                                           const Basis<T> (&bs)[Own<NX, NT>::MPT], const AvgTab<T>& av,
-                                           cx<T>* spec, cx<T>* a_buf, cx<T>* b_buf,
-                                           const cx<T>* __restrict__ tw) {
-  using G = Geo<NX>;
-  using O = Own<NX, NT>;
-  constexpr int KP = G::KP;
-#pragma unroll
-  for (int j = 0; j < O::MPT; ++j)
-    for (int al = 0; al < 3; ++al) acc[j][al] = czero<T>();
-  for (int m0 = 1; m0 < av.M; m0 += S) {
-    const int ns = min(S, av.M - m0);
-    for (int s = 0; s < ns; ++s) {
-      const cx<T>* rot = av.rot + size_t(m0 + s) * KP;
-#pragma unroll
-      for (int j = 0; j < O::MPT; ++j) {
-        if (!O::valid(j)) continue;
-        const int k = O::mode(j);
-        const cx<T> e = rot[k];
-        cx<T> x[3];
-        for (int al = 0; al < 3; ++al) x[al] = rot_in(y[j][al], e, al);
-        put_fields<T, NX>(spec, s, k, x, bs[j]);
-      }
-    }
-    __syncthreads();
-    cx<T>* R = nonlinear_core<T, NX, NT>(spec, a_buf, b_buf, ns, tw);
-    for (int s = 0; s < ns; ++s) {
-      const cx<T>* rot = av.rot + size_t(m0 + s) * KP;
-      const T wm = av.w[m0 + s];
-#pragma unroll
-      for (int j = 0; j < O::MPT; ++j) {
-        if (!O::valid(j)) continue;
-        const int k = O::mode(j);
-        const cx<T> e = rot[k];
-        cx<T> n[3];
-        get_N<T, NX>(R, s, k, bs[j], tw, n);
-        for (int al = 0; al < 3; ++al) acc[j][al] = acc[j][al] + wm * rot_out(n[al], e, al);
-      }
-    }
-  }
-}
-
-// One asymptotic coarse step on owned-mode registers u -> g (Alg. 2).
-template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void coarse_owned(const cx<T> (&u)[Own<NX, NT>::MPT][3], cx<T> (&g)[Own<NX, NT>::MPT][3],
-                                             const Basis<T> (&bs)[Own<NX, NT>::MPT], const CoarseTab<T>& ct,
-                                             cx<T>* spec, cx<T>* a_buf, cx<T>* b_buf,
-                                             const cx<T>* __restrict__ tw) {
-  using O = Own<NX, NT>;
-  constexpr int MPT = O::MPT;
-  cx<T> w[MPT][3], y[MPT][3], kk[MPT][3];
-  T hd[MPT];
-  cx<T> rT[MPT];
-#pragma unroll
-  for (int j = 0; j < MPT; ++j) {
-    const int k = O::valid(j) ? O::mode(j) : 0;
-    hd[j] = ct.hd[k];
-    rT[j] = ct.rotT[k];
-    for (int al = 0; al < 3; ++al) w[j][al] = hd[j] * u[j][al];
-  }
-  nbar_owned<T, NX, NT, S>(w, kk, bs, ct.avg, spec, a_buf, b_buf, tw);
-  const T half = T(0.5) * ct.dT;
-#pragma unroll
-  for (int j = 0; j < MPT; ++j)
-    for (int al = 0; al < 3; ++al) y[j][al] = w[j][al] + half * kk[j][al];
-  nbar_owned<T, NX, NT, S>(y, kk, bs, ct.avg, spec, a_buf, b_buf, tw);
-#pragma unroll
-  for (int j = 0; j < MPT; ++j)
-    for (int al = 0; al < 3; ++al) {
-      const cx<T> v = hd[j] * (w[j][al] + ct.dT * kk[j][al]);
-      g[j][al] = al == 2 ? v * rT[j] : (al == 0 ? v * conj(rT[j]) : v);
-    }
-}
-
+// ---------------------------------------------------- average and coarse ---
 template <typename T, int NX, int NT, int S>
 __global__ void __launch_bounds__(NT) k_average(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Nout,
                                                 AvgTab<T> av, const cx<T>* __restrict__ tw,
                                                 const Basis<T>* __restrict__ basis) {
-  using G = Geo<NX>;
-  using O = Own<NX, NT>;
+  using E_ = Engine<T, NX, NT, S>;
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* spec = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* a_buf = spec + Lds<T, NX>::spec_elems(S);
-  cx<T>* b_buf = a_buf + Lds<T, NX>::work_elems(S);
-  zero_spec_tail<T, NX, NT>(spec, S);
-  const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * G::KP;
-  cx<double>* dst = Nout + size_t(blockIdx.x) * 3 * G::KP;
-  cx<T> y[O::MPT][3], acc[O::MPT][3];
-  Basis<T> bs[O::MPT];
+  E_ en(smem_raw, tw);
+  const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * E_::KP;
+  cx<double>* dst = Nout + size_t(blockIdx.x) * 3 * E_::KP;
+  cx<T> y[E_::MPT][3], acc[E_::MPT][3];
+  Basis<T> bs[E_::MPT];
 #pragma unroll
-  for (int j = 0; j < O::MPT; ++j) {
-    const int k = O::valid(j) ? O::mode(j) : 0;
+  for (int j = 0; j < E_::MPT; ++j) {
+    const int k = E_::valid(j) ? E_::mode(j) : 0;
     bs[j] = basis[k];
-    for (int al = 0; al < 3; ++al) y[j][al] = O::valid(j) ? cvt<T>(src[al * G::KP + k]) : czero<T>();
+    for (int al = 0; al < 3; ++al) y[j][al] = E_::valid(j) ? cvt<T>(src[al * E_::KP + k]) : czero<T>();
   }
-  nbar_owned<T, NX, NT, S>(y, acc, bs, av, spec, a_buf, b_buf, tw);
+  nbar_owned<T, NX, NT, S>(en, y, acc, bs, av);
 #pragma unroll
-  for (int j = 0; j < O::MPT; ++j)
-    if (O::valid(j))
-      for (int al = 0; al < 3; ++al) dst[al * G::KP + O::mode(j)] = cvt<double>(acc[j][al]);
+  for (int j = 0; j < E_::MPT; ++j)
+    if (E_::valid(j))
+      for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = cvt<double>(acc[j][al]);
 }
 
 template <typename T, int NX, int NT, int S>
 __global__ void __launch_bounds__(NT) k_coarse(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
                                                CoarseTab<T> ct, const cx<T>* __restrict__ tw,
                                                const Basis<T>* __restrict__ basis) {
-  using G = Geo<NX>;
-  using O = Own<NX, NT>;
+  using E_ = Engine<T, NX, NT, S>;
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* spec = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* a_buf = spec + Lds<T, NX>::spec_elems(S);
-  cx<T>* b_buf = a_buf + Lds<T, NX>::work_elems(S);
-  zero_spec_tail<T, NX, NT>(spec, S);
-  const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * G::KP;
-  cx<double>* dst = Uout + size_t(blockIdx.x) * 3 * G::KP;
-  cx<T> u[O::MPT][3], g[O::MPT][3];
-  Basis<T> bs[O::MPT];
-#pragma unroll
-  for (int j = 0; j < O::MPT; ++j) {
-    const int k = O::valid(j) ? O::mode(j) : 0;
-    bs[j] = basis[k];
-    for (int al = 0; al < 3; ++al) u[j][al] = O::valid(j) ? cvt<T>(src[al * G::KP + k]) : czero<T>();
-  }
-  coarse_owned<T, NX, NT, S>(u, g, bs, ct, spec, a_buf, b_buf, tw);
-#pragma unroll
-  for (int j = 0; j < O::MPT; ++j)
-    if (O::valid(j))
-      for (int al = 0; al < 3; ++al) dst[al * G::KP + O::mode(j)] = cvt<double>(g[j][al]);
+  E_ en(smem_raw, tw);
+  const size_t st = size_t(3) * E_::KP;
+  cx<double>* o = Uout + blockIdx.x * st;
+  coarse_job<T, NX, NT, S>(en, ct, basis, Uin + blockIdx.x * st, o, o, nullptr, nullptr, nullptr, nullptr);
 }
 
-// ------------------------------------------------------ serial sweep ------
-// One workgroup per problem.  U, Fine, Gold: modal FP64 [Ns+1][3][KP].
-// initial != 0: U_n = Gold_n = G(U_{n-1}).  Otherwise
-// U_n <- Fine_n + (G(U_{n-1}) - Gold_n), Gold_n <- G(U_{n-1}), and
-// part[n-1] = (sum |U_n^new - U_n^old|^2, sum |U_n^new|^2) with Parseval
-// weights (1 for k = 0, 2 otherwise).
+// One workgroup runs the serial sweep over n = 1..Ns of one iteration.
+// U, Fine, Gold: modal FP64 [Ns+1][3][KP], updated in place.
 template <typename T, int NX, int NT, int S>
 __global__ void __launch_bounds__(NT) k_sweep(cx<double>* __restrict__ U, const cx<double>* __restrict__ Fine,
                                               cx<double>* __restrict__ Gold, double2* __restrict__ part, int Ns,
                                               int initial, CoarseTab<T> ct, const cx<T>* __restrict__ tw,
                                               const Basis<T>* __restrict__ basis) {
-  using G = Geo<NX>;
-  using O = Own<NX, NT>;
-  constexpr int KP = G::KP;
+  using E_ = Engine<T, NX, NT, S>;
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* spec = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* a_buf = spec + Lds<T, NX>::spec_elems(S);
-  cx<T>* b_buf = a_buf + Lds<T, NX>::work_elems(S);
-  double* red = reinterpret_cast<double*>(b_buf + Lds<T, NX>::work_elems(S));   // [2][NT]
-  zero_spec_tail<T, NX, NT>(spec, S);
-  Basis<T> bs[O::MPT];
-#pragma unroll
-  for (int j = 0; j < O::MPT; ++j) bs[j] = basis[O::valid(j) ? O::mode(j) : 0];
-  const size_t st = size_t(3) * KP;
+  E_ en(smem_raw, tw);
+  const size_t st = size_t(3) * E_::KP;
   for (int n = 1; n <= Ns; ++n) {
-    cx<T> u[O::MPT][3], g[O::MPT][3];
-#pragma unroll
-    for (int j = 0; j < O::MPT; ++j)
-      for (int al = 0; al < 3; ++al)
-        u[j][al] = O::valid(j) ? cvt<T>(U[(n - 1) * st + al * KP + O::mode(j)]) : czero<T>();
-    coarse_owned<T, NX, NT, S>(u, g, bs, ct, spec, a_buf, b_buf, tw);
-    double num = 0.0, den = 0.0;
-#pragma unroll
-    for (int j = 0; j < O::MPT; ++j) {
-      if (!O::valid(j)) continue;
-      const int k = O::mode(j);
-      const double wgt = k == 0 ? 1.0 : 2.0;
-      for (int al = 0; al < 3; ++al) {
-        const size_t o = n * st + al * KP + k;
-        const cx<double> gn = cvt<double>(g[j][al]);
-        if (initial) {
-          U[o] = gn;
-          Gold[o] = gn;
-        } else {
-          const cx<double> uold = U[o];
-          const cx<double> unew = Fine[o] + (gn - Gold[o]);
-          const cx<double> d = unew - uold;
-          num += wgt * (d.x * d.x + d.y * d.y);
-          den += wgt * (unew.x * unew.x + unew.y * unew.y);
-          U[o] = unew;
-          Gold[o] = gn;
-        }
-      }
-    }
-    if (!initial) {
-      red[threadIdx.x] = num;
-      red[NT + threadIdx.x] = den;
-      __syncthreads();
-      for (int off = NT / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-          red[threadIdx.x] += red[threadIdx.x + off];
-          red[NT + threadIdx.x] += red[NT + threadIdx.x + off];
-        }
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) part[n - 1] = make_double2(red[0], red[NT]);
-      __syncthreads();
-    }
+    cx<double>* Un = U + n * st;
+    cx<double>* Gn = Gold + n * st;
+    if (initial)
+      coarse_job<T, NX, NT, S>(en, ct, basis, U + (n - 1) * st, Un, Gn, nullptr, nullptr, nullptr, nullptr);
+    else
+      coarse_job<T, NX, NT, S>(en, ct, basis, U + (n - 1) * st, Un, Gn, Gn, Fine + n * st, Un, part + (n - 1));
   }
 }
 
-// r = max_n sqrt(num_n / den_n) over Ns partials, one workgroup of 256.
-__global__ void __launch_bounds__(256) k_resid(const double2* __restrict__ part, int Ns, double* __restrict__ out) {
+// ---------------------------------------------------- pipelined solve -----
+// Per problem (all of one grid size and precision in a launch):
+//   U [K+1][Ns+1], F [K][Ns+1], G [K+1][Ns+1] modal FP64 states (U(k,0) is
+//   read from U(0,0) = u0 for every k), part [K][Ns], done flags
+//   C(k,n) at k*Ns + n-1 (k = 0..K) and F(k,n) at (K+1)*Ns + k*Ns + n-1.
+// C(k,n): G(U(k,n-1)) -> G(k,n); U(k,n) = G (k = 0) or F(k-1,n) + (G - G(k-1,n)),
+//         needs C(k,n-1), F(k-1,n), C(k-1,n).
+// F(k,n): Fine(U(k,n-1)) -> F(k,n), needs C(k,n-1).
+// A wait that sees no progress for kStallTicks of the constant-rate device
+// clock (100 MHz: 0.5 s) declares a stall: the scheduler's order guarantees
+// progress, so this only fires on a defect, and it ends the launch instead of
+// hanging the device.
+constexpr unsigned long long kStallTicks = 50000000ull;
+
+// Thread 0 waits for *flag != 0 (relaxed polls, then an acquire fence).  On a
+// stall it records (1, job, flag) in diag[0..2] and returns false; it also
+// returns false once another workgroup has recorded one.
+constexpr int kStallPolls = 1 << 21;   // second bound, independent of the clock
+
+__device__ __forceinline__ bool wait_flag(int* flag, int* diag, int job, int flag_index) {
+  const unsigned long long t0 = wall_clock64();
+  int polls = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    if (__hip_atomic_load(diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (wall_clock64() - t0 > kStallTicks || ++polls > kStallPolls) {
+      if (__hip_atomic_fetch_add(diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        __hip_atomic_store(diag + 1, job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(diag + 2, flag_index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  return true;
+}
+
+template <typename T, int NX, int NT, int S>
+__global__ void __launch_bounds__(NT) k_pipeline(const PipeJob* __restrict__ jobs, int njobs,
+                                                 const PipeProb<T>* __restrict__ probs, int* ticket, int* abort,
+                                                 int* progress, const cx<T>* __restrict__ tw,
+                                                 const Basis<T>* __restrict__ basis) {
+  using E_ = Engine<T, NX, NT, S>;
+  extern __shared__ unsigned char smem_raw[];
+  E_ en(smem_raw, tw);
+  __shared__ int s_job, s_ok;
+  const size_t st = size_t(3) * E_::KP;
+  // Thread 0's scheduling work (publish the previous job's flag, take a ticket,
+  // wait on the new job's dependencies) is one region at the top of the body,
+  // between the end-of-job barrier and the hand-out barrier; the body ends
+  // with a barrier and nothing thread-specific.  Thread-0 regions on both
+  // sides of the back-edge would form a single divergent region across it,
+  // which the compiler may turn into a loop the other lanes never leave.  The
+  // exit values are read with readfirstlane so every branch on them is uniform.
+  int done_flag = -1;          // flag of the job this workgroup finished last
+  const PipeProb<T>* done_prob = nullptr;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (done_flag >= 0) {
+        __threadfence();
+        __hip_atomic_store(&done_prob->done[done_flag], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (progress) {
+          progress[2 * blockIdx.x] += 1;
+          progress[2 * blockIdx.x + 1] = done_flag;
+        }
+      }
+      const int jt = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      bool ok = true;
+      if (jt < njobs) {
+        const PipeJob jb = jobs[jt];
+        const PipeProb<T>& p = probs[jb.prob];
+        const int Ns = p.Ns, K = p.K, k = jb.k, n = jb.n;
+        if (n > 1) {
+          const int f = k * Ns + (n - 2);
+          ok = wait_flag(&p.done[f], abort, jt, f);
+        }
+        if (ok && jb.type == 0 && k >= 1) {
+          const int f1 = (K + 1) * Ns + (k - 1) * Ns + (n - 1), f2 = (k - 1) * Ns + (n - 1);
+          ok = wait_flag(&p.done[f1], abort, jt, f1);
+          if (ok) ok = wait_flag(&p.done[f2], abort, jt, f2);
+        }
+      }
+      s_job = jt;
+      s_ok = ok;
+    }
+    __syncthreads();
+    const int j = __builtin_amdgcn_readfirstlane(s_job);
+    const int ok = __builtin_amdgcn_readfirstlane(s_ok);
+    if (j >= njobs || !ok) break;
+    const PipeJob jb = jobs[j];
+    const PipeProb<T>& p = probs[jb.prob];
+    const int Ns = p.Ns, K = p.K, k = jb.k, n = jb.n;
+    auto state = [&](cx<double>* A, int lvl, int slice) { return A + (size_t(lvl) * (Ns + 1) + slice) * st; };
+    const cx<double>* uprev = n == 1 ? state(p.U, 0, 0) : state(p.U, k, n - 1);
+    if (jb.type == 0) {
+      if (k == 0) {
+        coarse_job<T, NX, NT, S>(en, p.ct, basis, uprev, state(p.U, 0, n), state(p.G, 0, n), nullptr, nullptr,
+                                 nullptr, nullptr);
+      } else {
+        coarse_job<T, NX, NT, S>(en, p.ct, basis, uprev, state(p.U, k, n), state(p.G, k, n),
+                                 state(p.G, k - 1, n), state(p.F, k - 1, n), state(p.U, k - 1, n),
+                                 p.part + size_t(k - 1) * Ns + (n - 1));
+      }
+      done_flag = k * Ns + (n - 1);
+    } else {
+      fine_job<T, NX, NT, S>(en, uprev, state(p.F, k, n), p.steps, p.coef64, p.coef, basis);
+      done_flag = (K + 1) * Ns + k * Ns + (n - 1);
+    }
+    done_prob = &p;
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_ints(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// rows r = 0..R-1: out[r] = max_n sqrt(part[r][n].x / part[r][n].y); NaN after an abort.
+__global__ void __launch_bounds__(256) k_resid_rows(const double2* __restrict__ part, int Ns,
+                                                     double* __restrict__ out, const int* __restrict__ abort) {
   __shared__ double red[256];
+  const double2* row = part + size_t(blockIdx.x) * Ns;
   double m = 0.0;
   for (int n = threadIdx.x; n < Ns; n += 256) {
-    const double2 p = part[n];
+    const double2 p = row[n];
     const double r = p.y > 0.0 ? sqrt(p.x / p.y) : (p.x > 0.0 ? INFINITY : 0.0);
     m = (r > m || r != r) ? r : m;
   }
@@ -477,63 +340,57 @@ __global__ void __launch_bounds__(256) k_resid(const double2* __restrict__ part,
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) out[blockIdx.x] = (abort && *abort) ? NAN : red[0];
 }
 
 // ------------------------------------------------------------- launchers ---
-template <int NX> struct Cfg;
-// block sizes: fine -> enough threads to own every retained mode (<= 512);
-// average/coarse -> 256 (N <= 512) or 512, with S samples in flight.
-template <> struct Cfg<64>   { static constexpr int FINE = 64,  AVG = 256; static constexpr int S32 = 16, S64 = 16; };
-template <> struct Cfg<128>  { static constexpr int FINE = 64,  AVG = 256; static constexpr int S32 = 16, S64 = 8; };
-template <> struct Cfg<256>  { static constexpr int FINE = 128, AVG = 256; static constexpr int S32 = 8, S64 = 4; };
-template <> struct Cfg<512>  { static constexpr int FINE = 192, AVG = 256; static constexpr int S32 = 4, S64 = 2; };
-template <> struct Cfg<1024> { static constexpr int FINE = 384, AVG = 512; static constexpr int S32 = 2, S64 = 1; };
-template <> struct Cfg<2048> { static constexpr int FINE = 512, AVG = 512; static constexpr int S32 = 1, S64 = 1; };
-
-template <typename T, int NX> constexpr int samples_in_flight() {
-  return sizeof(T) == 4 ? Cfg<NX>::S32 : Cfg<NX>::S64;
+// Threads per workgroup: the fine batch uses enough threads to own every
+// retained mode (<= 512); the sample-parallel kernels use 1024 (FP32) or 512
+// (FP64) threads with as many state slots as the LDS budget allows.
+template <int NX>
+constexpr int fine_threads() {
+  return NX == 64 ? 64 : NX == 128 ? 64 : NX == 256 ? 128 : NX == 512 ? 192 : NX == 1024 ? 384 : 512;
+}
+template <typename T, int NX>
+constexpr int avg_threads() {
+  return sizeof(T) == 4 ? (NX == 64 ? 512 : 1024) : 512;
 }
 
 // Raise the dynamic-LDS limit for launches above 64 KiB (gfx950 has 160 KiB per
 // workgroup).  Best effort: a launch that still exceeds the limit fails and is
 // reported by the hipGetLastError() that follows it.
 template <typename K>
-static hipError_t prep_lds(K kernel, size_t bytes) {
+static void prep_lds(K kernel, size_t bytes) {
   if (bytes > 65536) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(bytes));
     (void)hipGetLastError();
   }
-  return hipSuccess;
 }
 
 template <int NX>
 static hipError_t to_modal_nx(const double* phys, cx<double>* modal, int batch, const DevTables& t, hipStream_t s) {
-  constexpr int NT = Cfg<NX>::AVG;
-  const size_t lds = 2 * 3 * Geo<NX>::P * sizeof(cx<double>);
-  hipError_t e = prep_lds(k_to_modal<NX, NT>, lds);
-  if (e != hipSuccess) return e;
+  constexpr int NT = 256;
+  const size_t lds = (NX + 6 * Geo<NX>::P) * sizeof(cx<double>);
+  prep_lds(k_to_modal<NX, NT>, lds);
   hipLaunchKernelGGL((k_to_modal<NX, NT>), dim3(batch), dim3(NT), lds, s, phys, modal, t.tw64, t.basis64);
   return hipGetLastError();
 }
 
 template <int NX>
 static hipError_t to_physical_nx(const cx<double>* modal, double* phys, int batch, const DevTables& t, hipStream_t s) {
-  constexpr int NT = Cfg<NX>::AVG;
-  const size_t lds = (3 * (Geo<NX>::P + 1) + 2 * 3 * Geo<NX>::P) * sizeof(cx<double>);
-  hipError_t e = prep_lds(k_to_physical<NX, NT>, lds);
-  if (e != hipSuccess) return e;
+  constexpr int NT = 256;
+  const size_t lds = (NX + 3 * (Geo<NX>::P + 1) + 3 * Geo<NX>::P) * sizeof(cx<double>);
+  prep_lds(k_to_physical<NX, NT>, lds);
   hipLaunchKernelGGL((k_to_physical<NX, NT>), dim3(batch), dim3(NT), lds, s, modal, phys, t.tw64, t.basis64);
   return hipGetLastError();
 }
 
 template <typename T, int NX>
 static hipError_t nonlinear_nx(const cx<double>* in, cx<double>* out, int batch, const DevTables& t, hipStream_t s) {
-  constexpr int NT = Cfg<NX>::FINE;
-  const size_t lds = Lds<T, NX>::bytes(1);
-  hipError_t e = prep_lds(k_nonlinear<T, NX, NT>, lds);
-  if (e != hipSuccess) return e;
+  constexpr int NT = fine_threads<NX>();
+  const size_t lds = Engine<T, NX, NT, 1>::lds_bytes();
+  prep_lds(k_nonlinear<T, NX, NT>, lds);
   hipLaunchKernelGGL((k_nonlinear<T, NX, NT>), dim3(batch), dim3(NT), lds, s, in, out, t.tw<T>(), t.basis<T>());
   return hipGetLastError();
 }
@@ -541,10 +398,9 @@ static hipError_t nonlinear_nx(const cx<double>* in, cx<double>* out, int batch,
 template <typename T, int NX>
 static hipError_t fine_nx(const cx<double>* in, cx<double>* out, int batch, int steps, const cx<double>* coef64,
                           const cx<T>* coef, const DevTables& t, hipStream_t s) {
-  constexpr int NT = Cfg<NX>::FINE;
-  const size_t lds = Lds<T, NX>::bytes(1);
-  hipError_t e = prep_lds(k_fine<T, NX, NT>, lds);
-  if (e != hipSuccess) return e;
+  constexpr int NT = fine_threads<NX>();
+  const size_t lds = Engine<T, NX, NT, 1>::lds_bytes();
+  prep_lds(k_fine<T, NX, NT>, lds);
   hipLaunchKernelGGL((k_fine<T, NX, NT>), dim3(batch), dim3(NT), lds, s, in, out, steps, coef64, coef, t.tw<T>(),
                      t.basis<T>());
   return hipGetLastError();
@@ -553,11 +409,10 @@ static hipError_t fine_nx(const cx<double>* in, cx<double>* out, int batch, int 
 template <typename T, int NX>
 static hipError_t average_nx(const cx<double>* in, cx<double>* out, int batch, const AvgTab<T>& av,
                              const DevTables& t, hipStream_t s) {
-  constexpr int NT = Cfg<NX>::AVG;
-  constexpr int S = samples_in_flight<T, NX>();
-  const size_t lds = Lds<T, NX>::bytes(S);
-  hipError_t e = prep_lds(k_average<T, NX, NT, S>, lds);
-  if (e != hipSuccess) return e;
+  constexpr int NT = avg_threads<T, NX>();
+  constexpr int S = max_slots<T, NX, NT>();
+  const size_t lds = Engine<T, NX, NT, S>::lds_bytes();
+  prep_lds(k_average<T, NX, NT, S>, lds);
   hipLaunchKernelGGL((k_average<T, NX, NT, S>), dim3(batch), dim3(NT), lds, s, in, out, av, t.tw<T>(), t.basis<T>());
   return hipGetLastError();
 }
@@ -565,11 +420,10 @@ static hipError_t average_nx(const cx<double>* in, cx<double>* out, int batch, c
 template <typename T, int NX>
 static hipError_t coarse_nx(const cx<double>* in, cx<double>* out, int batch, const CoarseTab<T>& ct,
                             const DevTables& t, hipStream_t s) {
-  constexpr int NT = Cfg<NX>::AVG;
-  constexpr int S = samples_in_flight<T, NX>();
-  const size_t lds = Lds<T, NX>::bytes(S);
-  hipError_t e = prep_lds(k_coarse<T, NX, NT, S>, lds);
-  if (e != hipSuccess) return e;
+  constexpr int NT = avg_threads<T, NX>();
+  constexpr int S = max_slots<T, NX, NT>();
+  const size_t lds = Engine<T, NX, NT, S>::lds_bytes();
+  prep_lds(k_coarse<T, NX, NT, S>, lds);
   hipLaunchKernelGGL((k_coarse<T, NX, NT, S>), dim3(batch), dim3(NT), lds, s, in, out, ct, t.tw<T>(), t.basis<T>());
   return hipGetLastError();
 }
@@ -577,25 +431,36 @@ static hipError_t coarse_nx(const cx<double>* in, cx<double>* out, int batch, co
 template <typename T, int NX>
 static hipError_t sweep_nx(cx<double>* U, const cx<double>* Fine, cx<double>* Gold, double2* part, int Ns,
                            int initial, const CoarseTab<T>& ct, const DevTables& t, hipStream_t s) {
-  constexpr int NT = Cfg<NX>::AVG;
-  constexpr int S = samples_in_flight<T, NX>();
-  const size_t lds = Lds<T, NX>::bytes(S) + 2 * NT * sizeof(double);
-  hipError_t e = prep_lds(k_sweep<T, NX, NT, S>, lds);
-  if (e != hipSuccess) return e;
+  constexpr int NT = avg_threads<T, NX>();
+  constexpr int S = max_slots<T, NX, NT>();
+  const size_t lds = Engine<T, NX, NT, S>::lds_bytes();
+  prep_lds(k_sweep<T, NX, NT, S>, lds);
   hipLaunchKernelGGL((k_sweep<T, NX, NT, S>), dim3(1), dim3(NT), lds, s, U, Fine, Gold, part, Ns, initial, ct,
                      t.tw<T>(), t.basis<T>());
   return hipGetLastError();
 }
 
-#define AP_DISPATCH_NX(NXV, CALL)                  \
-  switch (NXV) {                                   \
+template <typename T, int NX>
+static hipError_t pipeline_nx(const PipeJob* jobs, int njobs, const void* probs, int* ticket, int* abort,
+                              int* progress, int grid, const DevTables& t, hipStream_t s) {
+  constexpr int NT = avg_threads<T, NX>();
+  constexpr int S = max_slots<T, NX, NT>();
+  const size_t lds = Engine<T, NX, NT, S>::lds_bytes();
+  prep_lds(k_pipeline<T, NX, NT, S>, lds);
+  hipLaunchKernelGGL((k_pipeline<T, NX, NT, S>), dim3(grid), dim3(NT), lds, s, jobs, njobs,
+                     static_cast<const PipeProb<T>*>(probs), ticket, abort, progress, t.tw<T>(), t.basis<T>());
+  return hipGetLastError();
+}
+
+#define AP_DISPATCH_NX(NXV, CALL)                        \
+  switch (NXV) {                                         \
     case 64: { constexpr int NX = 64; return CALL; }     \
     case 128: { constexpr int NX = 128; return CALL; }   \
     case 256: { constexpr int NX = 256; return CALL; }   \
     case 512: { constexpr int NX = 512; return CALL; }   \
     case 1024: { constexpr int NX = 1024; return CALL; } \
     case 2048: { constexpr int NX = 2048; return CALL; } \
-    default: return hipErrorInvalidValue;          \
+    default: return hipErrorInvalidValue;                \
   }
 
 hipError_t launch_to_modal(int nx, const double* phys, cx<double>* modal, int batch, const DevTables& t,
@@ -632,8 +497,21 @@ hipError_t launch_sweep(int nx, cx<double>* U, const cx<double>* Fine, cx<double
   if (c64) AP_DISPATCH_NX(nx, (sweep_nx<double, NX>(U, Fine, Gold, part, Ns, initial, *c64, t, s)));
   AP_DISPATCH_NX(nx, (sweep_nx<float, NX>(U, Fine, Gold, part, Ns, initial, *c32, t, s)));
 }
-hipError_t launch_resid(const double2* part, int Ns, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_resid, dim3(1), dim3(256), 0, s, part, Ns, out);
+hipError_t launch_pipeline(int nx, bool fp64, const void* jobs, int njobs, const void* probs, int* ticket,
+                           int* abort, int* progress, int grid, const DevTables& t, hipStream_t s) {
+  const PipeJob* j = static_cast<const PipeJob*>(jobs);
+  if (fp64) AP_DISPATCH_NX(nx, (pipeline_nx<double, NX>(j, njobs, probs, ticket, abort, progress, grid, t, s)));
+  AP_DISPATCH_NX(nx, (pipeline_nx<float, NX>(j, njobs, probs, ticket, abort, progress, grid, t, s)));
+}
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
+  hipLaunchKernelGGL(k_zero_ints, dim3(blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_resid(const double2* part, int Ns, int rows, double* out, const int* abort, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resid_rows, dim3(rows), dim3(256), 0, s, part, Ns, out, abort);
   return hipGetLastError();
 }
 

@@ -38,6 +38,26 @@ struct CoarseTab {
   T dT;
 };
 
+// Pipelined solve: one job = one coarse step (type 0) or one fine slice
+// (type 1) of problem `prob` at iteration level k for slice n (1-based).
+struct PipeJob {
+  int prob, type, k, n;
+};
+
+// Per-problem device descriptor of the pipelined solve (layout in kernels.hip).
+template <typename T>
+struct PipeProb {
+  cx<double>* U;       // [K+1][Ns+1][3][KP]
+  cx<double>* F;       // [K][Ns+1][3][KP]
+  cx<double>* G;       // [K+1][Ns+1][3][KP]
+  double2* part;       // [K][Ns] residual partial sums
+  int* done;           // [(2K+1) Ns] job flags
+  int Ns, K, steps;
+  const cx<double>* coef64;
+  const cx<T>* coef;
+  CoarseTab<T> ct;
+};
+
 hipError_t launch_to_modal(int nx, const double* phys, cx<double>* modal, int batch, const DevTables& t,
                            hipStream_t s);
 hipError_t launch_to_physical(int nx, const cx<double>* modal, double* phys, int batch, const DevTables& t,
@@ -53,6 +73,10 @@ hipError_t launch_coarse(int nx, const cx<double>* in, cx<double>* out, int batc
 hipError_t launch_sweep(int nx, cx<double>* U, const cx<double>* Fine, cx<double>* Gold, double2* part, int Ns,
                         int initial, const CoarseTab<double>* c64, const CoarseTab<float>* c32,
                         const DevTables& t, hipStream_t s);
-hipError_t launch_resid(const double2* part, int Ns, double* out, hipStream_t s);
+hipError_t launch_pipeline(int nx, bool fp64, const void* jobs, int njobs, const void* probs, int* ticket,
+                           int* abort, int* progress, int grid, const DevTables& t, hipStream_t s);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+// out[r] = max_n sqrt(part[r][n].x / part[r][n].y) for r < rows; NaN if *abort
+hipError_t launch_resid(const double2* part, int Ns, int rows, double* out, const int* abort, hipStream_t s);
 
 }  // namespace ap

@@ -182,6 +182,7 @@ struct Lds {
   static constexpr size_t spec_elems(int S) { return size_t(S) * 3 * (P + 1); }
   static constexpr size_t work_elems(int S) { return size_t(S) * 3 * P; }
   static constexpr size_t bytes(int S) { return (spec_elems(S) + 2 * work_elems(S)) * sizeof(cx<T>); }
+  static constexpr size_t per_state() { return bytes(1); }
 };
 
 // Zero the non-retained tail of every spectrum slot (done once per kernel).
@@ -214,7 +215,7 @@ __device__ __forceinline__ void put_fields(cx<T>* spec, int s, int k, const cx<T
 // Must be entered after a barrier that follows the last put_fields.
 template <typename T, int NX, int NT>
 __device__ __forceinline__ cx<T>* nonlinear_core(cx<T>* spec, cx<T>* a, cx<T>* b, int nstates,
-                                                 const cx<T>* __restrict__ tw) {
+                                                 const cx<T>* tw) {
   using G = Geo<NX>;
   constexpr int P = G::P;
   const int nvec = nstates * 3;

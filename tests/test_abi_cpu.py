@@ -48,3 +48,44 @@ def test_solve_params_layout_matches_header():
     names = [f[0] for f in binding.SolveParams._fields_]
     assert names == ["T", "slices", "K", "dt_fine", "M_avg", "T0", "tol", "precision"]
     assert ctypes.sizeof(binding.SolveParams) == 56
+
+
+def _deps(job, K):
+    t, k, n = job
+    d = []
+    if n > 1:
+        d.append((0, k, n - 1))
+    if t == 0 and k >= 1:
+        d += [(1, k - 1, n), (0, k - 1, n)]
+    return d
+
+
+@pytest.mark.parametrize("Ns,K,steps,M", [(16, 5, 125, 16), (64, 8, 63, 32), (7, 3, 1, 2), (5, 0, 10, 8),
+                                          (256, 10, 40, 64), (3, 9, 1250, 32)])
+def test_pipeline_schedule_is_topological_and_drains(L, Ns, K, steps, M):
+    jobs = binding.pipeline_schedule(Ns, K, steps, M)
+    want = {(0, k, n) for k in range(K + 1) for n in range(1, Ns + 1)} | \
+           {(1, k, n) for k in range(K) for n in range(1, Ns + 1)}
+    assert len(jobs) == len(want) and set(jobs) == want
+    pos = {j: i for i, j in enumerate(jobs)}
+    for j in jobs:
+        for d in _deps(j, K):
+            assert pos[d] < pos[j], (j, d)
+    # ticket scheduling with W workers: each takes the next job and waits for
+    # its dependencies; durations = nonlinear evaluations (coarse 2(M-1), fine 4*steps)
+    dur = {0: 2 * (M - 1), 1: 4 * steps}
+    for W in (1, 3, 256):
+        free = [0.0] * W
+        end = {}
+        for j in jobs:
+            w = min(range(W), key=lambda i: free[i])
+            start = max([free[w]] + [end[d] for d in _deps(j, K)])
+            end[j] = start + dur[j[0]]
+            free[w] = end[j]
+        makespan = max(end.values())
+        serial_bound = sum(dur[j[0]] for j in jobs)
+        assert makespan <= serial_bound + 1e-9
+    # with enough workers the critical path is Ns coarse steps plus K fine slices
+    # (not (K+1) sweeps): the pipelining across iterations
+    crit = Ns * dur[0] + K * max(dur[1], dur[0]) + K * dur[0]
+    assert makespan <= crit + 1e-9, (makespan, crit)

@@ -141,3 +141,30 @@ def test_solve(torch_cuda, cfg, prec, tol):
     # residual history follows the oracle's (FP32 plateaus near its rounding level)
     floor = 1e-13 if prec == FP64 else 1e-6
     assert np.all(np.abs(r - rref) <= 1e-3 * rref + floor), (r, rref)
+
+
+@pytest.mark.parametrize("cfg,prec", [(C1, FP64), (C2, FP32)])
+def test_pipelined_solve_equals_iteration_order_bitwise(torch_cuda, cfg, prec):
+    # tol > 0 runs the iteration-by-iteration sweeps (tol far below reach: all K
+    # iterations); tol <= 0 runs the pipelined persistent launch.  Same bits.
+    torch = torch_cuda
+    u0 = torch.tensor(cfg.initial_state(), device="cuda")
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        Up, rp = ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=prec)
+        Us, rs = ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, tol=1e-300, precision=prec)
+        Up2, rp2 = ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(Up, Us) and torch.equal(rp, rs)
+        assert torch.equal(Up, Up2) and torch.equal(rp, rp2)      # run to run
+
+
+def test_tolerance_stops_early(torch_cuda):
+    torch = torch_cuda
+    cfg = C1
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        U, r = ctx.solve(torch.tensor(cfg.initial_state(), device="cuda"), cfg.T, cfg.slices, cfg.K,
+                         cfg.dt, cfg.Mbar, tol=1e-6, precision=FP64)
+        r = r.cpu().numpy()
+    ran = r[r >= 0]
+    assert 0 < ran.size < cfg.K and ran[-1] <= 1e-6 and np.all(ran[:-1] > 1e-6)
+    assert np.all(r[ran.size:] == -1.0)
