@@ -148,6 +148,14 @@ int aparareal_pipeline_schedule(int slices, int K, int steps, int M_avg, int* ou
  * solve's residuals are NaN.  It does not occur in correct operation.        */
 int aparareal_pipeline_status(ap_ctx* ctx, int* info);
 
+/* Per-job timeline of pipelined solves (diagnostics).  enable = 1 / 0 turns
+ * recording on / off for the following solves (out may be NULL); enable = -1
+ * reads the last solve's record into host `out` [6 * max_jobs]: per job in
+ * hand-out order (type, k, n, start, end, workgroup) with start/end in ticks
+ * of the device's constant-rate clock (100 MHz on MI355X).  Returns the number
+ * of jobs written (reading waits for the solve).                              */
+int aparareal_pipeline_trace(ap_ctx* ctx, int enable, long long* out, int max_jobs);
+
 #ifdef __cplusplus
 }
 #endif

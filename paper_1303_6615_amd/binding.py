@@ -48,6 +48,7 @@ _SIGNATURES = {
     "aparareal_profile": (_i, [_vp, _i]),
     "aparareal_pipeline_schedule": (_i, [_i, _i, _i, _i, ctypes.POINTER(_i)]),
     "aparareal_pipeline_status": (_i, [_vp, ctypes.POINTER(_i)]),
+    "aparareal_pipeline_trace": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), _i]),
     "aparareal_profile_read": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
 }
 
@@ -173,6 +174,16 @@ class Context:
         buf = (ctypes.c_int * 3)()
         _check(lib().aparareal_pipeline_status(self._h, buf))
         return buf[0], buf[1], buf[2]
+
+    def trace(self, enable: bool):
+        """Record per-job device-clock intervals of the following pipelined solves."""
+        _check(lib().aparareal_pipeline_trace(self._h, 1 if enable else 0, None, 0))
+
+    def trace_read(self, max_jobs: int = 1 << 20):
+        """Last solve's jobs: list of (type, k, n, start_tick, end_tick, workgroup)."""
+        buf = (ctypes.c_longlong * (6 * max_jobs))()
+        n = _check(lib().aparareal_pipeline_trace(self._h, -1, buf, max_jobs))
+        return [tuple(buf[6 * i:6 * i + 6]) for i in range(n)]
 
     # -- the parareal solve ----------------------------------------------------
     def solve(self, u0, T: float, slices: int, K: int, dt_fine: float, M: int, T0: float = 0.0,

@@ -2,46 +2,56 @@
 // parareal path (one fine slice; one coarse step with the FP64 correction).
 //
 // LDS layout for S state slots (T = float or double, P = N/2):
-//   tw   [N]            exp(-2 pi i t / N), staged once per kernel when it
-//                       fits next to one state slot (else read from global)
-//   spec [S][3][P+1]    field half spectra (tail k > Kd kept zero)
-//   a, b [S][3][P]      ping-pong FFT buffers (contiguous); they double as the FP64
-//                       reduction scratch [2][NT] between nonlinear evaluations
+//   tw  [N]             exp(-2 pi i t / N), staged once per kernel when it
+//                       fits next to one slot (else read from global memory)
+//   sp  [S][3][P+1]     field half spectra in, forward transforms out
+//   ib  [S][3][P]       inverse transforms (in place); between evaluations it
+//                       also holds per-sample contributions and the FP64
+//                       reduction scratch [2][NT]
+//   y   [3][Kd+1]       the state being averaged (read by every thread)
 #pragma once
 #include "launch.hpp"
-#include "rsw_device.hpp"
+#include "wavefft.hpp"
 
 namespace ap {
 
 constexpr size_t kLdsBudget = 156 * 1024;   // of gfx950's 160 KiB per workgroup
 
 template <typename T, int NX>
+constexpr size_t y_bytes() {
+  return 3 * size_t(Geo<NX>::KP) * sizeof(cx<T>);
+}
+
+template <typename T, int NX>
 constexpr bool twiddles_in_lds() {
-  return NX * sizeof(cx<T>) + Lds<T, NX>::per_state() <= kLdsBudget;
+  return NX * sizeof(cx<T>) + Slot<T, NX>::bytes + y_bytes<T, NX>() <= kLdsBudget;
 }
 
 template <typename T, int NX, int NT>
 constexpr int max_slots() {
-  const size_t fixed = twiddles_in_lds<T, NX>() ? NX * sizeof(cx<T>) : 0;
-  const size_t per = Lds<T, NX>::per_state();
-  const size_t s = (kLdsBudget - fixed) / per;
+  const size_t fixed = (twiddles_in_lds<T, NX>() ? NX * sizeof(cx<T>) : 0) + y_bytes<T, NX>();
+  const size_t s = (kLdsBudget - fixed) / Slot<T, NX>::bytes;
   return s >= 32 ? 32 : (s < 1 ? 1 : int(s));
 }
 
 template <typename T, int NX, int NT, int S>
 struct Engine {
   using G = Geo<NX>;
+  using SL = Slot<T, NX>;
   static constexpr int P = G::P;
   static constexpr int KP = G::KP;
   static constexpr int MPT = (KP + NT - 1) / NT;
   static constexpr bool TW_LDS = twiddles_in_lds<T, NX>();
-  static_assert(2 * Lds<T, NX>::work_elems(S) * sizeof(cx<T>) >= 2 * NT * sizeof(double), "reduction scratch");
-  static constexpr size_t lds_bytes() { return (TW_LDS ? NX * sizeof(cx<T>) : 0) + Lds<T, NX>::bytes(S); }
+  static_assert(NT % 64 == 0, "whole wavefronts");
+  static_assert(SL::ib_elems >= size_t(3) * KP, "per-sample contributions fit a slot's ib");
+  static constexpr size_t lds_bytes() {
+    return (TW_LDS ? NX * sizeof(cx<T>) : 0) + S * SL::bytes + y_bytes<T, NX>();
+  }
   static_assert(lds_bytes() <= 160 * 1024, "LDS budget of gfx950 exceeded");
   const cx<T>* tw;
-  cx<T>* spec;
-  cx<T>* a;
-  cx<T>* b;
+  cx<T>* sp;
+  cx<T>* ib;
+  cx<T>* y;
   double* red;
 
   __device__ __forceinline__ Engine(unsigned char* smem, const cx<T>* __restrict__ tw_global) {
@@ -53,23 +63,42 @@ struct Engine {
     } else {
       tw = tw_global;
     }
-    spec = base;
-    a = spec + Lds<T, NX>::spec_elems(S);
-    b = a + Lds<T, NX>::work_elems(S);
-    red = reinterpret_cast<double*>(a);
-    zero_spec_tail<T, NX, NT>(spec, S);
+    sp = base;
+    ib = sp + S * SL::sp_elems;
+    y = ib + S * SL::ib_elems;
+    red = reinterpret_cast<double*>(ib);
     __syncthreads();
   }
   static __device__ __forceinline__ int mode(int j) { return threadIdx.x + j * NT; }
   static __device__ __forceinline__ bool valid(int j) { return mode(j) < KP; }
-  __device__ __forceinline__ cx<T>* nonlinear(int ns) { return nonlinear_core<T, NX, NT>(spec, a, b, ns, tw); }
+
+  // N of owned-mode modal states x -> n, using slot `slot` (callers alternate
+  // slots between consecutive evaluations when S >= 2).
+  __device__ __forceinline__ void neval(int slot, const cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3],
+                                        const Basis<T> (&bs)[MPT]) {
+    cx<T>* sps = sp + slot * SL::sp_elems;
+    cx<T>* ibs = ib + slot * SL::ib_elems;
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+      if (valid(j)) put_fields<T, NX>(sps, 0, mode(j), x[j], bs[j]);
+    __syncthreads();
+    inverse_fields<T, NX, NT>(sps, ibs, 1, tw);
+    __syncthreads();
+    forward_products<T, NX, NT>(sps, ibs, 1, tw);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+      if (valid(j)) get_N_sp<T, NX>(sps, mode(j), bs[j], tw, n[j]);
+    if constexpr (S == 1) __syncthreads();
+  }
 
   // FP64 block sum of (x, y) over the workgroup; result valid in every thread.
-  // The scratch lives in `a`, so wait for readers of the last FFT result first.
-  __device__ __forceinline__ double2 block_sum2(double x, double y) {
+  // The scratch lives in `ib`, so wait for its last readers first.
+  __device__ __forceinline__ double2 block_sum2(double x, double yv) {
+    static_assert(S * SL::ib_elems * sizeof(cx<T>) >= 2 * NT * sizeof(double), "reduction scratch");
     __syncthreads();
     red[threadIdx.x] = x;
-    red[NT + threadIdx.x] = y;
+    red[NT + threadIdx.x] = yv;
     __syncthreads();
     for (int off = NT / 2; off > 0; off >>= 1) {
       if (threadIdx.x < off) {
@@ -130,15 +159,10 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, const cx<doub
       cf3[j][al] = coef[7 * 3 * KP + o];
     }
   }
+  int slot = 0;
   auto neval = [&](cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3]) {
-#pragma unroll
-    for (int j = 0; j < MPT; ++j)
-      if (E_::valid(j)) put_fields<T, NX>(en.spec, 0, E_::mode(j), x[j], bs[j]);
-    __syncthreads();
-    cx<T>* R = en.nonlinear(1);
-#pragma unroll
-    for (int j = 0; j < MPT; ++j)
-      if (E_::valid(j)) get_N<T, NX>(R, 0, E_::mode(j), bs[j], en.tw, n[j]);
+    en.neval(slot, x, n, bs);
+    if constexpr (S >= 2) slot ^= 1;
   };
   cx<T> Nx[MPT][3], st[MPT][3], E2c[MPT][3], Nu[MPT][3];
   cx<double> acc[MPT][3];
@@ -187,45 +211,59 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, const cx<doub
 }
 
 // ----------------------------------------------------------- time average ---
-// Nbar of the owned-mode state y -> acc, with min(S, M-1) samples in flight.
-// Samples are accumulated in increasing m in every thread (fixed order).
+// Nbar of the owned-mode state y -> acc with min(S, M-1) samples in flight.
+// Per chunk: every thread rotates (sample, mode) items into the slots' field
+// spectra; wavefronts run the inverse transforms and the forward transforms
+// of the products; every thread turns (sample, mode) items back into weighted,
+// rotated modal contributions in the slot's ib; the mode owners then add the
+// chunk's contributions in increasing sample order (a fixed order).
 template <typename T, int NX, int NT, int S>
 __device__ __forceinline__ void nbar_owned(Engine<T, NX, NT, S>& en,
-                                           const cx<T> (&y)[Engine<T, NX, NT, S>::MPT][3],
+                                           const cx<T> (&yv)[Engine<T, NX, NT, S>::MPT][3],
                                            cx<T> (&acc)[Engine<T, NX, NT, S>::MPT][3],
-                                           const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT], const AvgTab<T>& av) {
+                                           const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT], const AvgTab<T>& av,
+                                           const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, S>;
+  using SL = Slot<T, NX>;
   constexpr int KP = E_::KP;
 #pragma unroll
-  for (int j = 0; j < E_::MPT; ++j)
+  for (int j = 0; j < E_::MPT; ++j) {
     for (int al = 0; al < 3; ++al) acc[j][al] = czero<T>();
+    if (E_::valid(j))
+      for (int al = 0; al < 3; ++al) en.y[al * KP + E_::mode(j)] = yv[j][al];
+  }
+  __syncthreads();
   for (int m0 = 1; m0 < av.M; m0 += S) {
     const int ns = min(S, av.M - m0);
-    for (int s = 0; s < ns; ++s) {
-      const cx<T>* rot = av.rot + size_t(m0 + s) * KP;
-#pragma unroll
-      for (int j = 0; j < E_::MPT; ++j) {
-        if (!E_::valid(j)) continue;
-        const int k = E_::mode(j);
-        const cx<T> e = rot[k];
-        cx<T> x[3];
-        for (int al = 0; al < 3; ++al) x[al] = rot_in(y[j][al], e, al);
-        put_fields<T, NX>(en.spec, s, k, x, bs[j]);
-      }
+    for (int i = threadIdx.x; i < ns * KP; i += NT) {
+      const int s = i / KP, k = i - s * KP;
+      const cx<T> e = av.rot[size_t(m0 + s) * KP + k];
+      cx<T> x[3];
+      for (int al = 0; al < 3; ++al) x[al] = rot_in(en.y[al * KP + k], e, al);
+      put_fields<T, NX>(en.sp, s, k, x, basis[k]);
     }
     __syncthreads();
-    cx<T>* R = en.nonlinear(ns);
-    for (int s = 0; s < ns; ++s) {
-      const cx<T>* rot = av.rot + size_t(m0 + s) * KP;
+    inverse_fields<T, NX, NT>(en.sp, en.ib, ns, en.tw);
+    __syncthreads();
+    forward_products<T, NX, NT>(en.sp, en.ib, ns, en.tw);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ns * KP; i += NT) {
+      const int s = i / KP, k = i - s * KP;
+      const cx<T> e = av.rot[size_t(m0 + s) * KP + k];
       const T wm = av.w[m0 + s];
+      cx<T> n[3];
+      get_N_sp<T, NX>(en.sp + s * SL::sp_elems, k, basis[k], en.tw, n);
+      cx<T>* c = en.ib + s * SL::ib_elems;
+      for (int al = 0; al < 3; ++al) c[al * KP + k] = wm * rot_out(n[al], e, al);
+    }
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E_::MPT; ++j) {
-        if (!E_::valid(j)) continue;
-        const int k = E_::mode(j);
-        const cx<T> e = rot[k];
-        cx<T> n[3];
-        get_N<T, NX>(R, s, k, bs[j], en.tw, n);
-        for (int al = 0; al < 3; ++al) acc[j][al] = acc[j][al] + wm * rot_out(n[al], e, al);
+    for (int j = 0; j < E_::MPT; ++j) {
+      if (!E_::valid(j)) continue;
+      const int k = E_::mode(j);
+      for (int s = 0; s < ns; ++s) {
+        const cx<T>* c = en.ib + s * SL::ib_elems;
+        for (int al = 0; al < 3; ++al) acc[j][al] = acc[j][al] + c[al * KP + k];
       }
     }
   }
@@ -237,7 +275,7 @@ __device__ __forceinline__ void coarse_owned(Engine<T, NX, NT, S>& en,
                                              const cx<T> (&u)[Engine<T, NX, NT, S>::MPT][3],
                                              cx<T> (&g)[Engine<T, NX, NT, S>::MPT][3],
                                              const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT],
-                                             const CoarseTab<T>& ct) {
+                                             const CoarseTab<T>& ct, const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, S>;
   constexpr int MPT = E_::MPT;
   cx<T> w[MPT][3], y[MPT][3], kk[MPT][3];
@@ -250,12 +288,12 @@ __device__ __forceinline__ void coarse_owned(Engine<T, NX, NT, S>& en,
     rT[j] = ct.rotT[k];
     for (int al = 0; al < 3; ++al) w[j][al] = hd[j] * u[j][al];
   }
-  nbar_owned<T, NX, NT, S>(en, w, kk, bs, ct.avg);
+  nbar_owned<T, NX, NT, S>(en, w, kk, bs, ct.avg, basis);
   const T half = T(0.5) * ct.dT;
 #pragma unroll
   for (int j = 0; j < MPT; ++j)
     for (int al = 0; al < 3; ++al) y[j][al] = w[j][al] + half * kk[j][al];
-  nbar_owned<T, NX, NT, S>(en, y, kk, bs, ct.avg);
+  nbar_owned<T, NX, NT, S>(en, y, kk, bs, ct.avg, basis);
 #pragma unroll
   for (int j = 0; j < MPT; ++j)
     for (int al = 0; al < 3; ++al) {
@@ -288,7 +326,7 @@ __device__ __forceinline__ void coarse_job(Engine<T, NX, NT, S>& en, const Coars
     bs[j] = basis[k];
     for (int al = 0; al < 3; ++al) u[j][al] = E_::valid(j) ? cvt<T>(uprev[al * KP + k]) : czero<T>();
   }
-  coarse_owned<T, NX, NT, S>(en, u, g, bs, ct);
+  coarse_owned<T, NX, NT, S>(en, u, g, bs, ct, basis);
   double num = 0.0, den = 0.0;
 #pragma unroll
   for (int j = 0; j < MPT; ++j) {

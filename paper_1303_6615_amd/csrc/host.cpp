@@ -152,6 +152,9 @@ struct ap_ctx {
   std::vector<ap::PipeJob> pp_jobs_host;
   std::vector<unsigned char> pp_prob_host;
   int* pp_diag = nullptr;   // stall record of the last pipelined launch
+  bool trace_on = false;     // record per-job device-clock intervals
+  DevBuf pp_trace;
+  int pp_trace_jobs = 0;
   hipStream_t last_stream = nullptr;
   bool has_last = false;
   // kernel timing (aparareal_profile)
@@ -503,9 +506,16 @@ int solve_pipelined(ap_ctx* c, const double* u0, const ap_solve_params* p, doubl
   if ((e = ap::launch_zero_ints(flags, nflags, s)) != hipSuccess) return hip_fail(e, "flag reset");
   c->pp_diag = abort;
   const int grid = std::min(c->pp_njobs, 256);
+  unsigned long long* trace = nullptr;
+  if (c->trace_on) {
+    if ((e = ensure(c, c->pp_trace, sizeof(unsigned long long) * 3 * size_t(c->pp_njobs))) != hipSuccess)
+      return hip_fail(e, "trace buffer");
+    trace = c->pp_trace.as<unsigned long long>();
+    c->pp_trace_jobs = c->pp_njobs;
+  }
   e = timed(c, AP_K_PIPELINE, s, [&] {
-    return ap::launch_pipeline(c->N, f64, c->pp_jobs.p, c->pp_njobs, c->pp_prob.p, ticket, abort, abort + 3, grid,
-                               c->tabs, s);
+    return ap::launch_pipeline(c->N, f64, c->pp_jobs.p, c->pp_njobs, c->pp_prob.p, ticket, abort, abort + 3, trace,
+                               grid, c->tabs, s);
   });
   if (e != hipSuccess) return hip_fail(e, "pipeline launch");
   if (K > 0) {
@@ -710,6 +720,32 @@ int aparareal_pipeline_schedule(int slices, int K, int steps, int M_avg, int* ou
     out[3 * i + 2] = jobs[i].n;
   }
   return int(jobs.size());
+}
+
+int aparareal_pipeline_trace(ap_ctx* c, int enable, long long* out, int max_jobs) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (enable >= 0) {
+    c->trace_on = enable != 0;
+    return AP_OK;
+  }
+  if (!out || max_jobs < 0) return fail(AP_EINVAL, "bad trace query");
+  if (!c->pp_trace.p || c->pp_trace_jobs == 0) return 0;
+  const int n = std::min(max_jobs, c->pp_trace_jobs);
+  std::vector<unsigned long long> raw(size_t(3) * n);
+  hipError_t e = c->has_last ? hipStreamSynchronize(c->last_stream) : hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(raw.data(), c->pp_trace.p, raw.size() * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "trace readback");
+  for (int i = 0; i < n; ++i) {
+    out[6 * i + 0] = c->pp_jobs_host[i].type;
+    out[6 * i + 1] = c->pp_jobs_host[i].k;
+    out[6 * i + 2] = c->pp_jobs_host[i].n;
+    out[6 * i + 3] = (long long)raw[3 * i];
+    out[6 * i + 4] = (long long)raw[3 * i + 1];
+    out[6 * i + 5] = (long long)raw[3 * i + 2];
+  }
+  return n;
 }
 
 int aparareal_profile(ap_ctx* c, int enable) {

@@ -21,6 +21,15 @@
 
 namespace ap {
 
+template <int NX>
+constexpr int fine_threads() {
+  return NX <= 512 ? 192 : NX == 1024 ? 384 : 704;
+}
+// two slots (alternating evaluations) when they fit
+template <typename T, int NX, int NT>
+constexpr int fine_slots() {
+  return max_slots<T, NX, NT>() >= 2 ? 2 : 1;
+}
 // ------------------------------------------------- boundary transforms -----
 // physical [B][3][N] float64 -> modal [B][3][KP] complex float64 (projected)
 template <int NX, int NT>
@@ -112,24 +121,19 @@ __global__ void __launch_bounds__(NT) k_nonlinear(const cx<double>* __restrict__
   E_ en(smem_raw, tw);
   const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * E_::KP;
   cx<double>* dst = Nout + size_t(blockIdx.x) * 3 * E_::KP;
+  cx<T> c[E_::MPT][3], n[E_::MPT][3];
+  Basis<T> bs[E_::MPT];
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j) {
-    if (!E_::valid(j)) continue;
-    const int k = E_::mode(j);
-    cx<T> c[3];
-    for (int al = 0; al < 3; ++al) c[al] = cvt<T>(src[al * E_::KP + k]);
-    put_fields<T, NX>(en.spec, 0, k, c, basis[k]);
+    const int k = E_::valid(j) ? E_::mode(j) : 0;
+    bs[j] = basis[k];
+    for (int al = 0; al < 3; ++al) c[j][al] = E_::valid(j) ? cvt<T>(src[al * E_::KP + k]) : czero<T>();
   }
-  __syncthreads();
-  cx<T>* R = en.nonlinear(1);
+  en.neval(0, c, n, bs);
 #pragma unroll
-  for (int j = 0; j < E_::MPT; ++j) {
-    if (!E_::valid(j)) continue;
-    const int k = E_::mode(j);
-    cx<T> n[3];
-    get_N<T, NX>(R, 0, k, basis[k], en.tw, n);
-    for (int al = 0; al < 3; ++al) dst[al * E_::KP + k] = cvt<double>(n[al]);
-  }
+  for (int j = 0; j < E_::MPT; ++j)
+    if (E_::valid(j))
+      for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = cvt<double>(n[j][al]);
 }
 
 // ------------------------------------------------------------ fine batch ---
@@ -138,11 +142,12 @@ __global__ void __launch_bounds__(NT) k_fine(const cx<double>* __restrict__ Uin,
                                              int steps, const cx<double>* __restrict__ coef64,
                                              const cx<T>* __restrict__ coef, const cx<T>* __restrict__ tw,
                                              const Basis<T>* __restrict__ basis) {
-  using E_ = Engine<T, NX, NT, 1>;
+  using E_ = Engine<T, NX, NT, fine_slots<T, NX, NT>()>;
   extern __shared__ unsigned char smem_raw[];
   E_ en(smem_raw, tw);
   const size_t st = size_t(3) * E_::KP;
-  fine_job<T, NX, NT, 1>(en, Uin + blockIdx.x * st, Uout + blockIdx.x * st, steps, coef64, coef, basis);
+  fine_job<T, NX, NT, fine_slots<T, NX, NT>()>(en, Uin + blockIdx.x * st, Uout + blockIdx.x * st, steps, coef64,
+                                                 coef, basis);
 }
 
 // ---------------------------------------------------- average and coarse ---
@@ -163,7 +168,7 @@ __global__ void __launch_bounds__(NT) k_average(const cx<double>* __restrict__ U
     bs[j] = basis[k];
     for (int al = 0; al < 3; ++al) y[j][al] = E_::valid(j) ? cvt<T>(src[al * E_::KP + k]) : czero<T>();
   }
-  nbar_owned<T, NX, NT, S>(en, y, acc, bs, av);
+  nbar_owned<T, NX, NT, S>(en, y, acc, bs, av, basis);
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j)
     if (E_::valid(j))
@@ -243,8 +248,8 @@ __device__ __forceinline__ bool wait_flag(int* flag, int* diag, int job, int fla
 template <typename T, int NX, int NT, int S>
 __global__ void __launch_bounds__(NT) k_pipeline(const PipeJob* __restrict__ jobs, int njobs,
                                                  const PipeProb<T>* __restrict__ probs, int* ticket, int* abort,
-                                                 int* progress, const cx<T>* __restrict__ tw,
-                                                 const Basis<T>* __restrict__ basis) {
+                                                 int* progress, unsigned long long* trace,
+                                                 const cx<T>* __restrict__ tw, const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, S>;
   extern __shared__ unsigned char smem_raw[];
   E_ en(smem_raw, tw);
@@ -292,6 +297,10 @@ __global__ void __launch_bounds__(NT) k_pipeline(const PipeJob* __restrict__ job
     const int j = __builtin_amdgcn_readfirstlane(s_job);
     const int ok = __builtin_amdgcn_readfirstlane(s_ok);
     if (j >= njobs || !ok) break;
+    if (trace && threadIdx.x == 0) {
+      trace[3 * j] = wall_clock64();
+      trace[3 * j + 2] = blockIdx.x;
+    }
     const PipeJob jb = jobs[j];
     const PipeProb<T>& p = probs[jb.prob];
     const int Ns = p.Ns, K = p.K, k = jb.k, n = jb.n;
@@ -313,6 +322,7 @@ __global__ void __launch_bounds__(NT) k_pipeline(const PipeJob* __restrict__ job
     }
     done_prob = &p;
     __syncthreads();
+    if (trace && threadIdx.x == 0) trace[3 * j + 1] = wall_clock64();
   }
 }
 
@@ -344,16 +354,15 @@ __global__ void __launch_bounds__(256) k_resid_rows(const double2* __restrict__ 
 }
 
 // ------------------------------------------------------------- launchers ---
-// Threads per workgroup: the fine batch uses enough threads to own every
-// retained mode (<= 512); the sample-parallel kernels use 1024 (FP32) or 512
-// (FP64) threads with as many state slots as the LDS budget allows.
-template <int NX>
-constexpr int fine_threads() {
-  return NX == 64 ? 64 : NX == 128 ? 64 : NX == 256 ? 128 : NX == 512 ? 192 : NX == 1024 ? 384 : 512;
-}
+// Threads per workgroup: the fine batch uses three wavefronts (one per field
+// transform) or enough threads to own every retained mode; the
+// sample-parallel kernels use 512 threads with as many state slots as the
+// LDS budget allows.
+// 512 threads: eight wavefronts with up to 256 VGPRs each (the jobs keep the
+// ETDRK4 state, coefficients and a register DFT live at once).
 template <typename T, int NX>
 constexpr int avg_threads() {
-  return sizeof(T) == 4 ? (NX == 64 ? 512 : 1024) : 512;
+  return 512;
 }
 
 // Raise the dynamic-LDS limit for launches above 64 KiB (gfx950 has 160 KiB per
@@ -399,7 +408,7 @@ template <typename T, int NX>
 static hipError_t fine_nx(const cx<double>* in, cx<double>* out, int batch, int steps, const cx<double>* coef64,
                           const cx<T>* coef, const DevTables& t, hipStream_t s) {
   constexpr int NT = fine_threads<NX>();
-  const size_t lds = Engine<T, NX, NT, 1>::lds_bytes();
+  const size_t lds = Engine<T, NX, NT, fine_slots<T, NX, NT>()>::lds_bytes();
   prep_lds(k_fine<T, NX, NT>, lds);
   hipLaunchKernelGGL((k_fine<T, NX, NT>), dim3(batch), dim3(NT), lds, s, in, out, steps, coef64, coef, t.tw<T>(),
                      t.basis<T>());
@@ -442,13 +451,15 @@ static hipError_t sweep_nx(cx<double>* U, const cx<double>* Fine, cx<double>* Go
 
 template <typename T, int NX>
 static hipError_t pipeline_nx(const PipeJob* jobs, int njobs, const void* probs, int* ticket, int* abort,
-                              int* progress, int grid, const DevTables& t, hipStream_t s) {
+                              int* progress, unsigned long long* trace, int grid, const DevTables& t,
+                              hipStream_t s) {
   constexpr int NT = avg_threads<T, NX>();
   constexpr int S = max_slots<T, NX, NT>();
   const size_t lds = Engine<T, NX, NT, S>::lds_bytes();
   prep_lds(k_pipeline<T, NX, NT, S>, lds);
   hipLaunchKernelGGL((k_pipeline<T, NX, NT, S>), dim3(grid), dim3(NT), lds, s, jobs, njobs,
-                     static_cast<const PipeProb<T>*>(probs), ticket, abort, progress, t.tw<T>(), t.basis<T>());
+                     static_cast<const PipeProb<T>*>(probs), ticket, abort, progress, trace, t.tw<T>(),
+                     t.basis<T>());
   return hipGetLastError();
 }
 
@@ -498,10 +509,12 @@ hipError_t launch_sweep(int nx, cx<double>* U, const cx<double>* Fine, cx<double
   AP_DISPATCH_NX(nx, (sweep_nx<float, NX>(U, Fine, Gold, part, Ns, initial, *c32, t, s)));
 }
 hipError_t launch_pipeline(int nx, bool fp64, const void* jobs, int njobs, const void* probs, int* ticket,
-                           int* abort, int* progress, int grid, const DevTables& t, hipStream_t s) {
+                           int* abort, int* progress, unsigned long long* trace, int grid, const DevTables& t,
+                           hipStream_t s) {
   const PipeJob* j = static_cast<const PipeJob*>(jobs);
-  if (fp64) AP_DISPATCH_NX(nx, (pipeline_nx<double, NX>(j, njobs, probs, ticket, abort, progress, grid, t, s)));
-  AP_DISPATCH_NX(nx, (pipeline_nx<float, NX>(j, njobs, probs, ticket, abort, progress, grid, t, s)));
+  if (fp64)
+    AP_DISPATCH_NX(nx, (pipeline_nx<double, NX>(j, njobs, probs, ticket, abort, progress, trace, grid, t, s)));
+  AP_DISPATCH_NX(nx, (pipeline_nx<float, NX>(j, njobs, probs, ticket, abort, progress, trace, grid, t, s)));
 }
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

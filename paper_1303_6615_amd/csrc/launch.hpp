@@ -74,7 +74,8 @@ hipError_t launch_sweep(int nx, cx<double>* U, const cx<double>* Fine, cx<double
                         int initial, const CoarseTab<double>* c64, const CoarseTab<float>* c32,
                         const DevTables& t, hipStream_t s);
 hipError_t launch_pipeline(int nx, bool fp64, const void* jobs, int njobs, const void* probs, int* ticket,
-                           int* abort, int* progress, int grid, const DevTables& t, hipStream_t s);
+                           int* abort, int* progress, unsigned long long* trace, int grid, const DevTables& t,
+                           hipStream_t s);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 // out[r] = max_n sqrt(part[r][n].x / part[r][n].y) for r < rows; NaN if *abort
 hipError_t launch_resid(const double2* part, int Ns, int rows, double* out, const int* abort, hipStream_t s);

@@ -1,0 +1,242 @@
+// Wave-local FFTs and the fused nonlinear evaluation on top of them.
+//
+// A group of G lanes of one wavefront (G = 8..64 by length) transforms one real
+// signal of length N through a complex FFT of length P = N/2, with in-place
+// Stockham passes of radix 4, 8 or 16 in LDS: every lane loads its
+// butterflies' inputs, computes a register DFT, and after a wavefront-level
+// synchronisation stores the outputs at their auto-sorted positions.  No
+// workgroup barrier is needed inside a transform; 64/G signals share a
+// wavefront and the wavefronts of a workgroup work on further signals.
+//
+// The real-signal pre/post-processing is fused into the first and last data
+// movement: the first inverse pass forms Z[k] = (X[k] + conj X[P-k])
+//   + i e^{2 pi i k/N} (X[k] - conj X[P-k]) from the half spectrum on the fly,
+// and the first forward pass forms the quadratic products (v1^2/2, v1 v2x,
+// h v1) of the inverse outputs on the fly.
+#pragma once
+#include "rsw_device.hpp"
+
+namespace ap {
+
+// Orders LDS accesses of one wavefront: the hardware executes a wavefront's
+// LDS instructions in order; this keeps the compiler from reordering them.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// cos(2 pi j / 16), j = 0..15 (sin(2 pi j/16) = cos(2 pi (j+12)/16))
+constexpr double kCos16[16] = {1.0,
+                               0.92387953251128675613,
+                               0.70710678118654752440,
+                               0.38268343236508977173,
+                               0.0,
+                               -0.38268343236508977173,
+                               -0.70710678118654752440,
+                               -0.92387953251128675613,
+                               -1.0,
+                               -0.92387953251128675613,
+                               -0.70710678118654752440,
+                               -0.38268343236508977173,
+                               0.0,
+                               0.38268343236508977173,
+                               0.70710678118654752440,
+                               0.92387953251128675613};
+
+// Register DFT y_q = sum_p x_p exp(DIR 2 pi i p q / R), R a power of two <= 16,
+// radix-2 decimation in time with compile-time twiddles.
+template <typename T, int R, int DIR, int K>
+__device__ __forceinline__ void dft_combine(cx<T> (&x)[R], const cx<T> (&e)[R / 2], const cx<T> (&o)[R / 2]) {
+  if constexpr (K < R / 2) {
+    cx<T> t;
+    if constexpr (K == 0) {
+      t = o[0];
+    } else if constexpr (4 * K == R) {
+      t = DIR > 0 ? mul_i(o[K]) : mul_mi(o[K]);
+    } else {
+      constexpr int j = K * 16 / R;
+      const cx<T> w{T(kCos16[j]), T(DIR > 0 ? kCos16[(j + 12) % 16] : -kCos16[(j + 12) % 16])};
+      t = w * o[K];
+    }
+    x[K] = e[K] + t;
+    x[K + R / 2] = e[K] - t;
+    dft_combine<T, R, DIR, K + 1>(x, e, o);
+  }
+}
+
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft_reg(cx<T> (&x)[R]) {
+  if constexpr (R == 2) {
+    const cx<T> a = x[0] + x[1], b = x[0] - x[1];
+    x[0] = a;
+    x[1] = b;
+  } else {
+    cx<T> e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = x[2 * i];
+      o[i] = x[2 * i + 1];
+    }
+    dft_reg<T, R / 2, DIR>(e);
+    dft_reg<T, R / 2, DIR>(o);
+    dft_combine<T, R, DIR, 0>(x, e, o);
+  }
+}
+
+// Plan per transform length: G lanes per signal (64/G signals share a
+// wavefront) and radices R0, R1[, R2] with product P, chosen so that every
+// pass has about G butterflies.
+template <int P> struct WavePlan;
+template <> struct WavePlan<32>   { static constexpr int G = 8,  n = 2, r0 = 4,  r1 = 8, r2 = 1; };
+template <> struct WavePlan<64>   { static constexpr int G = 16, n = 3, r0 = 4,  r1 = 4, r2 = 4; };
+template <> struct WavePlan<128>  { static constexpr int G = 32, n = 3, r0 = 4,  r1 = 4, r2 = 8; };
+template <> struct WavePlan<256>  { static constexpr int G = 64, n = 3, r0 = 4,  r1 = 8, r2 = 8; };
+template <> struct WavePlan<512>  { static constexpr int G = 64, n = 3, r0 = 8,  r1 = 8, r2 = 8; };
+template <> struct WavePlan<1024> { static constexpr int G = 64, n = 3, r0 = 16, r1 = 8, r2 = 8; };
+
+// One in-place Stockham pass of radix R after NS points have been combined,
+// by the G lanes of one signal group: butterfly b (b = lig, lig + G, ...)
+// reads positions b + q P/R (through `load` on the first pass), twiddles by
+// exp(DIR 2 pi i q k / (NS R)), k = b mod NS, and writes (b - k) R + k + q NS.
+// tw[t] = exp(-2 pi i t / (2P)).  Every lane of the wavefront executes the
+// synchronisations; lanes of an inactive group skip loads and stores.
+template <typename T, int P, int R, int NS, int DIR, int G, typename Load>
+__device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, int lig, bool active, Load&& load) {
+  constexpr int NB = P / R;
+  constexpr int BPL = (NB + G - 1) / G;
+  cx<T> x[BPL][R];
+#pragma unroll
+  for (int i = 0; i < BPL; ++i) {
+    const int b = lig + G * i;
+    if (active && (NB % G == 0 || b < NB)) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[i][q] = load(b + q * NB);
+      if constexpr (NS > 1) {
+        const int k = b & (NS - 1);
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          cx<T> w = tw[2 * (q * k * (P / (NS * R)))];
+          if (DIR > 0) w = conj(w);
+          x[i][q] = x[i][q] * w;
+        }
+      }
+      dft_reg<T, R, DIR>(x[i]);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < BPL; ++i) {
+    const int b = lig + G * i;
+    if (active && (NB % G == 0 || b < NB)) {
+      const int k = b & (NS - 1);
+      cx<T>* d = buf + (b - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) d[q * NS] = x[i][q];
+    }
+  }
+  wave_sync();
+}
+
+// Unnormalised complex FFT of length P by one lane group, result in `buf`
+// (natural order); the first pass reads its inputs through load(index).
+template <typename T, int P, int DIR, typename Load>
+__device__ __forceinline__ void wave_fft(cx<T>* buf, const cx<T>* tw, int lig, bool active, Load&& load) {
+  using PL = WavePlan<P>;
+  auto self = [buf](int i) { return buf[i]; };
+  wave_pass<T, P, PL::r0, 1, DIR, PL::G>(buf, tw, lig, active, load);
+  wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G>(buf, tw, lig, active, self);
+  if constexpr (PL::n == 3) wave_pass<T, P, PL::r2, PL::r0 * PL::r1, DIR, PL::G>(buf, tw, lig, active, self);
+}
+
+// LDS per state slot: SP [3][P+1] (half spectra in; forward transforms out)
+// and IB [3][P] (inverse transforms, in place).
+template <typename T, int NX>
+struct Slot {
+  static constexpr int P = Geo<NX>::P;
+  static constexpr size_t sp_elems = 3 * (P + 1);
+  static constexpr size_t ib_elems = 3 * P;
+  static constexpr size_t bytes = (sp_elems + ib_elems) * sizeof(cx<T>);
+};
+
+// Inverse transforms of the 3*ns field spectra in SP (k <= Kd written, the
+// rest read as zero) into IB, one signal per lane group at a time.
+template <typename T, int NX, int NT>
+__device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, const cx<T>* tw) {
+  using G_ = Geo<NX>;
+  constexpr int P = G_::P;
+  constexpr int G = WavePlan<P>::G;
+  constexpr int SPW = 64 / G;             // signals per wavefront
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63;
+  const int group = lane / G, lig = lane - group * G;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nsig = 3 * ns;
+  for (int v0 = wave * SPW; v0 < nsig; v0 += NW * SPW) {
+    const int v = v0 + group;
+    const bool active = v < nsig;
+    const cx<T>* X = sp + (active ? v : 0) * (P + 1);
+    auto load = [X, tw](int idx) {
+      const cx<T> xk = idx <= G_::KD ? X[idx] : czero<T>();
+      const int ic = P - idx;
+      const cx<T> xc = ic <= G_::KD ? conj(X[ic]) : czero<T>();
+      return (xk + xc) + mul_i(conj(tw[idx]) * (xk - xc));
+    };
+    wave_fft<T, P, +1>(ib + (active ? v : 0) * P, tw, lig, active, load);
+  }
+}
+
+// Forward transforms of the packed products of each state's inverse outputs,
+// written into SP (stride P+1).
+template <typename T, int NX, int NT>
+__device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int ns, const cx<T>* tw) {
+  constexpr int P = Geo<NX>::P;
+  constexpr int G = WavePlan<P>::G;
+  constexpr int SPW = 64 / G;
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63;
+  const int group = lane / G, lig = lane - group * G;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nsig = 3 * ns;
+  for (int v0 = wave * SPW; v0 < nsig; v0 += NW * SPW) {
+    const int v = v0 + group;
+    const bool active = v < nsig;
+    const int vv = active ? v : 0;
+    const int s = vv / 3, f = vv - 3 * s;
+    const cx<T>* V1 = ib + (3 * s) * P;
+    const cx<T>* W = ib + (3 * s + (f == 2 ? 2 : 1)) * P;
+    auto load = [V1, W, f](int idx) {
+      const cx<T> v1 = V1[idx];
+      if (f == 0) return cx<T>{T(0.5) * v1.x * v1.x, T(0.5) * v1.y * v1.y};
+      const cx<T> w = W[idx];
+      return cx<T>{v1.x * w.x, v1.y * w.y};
+    };
+    wave_fft<T, P, -1>(sp + vv * (P + 1), tw, lig, active, load);
+  }
+}
+
+// Modal N amplitudes of retained mode k from the forward transforms of one
+// slot's products (SP base of the slot, stride P+1).
+template <typename T, int NX>
+__device__ __forceinline__ void get_N_sp(const cx<T>* sp_slot, int k, Basis<T> bs, const cx<T>* tw, cx<T> out[3]) {
+  using G = Geo<NX>;
+  constexpr int P = G::P;
+  const T half_over_n = T(0.5) / T(G::N);
+  const cx<T> w = tw[k];
+  const int kc = (P - k) & (P - 1);
+  cx<T> Pf[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const cx<T>* Z = sp_slot + f * (P + 1);
+    const cx<T> zk = Z[k];
+    const cx<T> zc = conj(Z[kc]);
+    Pf[f] = half_over_n * ((zk + zc) - mul_i(w * (zk - zc)));
+  }
+  const T kk = T(k);
+  const cx<T> n1 = (-kk) * mul_i(Pf[0]);
+  const cx<T> n2 = T(-1) * Pf[1];
+  const cx<T> n3 = (-kk) * mul_i(Pf[2]);
+  fields_to_modal<T>(n1, n2, n3, bs, out);
+}
+
+}  // namespace ap
