@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB three times (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -57,8 +60,54 @@ def cpu_baseline(cfg):
             "sample": f"one full parareal solve of {cfg.name} (numpy FP64, single thread)"}
 
 
+def kernel_source_hash():
+    """sha256 over the kernel sources and build flags (identifies the kernels that
+    a stored counter measurement belongs to)."""
+    import hashlib
+    h = hashlib.sha256()
+    cs = os.path.join(ROOT, "paper_1303_6615_amd", "csrc")
+    for f in sorted(os.listdir(cs)):
+        h.update(f.encode())
+        with open(os.path.join(cs, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1303_6615_amd", "build.py"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (scaled by a plain copy), or None when there is no
+    measurement for this workload or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic-{workload_name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["traffic_bytes"]
+
+
+def copy_probe(mib):
+    """Three plain device-to-device copies of `mib` MiB: each dispatch reads and
+    writes exactly mib * 1024 KiB, the yardstick for the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_kib_per_dispatch": mib * 1024, "dispatches": 3}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_mib:
+        copy_probe(args.copy_mib)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the parallel-in-time "
               "dimension is the batch dimension of the single-GPU kernels.", file=sys.stderr)
@@ -126,7 +175,7 @@ def main():
         kernel_names = {k: v.replace("float", "double") for k, v in kernel_names.items()}
     peak = metrics.PEAK_FP32_TFLOPS if cfg.precision == 0 else metrics.PEAK_FP64_TFLOPS
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 6), "traffic": None,
+                "frac": round(achieved / peak, 6), "traffic": measured_traffic(cfg.name),
                 "kernel": kernel_names[dominant], "flops_per_launch": flops[dominant],
                 "avg_launch_ms": round(avg_s * 1e3, 5)}
     line = {

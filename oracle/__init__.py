@@ -22,7 +22,7 @@ What each module follows:
   model      the paper's speedup estimate (eq. speedup upper bound)
 
 Readings taken where the paper is silent, garbled or self-inconsistent are
-listed in the docstrings where they are used, and collected in the design doc.
+listed in the docstrings where they are used.
 Every function here is pinned by a CPU test against something other than
 itself (closed forms, brute force, library routines, invariants).
 """
