@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the schedule autotuner (analytic job durations, default mapping)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -116,7 +118,7 @@ def main():
     import torch
 
     from paper_1303_6615_amd import metrics
-    from paper_1303_6615_amd.binding import Context
+    from paper_1303_6615_amd.binding import Context, autotune
     from paper_1303_6615_amd.inputs import C1, C2, C3
 
     cfg = {"c1": C1, "c2": C2, "c3": C3}[args.workload]
@@ -130,6 +132,11 @@ def main():
         ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=cfg.precision,
                   out=out, resid=resid)
 
+    tuned_ms = None
+    if not args.no_autotune:
+        # untimed: measures job durations on the device and picks the mapping
+        tuned_ms = autotune([(ctx, u0, dict(T=cfg.T, slices=cfg.slices, K=cfg.K, dt_fine=cfg.dt, M=cfg.Mbar))],
+                            precision=cfg.precision)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -199,6 +206,8 @@ def main():
         "roofline": roofline,
         "kernels": kern,
         "final_residual": float(r[-1]) if r.size else None,
+        "autotune": None if tuned_ms is None else {"best_ms": round(tuned_ms, 4),
+                                                   "split_coarse": ctx.get_option(0)},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)

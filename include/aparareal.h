@@ -112,6 +112,50 @@ typedef struct {
 int aparareal_solve(ap_ctx* ctx, const double* u0, const ap_solve_params* params,
                     double* U_out, double* resid, void* stream);
 
+/* Many independent problems in one persistent launch (the slices of every
+ * problem are the batch of one launch; Alg. 4 per problem).  Each item names
+ * its own context (grid size, eps, F, nu; a context may appear only once),
+ * initial state, parameters (tol <= 0: exactly K iterations; the precision
+ * must be the same for all items) and outputs, with the meaning and layout of
+ * aparareal_solve.  Each problem's results equal those of aparareal_solve on
+ * its own.  The first item's context holds the launch's job list and
+ * counters; every context keeps its problem's states.                       */
+typedef struct {
+  ap_ctx* ctx;
+  const double* u0;          /* device [3][N]                                     */
+  ap_solve_params params;
+  double* U_out;             /* device [slices+1][3][N]                           */
+  double* resid;             /* device [K]                                        */
+} ap_batch_item;
+int aparareal_solve_batch(const ap_batch_item* items, int count, void* stream);
+
+/* Execution options of a context (none changes the method; AP_OPT_GROUP
+ * changes the summation order of the time average, hence rounding):
+ *   AP_OPT_SPLIT  -1 (default): a coarse step of a pipelined solve runs on
+ *                 several workgroups (one per sample group, for each of its
+ *                 two averages) when the average has two groups or more;
+ *                 0: one workgroup per coarse step; 1: always split.
+ *   AP_OPT_GROUP  samples per group of the time average (the sum runs over
+ *                 each group in sample order, then over the groups in order);
+ *                 0 (default) = by grid size.  Reading returns the size used.
+ *   AP_OPT_GRID   workgroups of a persistent launch; 0 (default) = as many as
+ *                 are resident on the device at once.                        */
+enum { AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2 };
+int aparareal_set_option(ap_ctx* ctx, int option, int value);
+int aparareal_get_option(ap_ctx* ctx, int option, int* value);
+
+/* Autotuner of the pipelined schedule for the problems of `items` (one item:
+ * a single solve; several: a batch as in aparareal_solve_batch, with the same
+ * argument rules).  For each execution mapping (AP_OPT_SPLIT 0 and 1) it runs
+ * the solve, records every job's duration on the device clock, re-orders the
+ * jobs with the measured durations per problem and job type (twice), and
+ * times three solves; it then keeps the fastest mapping and its measured
+ * durations in the contexts, so that later solves of the same shape use
+ * them.  The outputs receive the results of the last solve run.  *best_ms
+ * (host, may be NULL) receives the best solve time.  Results of later solves
+ * do not depend on the tuning (the group size is not tuned).                */
+int aparareal_autotune(const ap_batch_item* items, int count, void* stream, double* best_ms);
+
 /* Kernel timing (diagnostics, no effect on results).  While enabled, the
  * library brackets each of its own kernel launches with a pair of HIP events
  * recorded on the launch stream and accumulates the elapsed time per kernel
@@ -135,12 +179,15 @@ int aparareal_profile(ap_ctx* ctx, int enable);
 int aparareal_profile_read(ap_ctx* ctx, int kernel_class, int* launches, double* total_ms);
 
 /* Order in which the pipelined solve hands out its jobs (host only, no device
- * needed; for inspection and tests).  Writes (type, k, n) triples to the host
- * array `out` [3 * (2K+1) * slices]: type 0 = coarse step C(k,n) of iteration
- * level k = 0..K, type 1 = fine slice F(k,n) = Fine(U_{n-1}^k), k = 0..K-1;
- * n = 1..slices.  `steps` fine steps per slice and M_avg samples set the
- * estimated ready times that order the list.  Returns the job count or AP_EINVAL. */
-int aparareal_pipeline_schedule(int slices, int K, int steps, int M_avg, int* out);
+ * needed; for inspection and tests), for a problem of grid size N with
+ * parameters p, split / group as AP_OPT_SPLIT / AP_OPT_GROUP.  Writes up to
+ * max_jobs (type, k, n, g) quadruples to the host array `out` (may be NULL):
+ * type 0 = coarse step C(k,n) in one workgroup, k = 0..K; 1 = fine slice
+ * F(k,n) = Fine(U_{n-1}^k), k = 0..K-1; 2 / 3 = first / second average of a
+ * split coarse step C(k,n) for sample group g.  Jobs are ordered by their
+ * estimated ready times, and every job comes after the jobs it depends on.
+ * Returns the job count or AP_EINVAL.                                        */
+int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int group, int* out, int max_jobs);
 
 /* Stall record of the context's last pipelined solve (waits for it): host
  * info[3] = (stalled, job index, flag index).  A stall means a job saw no
@@ -150,10 +197,10 @@ int aparareal_pipeline_status(ap_ctx* ctx, int* info);
 
 /* Per-job timeline of pipelined solves (diagnostics).  enable = 1 / 0 turns
  * recording on / off for the following solves (out may be NULL); enable = -1
- * reads the last solve's record into host `out` [6 * max_jobs]: per job in
- * hand-out order (type, k, n, start, end, workgroup) with start/end in ticks
- * of the device's constant-rate clock (100 MHz on MI355X).  Returns the number
- * of jobs written (reading waits for the solve).                              */
+ * reads the last launch this context owned into host `out` [8 * max_jobs]:
+ * per job in hand-out order (problem, type, k, n, g, start, end, workgroup)
+ * with start/end in ticks of the device's constant-rate clock (100 MHz on
+ * MI355X).  Returns the number of jobs written (reading waits for the solve). */
 int aparareal_pipeline_trace(ap_ctx* ctx, int enable, long long* out, int max_jobs);
 
 #ifdef __cplusplus

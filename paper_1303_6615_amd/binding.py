@@ -33,6 +33,15 @@ class SolveParams(ctypes.Structure):
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("u0", ctypes.c_void_p), ("params", SolveParams),
+                ("U_out", ctypes.c_void_p), ("resid", ctypes.c_void_p)]
+
+
+AP_OPT_SPLIT, AP_OPT_GROUP, AP_OPT_GRID = 0, 1, 2
+JOB_COARSE, JOB_FINE, JOB_STAGE1, JOB_STAGE2 = 0, 1, 2, 3
+
+
 _lib = None
 _vp, _dp, _i, _d = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
 
@@ -46,7 +55,11 @@ _SIGNATURES = {
     "aparareal_coarse": (_i, [_vp, _dp, _dp, _i, _d, _i, _d, _i, _vp]),
     "aparareal_solve": (_i, [_vp, _dp, ctypes.POINTER(SolveParams), _dp, _dp, _vp]),
     "aparareal_profile": (_i, [_vp, _i]),
-    "aparareal_pipeline_schedule": (_i, [_i, _i, _i, _i, ctypes.POINTER(_i)]),
+    "aparareal_solve_batch": (_i, [ctypes.POINTER(BatchItem), _i, _vp]),
+    "aparareal_set_option": (_i, [_vp, _i, _i]),
+    "aparareal_autotune": (_i, [ctypes.POINTER(BatchItem), _i, _vp, ctypes.POINTER(_d)]),
+    "aparareal_get_option": (_i, [_vp, _i, ctypes.POINTER(_i)]),
+    "aparareal_pipeline_schedule": (_i, [_i, ctypes.POINTER(SolveParams), _i, _i, ctypes.POINTER(_i), _i]),
     "aparareal_pipeline_status": (_i, [_vp, ctypes.POINTER(_i)]),
     "aparareal_pipeline_trace": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), _i]),
     "aparareal_profile_read": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
@@ -78,12 +91,54 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
-def pipeline_schedule(slices: int, K: int, steps: int, M: int) -> list[tuple[int, int, int]]:
-    """Job order of the pipelined solve as (type, k, n) triples (host only)."""
-    n = (2 * K + 1) * slices
-    buf = (ctypes.c_int * (3 * n))()
-    cnt = _check(lib().aparareal_pipeline_schedule(slices, K, steps, M, buf))
-    return [(buf[3 * i], buf[3 * i + 1], buf[3 * i + 2]) for i in range(cnt)]
+def pipeline_schedule(N: int, T: float, slices: int, K: int, dt_fine: float, M: int, split: int = -1,
+                      group: int = 0, precision: int = AP_PREC_FP32) -> list[tuple[int, int, int, int]]:
+    """Job order of the pipelined solve as (type, k, n, g) quadruples (host only)."""
+    p = SolveParams(float(T), int(slices), int(K), float(dt_fine), int(M), 0.0, 0.0, int(precision))
+    cnt = _check(lib().aparareal_pipeline_schedule(N, ctypes.byref(p), split, group, None, 0))
+    buf = (ctypes.c_int * (4 * max(cnt, 1)))()
+    cnt = _check(lib().aparareal_pipeline_schedule(N, ctypes.byref(p), split, group, buf, cnt))
+    return [tuple(buf[4 * i:4 * i + 4]) for i in range(cnt)]
+
+
+def _batch_items(problems, precision):
+    import torch
+    items = (BatchItem * len(problems))()
+    outs = []
+    for i, (ctx, u0, prm) in enumerate(problems):
+        u0 = _states(u0, ctx.N, "u0")
+        S, K = int(prm["slices"]), int(prm["K"])
+        U = torch.empty((S + 1, 3, ctx.N), dtype=torch.float64, device=u0.device)
+        r = torch.empty((max(K, 1),), dtype=torch.float64, device=u0.device)
+        items[i].ctx = ctx._h
+        items[i].u0 = u0.data_ptr()
+        items[i].params = SolveParams(float(prm["T"]), S, K, float(prm["dt_fine"]), int(prm["M"]),
+                                      float(prm.get("T0", 0.0)), 0.0, int(precision))
+        items[i].U_out = U.data_ptr()
+        items[i].resid = r.data_ptr()
+        outs.append((U, r[:K], u0))
+    return items, outs
+
+
+def solve_batch(problems, precision: int = AP_PREC_FP32):
+    """Many problems in one persistent launch.  `problems` is a list of
+    (Context, u0, dict(T, slices, K, dt_fine, M[, T0])); returns a list of
+    (U [slices+1, 3, N], resid [K]) CUDA tensors."""
+    import torch
+    items, outs = _batch_items(problems, precision)
+    _check(lib().aparareal_solve_batch(items, len(problems), _stream(torch)))
+    return [(U, r) for (U, r, _) in outs]
+
+
+def autotune(problems, precision: int = AP_PREC_FP32) -> float:
+    """Tune the pipelined schedule of these problems (as for solve_batch; one
+    problem tunes a single solve).  Returns the best solve time in ms."""
+    import torch
+    items, outs = _batch_items(problems, precision)
+    ms = ctypes.c_double(0.0)
+    _check(lib().aparareal_autotune(items, len(problems), _stream(torch), ctypes.byref(ms)))
+    torch.cuda.synchronize()
+    return ms.value
 
 
 def _check(rc: int) -> int:
@@ -180,10 +235,18 @@ class Context:
         _check(lib().aparareal_pipeline_trace(self._h, 1 if enable else 0, None, 0))
 
     def trace_read(self, max_jobs: int = 1 << 20):
-        """Last solve's jobs: list of (type, k, n, start_tick, end_tick, workgroup)."""
-        buf = (ctypes.c_longlong * (6 * max_jobs))()
+        """Last launch's jobs: list of (problem, type, k, n, g, start_tick, end_tick, workgroup)."""
+        buf = (ctypes.c_longlong * (8 * max_jobs))()
         n = _check(lib().aparareal_pipeline_trace(self._h, -1, buf, max_jobs))
-        return [tuple(buf[6 * i:6 * i + 6]) for i in range(n)]
+        return [tuple(buf[8 * i:8 * i + 8]) for i in range(n)]
+
+    def set_option(self, option: int, value: int):
+        _check(lib().aparareal_set_option(self._h, int(option), int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int(0)
+        _check(lib().aparareal_get_option(self._h, int(option), ctypes.byref(v)))
+        return v.value
 
     # -- the parareal solve ----------------------------------------------------
     def solve(self, u0, T: float, slices: int, K: int, dt_fine: float, M: int, T0: float = 0.0,

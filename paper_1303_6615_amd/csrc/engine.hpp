@@ -54,10 +54,15 @@ struct Engine {
   cx<T>* y;
   double* red;
 
-  __device__ __forceinline__ Engine(unsigned char* smem, const cx<T>* __restrict__ tw_global) {
+  // stage == false: the twiddles of this grid size are already in LDS (the
+  // previous job of this workgroup staged them and nothing overwrote them).
+  __device__ __forceinline__ Engine(unsigned char* smem, const cx<T>* __restrict__ tw_global, bool stage = true) {
     cx<T>* base = reinterpret_cast<cx<T>*>(smem);
     if constexpr (TW_LDS) {
-      for (int i = threadIdx.x; i < NX; i += NT) base[i] = tw_global[i];
+      if (stage) {
+        for (int i = threadIdx.x; i < NX; i += NT) base[i] = tw_global[i];
+        __syncthreads();
+      }
       tw = base;
       base += NX;
     } else {
@@ -67,8 +72,8 @@ struct Engine {
     ib = sp + S * SL::sp_elems;
     y = ib + S * SL::ib_elems;
     red = reinterpret_cast<double*>(ib);
-    __syncthreads();
   }
+
   static __device__ __forceinline__ int mode(int j) { return threadIdx.x + j * NT; }
   static __device__ __forceinline__ bool valid(int j) { return mode(j) < KP; }
 
@@ -211,30 +216,39 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, const cx<doub
 }
 
 // ----------------------------------------------------------- time average ---
-// Nbar of the owned-mode state y -> acc with min(S, M-1) samples in flight.
-// Per chunk: every thread rotates (sample, mode) items into the slots' field
-// spectra; wavefronts run the inverse transforms and the forward transforms
-// of the products; every thread turns (sample, mode) items back into weighted,
+// Nbar contributions of the samples m in [mb, me) of the owned-mode state yv,
+// with min(S, me - m0) samples in flight.  [mb, me) covers whole groups of
+// av.gs consecutive samples (the last group may be shorter).  Per chunk every
+// thread rotates (sample, mode) items into the slots' field spectra; the
+// wavefronts run the inverse transforms and the forward transforms of the
+// products; every thread turns (sample, mode) items back into weighted,
 // rotated modal contributions in the slot's ib; the mode owners then add the
-// chunk's contributions in increasing sample order (a fixed order).
+// contributions of each group in increasing sample order.
+//   whole:  acc = 0 + S_0 + S_1 + ... over the groups, in increasing order
+//   !whole: [mb, me) is one group and acc = its sum S_g
+// (S_g = c_first + c_next + ..., the same association in every kernel).
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void nbar_owned(Engine<T, NX, NT, S>& en,
+__device__ __forceinline__ void nbar_range(Engine<T, NX, NT, S>& en,
                                            const cx<T> (&yv)[Engine<T, NX, NT, S>::MPT][3],
-                                           cx<T> (&acc)[Engine<T, NX, NT, S>::MPT][3],
-                                           const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT], const AvgTab<T>& av,
-                                           const Basis<T>* __restrict__ basis) {
+                                           cx<T> (&acc)[Engine<T, NX, NT, S>::MPT][3], int mb, int me, bool whole,
+                                           const AvgTab<T>& av, const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, S>;
   using SL = Slot<T, NX>;
   constexpr int KP = E_::KP;
+  constexpr int MPT = E_::MPT;
+  cx<T> pg[MPT][3];
 #pragma unroll
-  for (int j = 0; j < E_::MPT; ++j) {
-    for (int al = 0; al < 3; ++al) acc[j][al] = czero<T>();
+  for (int j = 0; j < MPT; ++j) {
+    for (int al = 0; al < 3; ++al) {
+      acc[j][al] = czero<T>();
+      pg[j][al] = czero<T>();
+    }
     if (E_::valid(j))
       for (int al = 0; al < 3; ++al) en.y[al * KP + E_::mode(j)] = yv[j][al];
   }
   __syncthreads();
-  for (int m0 = 1; m0 < av.M; m0 += S) {
-    const int ns = min(S, av.M - m0);
+  for (int m0 = mb; m0 < me; m0 += S) {
+    const int ns = min(S, me - m0);
     for (int i = threadIdx.x; i < ns * KP; i += NT) {
       const int s = i / KP, k = i - s * KP;
       const cx<T> e = av.rot[size_t(m0 + s) * KP + k];
@@ -257,79 +271,125 @@ __device__ __forceinline__ void nbar_owned(Engine<T, NX, NT, S>& en,
       for (int al = 0; al < 3; ++al) c[al * KP + k] = wm * rot_out(n[al], e, al);
     }
     __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+      const int r = (m0 + s - 1) % av.gs;
+      const bool first = r == 0;
+      const bool last = r == av.gs - 1 || m0 + s == av.M - 1;
+      const cx<T>* c = en.ib + s * SL::ib_elems;
 #pragma unroll
-    for (int j = 0; j < E_::MPT; ++j) {
-      if (!E_::valid(j)) continue;
-      const int k = E_::mode(j);
-      for (int s = 0; s < ns; ++s) {
-        const cx<T>* c = en.ib + s * SL::ib_elems;
-        for (int al = 0; al < 3; ++al) acc[j][al] = acc[j][al] + c[al * KP + k];
+      for (int j = 0; j < MPT; ++j) {
+        if (!E_::valid(j)) continue;
+        const int k = E_::mode(j);
+        for (int al = 0; al < 3; ++al) {
+          const cx<T> v = c[al * KP + k];
+          pg[j][al] = first ? v : pg[j][al] + v;
+          if (last) acc[j][al] = whole ? acc[j][al] + pg[j][al] : pg[j][al];
+        }
       }
     }
   }
 }
 
-// One asymptotic coarse step on owned-mode registers u -> g (Alg. 2).
+// Nbar over all samples (every group, in order).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void nbar_owned(Engine<T, NX, NT, S>& en,
+                                           const cx<T> (&yv)[Engine<T, NX, NT, S>::MPT][3],
+                                           cx<T> (&acc)[Engine<T, NX, NT, S>::MPT][3], const AvgTab<T>& av,
+                                           const Basis<T>* __restrict__ basis) {
+  nbar_range<T, NX, NT, S>(en, yv, acc, 1, av.M, true, av, basis);
+}
+
+// ------------------------------------------------------------ coarse step ---
+// The asymptotic coarse step (Alg. 2) on owned-mode registers, in pieces that
+// the single-workgroup and the split evaluation share, so that both round
+// identically:
+//   w = e^{(dT/2) D} u;  y = w + (dT/2) Nbar(w);
+//   g = e^{-(dT/eps) L} e^{(dT/2) D} (w + dT Nbar(y)).
+template <typename T, int MPT>
+struct CoarseRegs {
+  T hd[MPT];
+  cx<T> rT[MPT];
+};
+
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void coarse_begin(const CoarseTab<T>& ct, const cx<T> (&u)[Engine<T, NX, NT, S>::MPT][3],
+                                             cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3],
+                                             CoarseRegs<T, Engine<T, NX, NT, S>::MPT>& cr) {
+  using E_ = Engine<T, NX, NT, S>;
+#pragma unroll
+  for (int j = 0; j < E_::MPT; ++j) {
+    const int k = E_::valid(j) ? E_::mode(j) : 0;
+    cr.hd[j] = ct.hd[k];
+    cr.rT[j] = ct.rotT[k];
+    for (int al = 0; al < 3; ++al) w[j][al] = cr.hd[j] * u[j][al];
+  }
+}
+
+template <typename T, int MPT>
+__device__ __forceinline__ void coarse_mid(const CoarseTab<T>& ct, const cx<T> (&w)[MPT][3],
+                                           const cx<T> (&k1)[MPT][3], cx<T> (&y)[MPT][3]) {
+  const T half = T(0.5) * ct.dT;
+#pragma unroll
+  for (int j = 0; j < MPT; ++j)
+    for (int al = 0; al < 3; ++al) y[j][al] = w[j][al] + half * k1[j][al];
+}
+
+template <typename T, int MPT>
+__device__ __forceinline__ void coarse_end(const CoarseTab<T>& ct, const CoarseRegs<T, MPT>& cr,
+                                           const cx<T> (&w)[MPT][3], const cx<T> (&k2)[MPT][3],
+                                           cx<T> (&g)[MPT][3]) {
+#pragma unroll
+  for (int j = 0; j < MPT; ++j)
+    for (int al = 0; al < 3; ++al) {
+      const cx<T> v = cr.hd[j] * (w[j][al] + ct.dT * k2[j][al]);
+      g[j][al] = al == 2 ? v * cr.rT[j] : (al == 0 ? v * conj(cr.rT[j]) : v);
+    }
+}
+
+// One asymptotic coarse step in one workgroup: u -> g.
 template <typename T, int NX, int NT, int S>
 __device__ __forceinline__ void coarse_owned(Engine<T, NX, NT, S>& en,
                                              const cx<T> (&u)[Engine<T, NX, NT, S>::MPT][3],
                                              cx<T> (&g)[Engine<T, NX, NT, S>::MPT][3],
-                                             const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT],
                                              const CoarseTab<T>& ct, const Basis<T>* __restrict__ basis) {
-  using E_ = Engine<T, NX, NT, S>;
-  constexpr int MPT = E_::MPT;
+  constexpr int MPT = Engine<T, NX, NT, S>::MPT;
   cx<T> w[MPT][3], y[MPT][3], kk[MPT][3];
-  T hd[MPT];
-  cx<T> rT[MPT];
-#pragma unroll
-  for (int j = 0; j < MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : 0;
-    hd[j] = ct.hd[k];
-    rT[j] = ct.rotT[k];
-    for (int al = 0; al < 3; ++al) w[j][al] = hd[j] * u[j][al];
-  }
-  nbar_owned<T, NX, NT, S>(en, w, kk, bs, ct.avg, basis);
-  const T half = T(0.5) * ct.dT;
-#pragma unroll
-  for (int j = 0; j < MPT; ++j)
-    for (int al = 0; al < 3; ++al) y[j][al] = w[j][al] + half * kk[j][al];
-  nbar_owned<T, NX, NT, S>(en, y, kk, bs, ct.avg, basis);
-#pragma unroll
-  for (int j = 0; j < MPT; ++j)
-    for (int al = 0; al < 3; ++al) {
-      const cx<T> v = hd[j] * (w[j][al] + ct.dT * kk[j][al]);
-      g[j][al] = al == 2 ? v * rT[j] : (al == 0 ? v * conj(rT[j]) : v);
-    }
+  CoarseRegs<T, MPT> cr;
+  coarse_begin<T, NX, NT, S>(ct, u, w, cr);
+  nbar_owned<T, NX, NT, S>(en, w, kk, ct.avg, basis);
+  coarse_mid<T, MPT>(ct, w, kk, y);
+  nbar_owned<T, NX, NT, S>(en, y, kk, ct.avg, basis);
+  coarse_end<T, MPT>(ct, cr, w, kk, g);
 }
 
-// One coarse job of the parareal iteration on modal FP64 states:
-//   g = G(uprev);  gnew <- g
-//   gold == nullptr (k = 0):  unew <- g
-//   otherwise:                unew <- fold + (g - gold)     (FP64)
+// Owned modes of a modal FP64 state, rounded to T (zero for unowned slots).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void load_owned(const cx<double>* __restrict__ src,
+                                           cx<T> (&u)[Engine<T, NX, NT, S>::MPT][3]) {
+  using E_ = Engine<T, NX, NT, S>;
+#pragma unroll
+  for (int j = 0; j < E_::MPT; ++j) {
+    const int k = E_::valid(j) ? E_::mode(j) : 0;
+    for (int al = 0; al < 3; ++al) u[j][al] = E_::valid(j) ? cvt<T>(src[al * E_::KP + k]) : czero<T>();
+  }
+}
+
+// The parareal correction of a coarse result g (owned modes):
+//   gnew <- g;  unew <- g (gold == nullptr, k = 0) or fold + (g - gold) (FP64);
 //   uold != nullptr: *part = (sum |unew - uold|^2, sum |unew|^2) with Parseval
 //   weights (1 for k = 0, 2 otherwise).
 // Every location is read before it is written by the same thread, so unew may
 // alias uold and gnew may alias gold (the in-place serial sweep).
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void coarse_job(Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct,
-                                           const Basis<T>* __restrict__ basis, const cx<double>* uprev,
-                                           cx<double>* unew, cx<double>* gnew, const cx<double>* gold,
-                                           const cx<double>* fold, const cx<double>* uold, double2* part) {
+__device__ __forceinline__ void coarse_correct(Engine<T, NX, NT, S>& en,
+                                               const cx<T> (&g)[Engine<T, NX, NT, S>::MPT][3], cx<double>* unew,
+                                               cx<double>* gnew, const cx<double>* gold, const cx<double>* fold,
+                                               const cx<double>* uold, double2* part) {
   using E_ = Engine<T, NX, NT, S>;
   constexpr int KP = E_::KP;
-  constexpr int MPT = E_::MPT;
-  cx<T> u[MPT][3], g[MPT][3];
-  Basis<T> bs[MPT];
-#pragma unroll
-  for (int j = 0; j < MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : 0;
-    bs[j] = basis[k];
-    for (int al = 0; al < 3; ++al) u[j][al] = E_::valid(j) ? cvt<T>(uprev[al * KP + k]) : czero<T>();
-  }
-  coarse_owned<T, NX, NT, S>(en, u, g, bs, ct, basis);
   double num = 0.0, den = 0.0;
 #pragma unroll
-  for (int j = 0; j < MPT; ++j) {
+  for (int j = 0; j < E_::MPT; ++j) {
     if (!E_::valid(j)) continue;
     const int k = E_::mode(j);
     const double wgt = k == 0 ? 1.0 : 2.0;
@@ -351,6 +411,93 @@ __device__ __forceinline__ void coarse_job(Engine<T, NX, NT, S>& en, const Coars
     const double2 r = en.block_sum2(num, den);
     if (threadIdx.x == 0) *part = r;
   }
+}
+
+// One coarse job of the parareal iteration on modal FP64 states, in one
+// workgroup: g = G(uprev), then the correction above.
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void coarse_job(Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct,
+                                           const Basis<T>* __restrict__ basis, const cx<double>* uprev,
+                                           cx<double>* unew, cx<double>* gnew, const cx<double>* gold,
+                                           const cx<double>* fold, const cx<double>* uold, double2* part) {
+  constexpr int MPT = Engine<T, NX, NT, S>::MPT;
+  cx<T> u[MPT][3], g[MPT][3];
+  load_owned<T, NX, NT, S>(uprev, u);
+  coarse_owned<T, NX, NT, S>(en, u, g, ct, basis);
+  coarse_correct<T, NX, NT, S>(en, g, unew, gnew, gold, fold, uold, part);
+}
+
+// ------------------------------------------------- split coarse step -------
+// A coarse step evaluated by several workgroups: the stage-1 job of group g
+// stores S_g of Nbar(w); the stage-2 job of group g sums the stored stage-1
+// group sums (0 + S_0 + S_1 + ..., the order of the single-workgroup step),
+// forms y and stores S_g of Nbar(y).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void sum_groups(const cx<T>* __restrict__ P, int groups,
+                                           cx<T> (&acc)[Engine<T, NX, NT, S>::MPT][3]) {
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int KP = E_::KP;
+#pragma unroll
+  for (int j = 0; j < E_::MPT; ++j)
+    for (int al = 0; al < 3; ++al) acc[j][al] = czero<T>();
+  for (int g = 0; g < groups; ++g) {
+    const cx<T>* Pg = P + size_t(g) * 3 * KP;
+#pragma unroll
+    for (int j = 0; j < E_::MPT; ++j) {
+      if (!E_::valid(j)) continue;
+      for (int al = 0; al < 3; ++al) acc[j][al] = acc[j][al] + Pg[al * KP + E_::mode(j)];
+    }
+  }
+}
+
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void store_owned(cx<T>* __restrict__ dst,
+                                            const cx<T> (&v)[Engine<T, NX, NT, S>::MPT][3]) {
+  using E_ = Engine<T, NX, NT, S>;
+#pragma unroll
+  for (int j = 0; j < E_::MPT; ++j)
+    if (E_::valid(j))
+      for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = v[j][al];
+}
+
+// Stage job of group g: stage 1 stores S_g(Nbar(w)) at P1g; stage 2 forms y
+// from the stage-1 sums at P1 and stores S_g(Nbar(y)) at P2g.  On return of
+// stage 2, w holds the step's w (for the finishing job).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void stage_job(Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct,
+                                          const Basis<T>* __restrict__ basis, const cx<double>* uprev, int stage,
+                                          int g, const cx<T>* P1, int groups, cx<T>* Pout,
+                                          cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3],
+                                          CoarseRegs<T, Engine<T, NX, NT, S>::MPT>& cr) {
+  constexpr int MPT = Engine<T, NX, NT, S>::MPT;
+  cx<T> u[MPT][3], y[MPT][3], acc[MPT][3];
+  load_owned<T, NX, NT, S>(uprev, u);
+  coarse_begin<T, NX, NT, S>(ct, u, w, cr);
+  if (stage == 2) {
+    sum_groups<T, NX, NT, S>(P1, groups, acc);
+    coarse_mid<T, MPT>(ct, w, acc, y);
+  } else {
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+      for (int al = 0; al < 3; ++al) y[j][al] = w[j][al];
+  }
+  const int mb = 1 + g * ct.avg.gs;
+  const int me = min(ct.avg.M, mb + ct.avg.gs);
+  nbar_range<T, NX, NT, S>(en, y, acc, mb, me, false, ct.avg, basis);
+  store_owned<T, NX, NT, S>(Pout, acc);
+}
+
+// The finishing part of a split step: Nbar(y) = sum of the stage-2 group sums,
+// then the end of the step (the correction follows via coarse_correct).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void stage_finish(const CoarseTab<T>& ct, const cx<T>* P2, int groups,
+                                             const cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3],
+                                             const CoarseRegs<T, Engine<T, NX, NT, S>::MPT>& cr,
+                                             cx<T> (&g)[Engine<T, NX, NT, S>::MPT][3]) {
+  constexpr int MPT = Engine<T, NX, NT, S>::MPT;
+  cx<T> k2[MPT][3];
+  sum_groups<T, NX, NT, S>(P2, groups, k2);
+  coarse_end<T, MPT>(ct, cr, w, k2, g);
 }
 
 }  // namespace ap

@@ -133,6 +133,13 @@ struct AvgTables {
   ap::CoarseTab<float> c32{};
 };
 
+// Measured durations (us) of the pipeline's workgroup jobs for one problem
+// (aparareal_autotune); they replace the analytic estimates that order jobs.
+struct CostCal {
+  bool valid = false;
+  double fine_step = 0, stage1 = 0, stage2 = 0, whole = 0;
+};
+
 }  // namespace
 
 struct ap_ctx {
@@ -143,14 +150,20 @@ struct ap_ctx {
   DevBuf tw64, tw32, basis64, basis32;
   ap::DevTables tabs;
   std::map<uint64_t, std::unique_ptr<FineTables>> fine_cache;
-  std::map<std::tuple<uint64_t, uint64_t, int>, std::unique_ptr<AvgTables>> avg_cache;
+  std::map<std::tuple<uint64_t, uint64_t, int, int>, std::unique_ptr<AvgTables>> avg_cache;
   DevBuf ws_in, ws_out, ws_U, ws_F, ws_G, ws_part;
   // pipelined solve: per-level states, flags, job list and descriptor
-  DevBuf pp_U, pp_F, pp_G, pp_part, pp_flags, pp_jobs, pp_prob;
-  std::tuple<int, int, int, int> pp_jobs_key{-1, -1, -1, -1};
+  DevBuf pp_U, pp_F, pp_G, pp_part, pp_P1, pp_P2;     // this context's problem
+  DevBuf pp_flags, pp_jobs, pp_prob, pp_rows;          // launches this context owns
+  std::string pp_jobs_key;
   int pp_njobs = 0;
   std::vector<ap::PipeJob> pp_jobs_host;
-  std::vector<unsigned char> pp_prob_host;
+  std::vector<unsigned char> pp_prob_host, pp_rows_host;
+  // options (aparareal_set_option)
+  int opt_split = -1;        // split coarse steps over workgroups: -1 auto, 0 no, 1 yes
+  int opt_group = 0;         // samples per group of the average; 0 = by grid size
+  int opt_grid = 0;          // workgroups of a persistent launch; 0 = all that fit
+  CostCal cost;              // calibrated job durations (aparareal_autotune)
   int* pp_diag = nullptr;   // stall record of the last pipelined launch
   bool trace_on = false;     // record per-job device-clock intervals
   DevBuf pp_trace;
@@ -275,9 +288,21 @@ int fine_tables(ap_ctx* c, double h, FineTables** out) {
   return AP_OK;
 }
 
+// Samples per group of the time average: as many as make one round of
+// transforms for the eight wavefronts of a pipeline workgroup (3 signals per
+// sample; 64 / G signals per wavefront with G lanes per signal of length N).
+int default_group_size(int nx) {
+  const int P = nx / 2;
+  const int G = P <= 32 ? 8 : P <= 64 ? 16 : P <= 128 ? 32 : 64;
+  return std::max(1, 8 * (64 / G) / 3);
+}
+
+int group_size(const ap_ctx* c) { return c->opt_group > 0 ? c->opt_group : default_group_size(c->N); }
+
 // dT == 0 builds the average-only tables.
 int avg_tables(ap_ctx* c, double dT, double T0, int M, AvgTables** out) {
-  auto key = std::make_tuple(bits(dT), bits(T0), M);
+  const int gs = group_size(c);
+  auto key = std::make_tuple(bits(dT), bits(T0), M, gs);
   auto it = c->avg_cache.find(key);
   if (it != c->avg_cache.end()) {
     *out = it->second.get();
@@ -325,9 +350,9 @@ int avg_tables(ap_ctx* c, double dT, double T0, int M, AvgTables** out) {
   if (e == hipSuccess) e = at->rotT64.upload(rt64);
   if (e == hipSuccess) e = at->rotT32.upload(rt32);
   if (e != hipSuccess) return hip_fail(e, "average table upload");
-  at->c64 = ap::CoarseTab<double>{{at->rot64.as<cx<double>>(), at->w64.as<double>(), M},
+  at->c64 = ap::CoarseTab<double>{{at->rot64.as<cx<double>>(), at->w64.as<double>(), M, gs},
                                   at->hd64.as<double>(), at->rotT64.as<cx<double>>(), dT};
-  at->c32 = ap::CoarseTab<float>{{at->rot32.as<cx<float>>(), at->w32.as<float>(), M},
+  at->c32 = ap::CoarseTab<float>{{at->rot32.as<cx<float>>(), at->w32.as<float>(), M, gs},
                                  at->hd32.as<float>(), at->rotT32.as<cx<float>>(), float(dT)};
   *out = at.get();
   c->avg_cache[key] = std::move(at);
@@ -370,35 +395,6 @@ int batch_epilogue(ap_ctx* c, double* out, int batch, hipStream_t s) {
                        [&] { return ap::launch_to_physical(c->N, c->ws_out.as<cx<double>>(), out, batch, c->tabs, s); });
   if (e != hipSuccess) return hip_fail(e, "to_physical launch");
   return AP_OK;
-}
-
-// Jobs of the pipelined solve in a topological order: by estimated ready time
-// t(C(k,n)) = n tc + k tf, t(F(k,n)) = (n-1) tc + k tf (tc, tf: nonlinear
-// evaluations per coarse step / fine slice), coarse before fine on ties.  Every
-// dependency of a job has a smaller t or is a coarse job of equal t, so the
-// ticket order lets the earliest unfinished job always run.
-std::vector<ap::PipeJob> pipeline_jobs(int prob, int Ns, int K, int steps, int M) {
-  struct Item {
-    long long t;
-    ap::PipeJob j;
-  };
-  const long long tc = 2LL * (M - 1) > 0 ? 2LL * (M - 1) : 1, tf = 4LL * steps;
-  std::vector<Item> it;
-  it.reserve(size_t(2 * K + 1) * Ns);
-  for (int k = 0; k <= K; ++k)
-    for (int n = 1; n <= Ns; ++n) it.push_back({n * tc + k * tf, {prob, 0, k, n}});
-  for (int k = 0; k < K; ++k)
-    for (int n = 1; n <= Ns; ++n) it.push_back({(n - 1) * tc + k * tf, {prob, 1, k, n}});
-  std::stable_sort(it.begin(), it.end(), [](const Item& a, const Item& b) {
-    if (a.t != b.t) return a.t < b.t;
-    if (a.j.type != b.j.type) return a.j.type < b.j.type;
-    if (a.j.k != b.j.k) return a.j.k < b.j.k;
-    return a.j.n < b.j.n;
-  });
-  std::vector<ap::PipeJob> out;
-  out.reserve(it.size());
-  for (auto& x : it) out.push_back(x.j);
-  return out;
 }
 
 int solve_sweeps(ap_ctx* c, const double* u0, const ap_solve_params* p, double* U_out, double* resid,
@@ -456,76 +452,380 @@ int solve_sweeps(ap_ctx* c, const double* u0, const ap_solve_params* p, double* 
   return AP_OK;
 }
 
-int solve_pipelined(ap_ctx* c, const double* u0, const ap_solve_params* p, double* U_out, double* resid,
-                    hipStream_t s, int steps, FineTables* ft, AvgTables* at) {
-  const int Ns = p->slices, K = p->K;
-  const size_t sb = state_bytes(c);
-  // job flags, ticket, stall record [3], per-workgroup progress [2][256]
-  const int nflags = (2 * K + 1) * Ns + 4 + 2 * 256;
+// ------------------------------------------------------------- scheduling ---
+// Shape of one problem in a pipelined launch.
+struct PipeShape {
+  int nx = 0, Ns = 0, K = 0, steps = 0, M = 0, gs = 1, groups = 1;
+  bool split = false, fp64 = false;
+  CostCal cal;
+};
+
+// Estimated duration (us) of the workgroup jobs of one problem, used only to
+// order the jobs.  Without a calibration: one nonlinear evaluation at grid
+// size N takes about 1.6 + 0.0032 N us in FP32 (x1.6 in FP64), a fine step
+// four of them; a group job of the average costs a fixed 3 us plus 1.5
+// evaluation times per round of transforms its 3 gs signals need, a whole
+// coarse step 3 us plus 2.2 per round for each of its two averages (measured
+// on MI355X at N = 256 and 1024).
+struct JobCost {
+  double fine, stage1, stage2, finish, whole;
+};
+
+JobCost job_cost(const PipeShape& q) {
+  const double ev = (1.6 + 0.0032 * q.nx) * (q.fp64 ? 1.6 : 1.0);
+  const int P = q.nx / 2;
+  const int G = P <= 32 ? 8 : P <= 64 ? 16 : P <= 128 ? 32 : 64;
+  const int per_round = 8 * (64 / G);
+  auto rounds = [&](int samples) { return double((3 * samples + per_round - 1) / per_round); };
+  JobCost c;
+  c.fine = 4.0 * ev * q.steps + 2.0;
+  c.stage1 = 3.0 + 1.5 * rounds(q.gs) * ev;
+  c.stage2 = c.stage1 + 3.0;
+  c.finish = 0.5;
+  c.whole = 2.0 * (3.0 + 2.2 * rounds(q.M - 1) * ev) + 1.0;
+  if (q.cal.valid) {
+    if (q.cal.fine_step > 0) c.fine = q.cal.fine_step * q.steps;
+    if (q.cal.stage1 > 0) c.stage1 = q.cal.stage1;
+    if (q.cal.stage2 > 0) c.stage2 = q.cal.stage2;
+    if (q.cal.whole > 0) c.whole = q.cal.whole;
+  }
+  return c;
+}
+
+struct SchedItem {
+  double t;       // estimated ready time with unlimited workgroups (us)
+  double crit;    // the problem's estimated critical path: longer problems first on ties
+  int rank;       // stage 1 / whole coarse 0, stage 2 1, fine 2
+  ap::PipeJob j;
+};
+
+// Jobs of one problem with their earliest start times: a fine slice F(k,n)
+// and the first stage of C(k,n) start when C(k,n-1) is done; the second stage
+// one stage later; C(k,n) is done after both stages and (k >= 1) after F(k-1,n)
+// and C(k-1,n).  Returns the estimated completion of the last coarse step.
+double problem_jobs(int prob, const PipeShape& q, std::vector<SchedItem>& out) {
+  const JobCost jc = job_cost(q);
+  const int Ns = q.Ns, K = q.K;
+  std::vector<double> dC(size_t(K + 1) * Ns, 0.0), dF(size_t(std::max(K, 1)) * Ns, 0.0);
+  auto C = [&](int k, int n) -> double& { return dC[size_t(k) * Ns + n - 1]; };
+  auto Fd = [&](int k, int n) -> double& { return dF[size_t(k) * Ns + n - 1]; };
+  const size_t first = out.size();
+  for (int k = 0; k <= K; ++k)
+    for (int n = 1; n <= Ns; ++n) {
+      const double ready = n > 1 ? C(k, n - 1) : 0.0;
+      if (k < K) {
+        Fd(k, n) = ready + jc.fine;
+        out.push_back({ready, 0.0, 2, {prob, ap::kJobFine, k, n, 0}});
+      }
+      double after = 0.0;
+      if (k >= 1) after = std::max(Fd(k - 1, n), C(k - 1, n));
+      if (q.split) {
+        for (int g = 0; g < q.groups; ++g) out.push_back({ready, 0.0, 0, {prob, ap::kJobStage1, k, n, g}});
+        for (int g = 0; g < q.groups; ++g)
+          out.push_back({ready + jc.stage1, 0.0, 1, {prob, ap::kJobStage2, k, n, g}});
+        C(k, n) = std::max(ready + jc.stage1 + jc.stage2, after) + jc.finish;
+      } else {
+        const double start = std::max(ready, after);
+        out.push_back({start, 0.0, 0, {prob, ap::kJobCoarse, k, n, 0}});
+        C(k, n) = start + jc.whole;
+      }
+    }
+  const double span = C(K, Ns);
+  for (size_t i = first; i < out.size(); ++i) out[i].crit = span;
+  return span;
+}
+
+// Every job's dependencies must come earlier in the hand-out order (for a
+// split step: every stage-2 job after all stage-1 jobs of the step and after
+// every job the finishing one waits for).  Then the earliest unfinished job
+// always has its inputs, whatever the number of workgroups.
+bool order_is_valid(const std::vector<ap::PipeJob>& jobs, const std::vector<PipeShape>& shapes) {
+  std::vector<size_t> base(shapes.size() + 1, 0);
+  for (size_t p = 0; p < shapes.size(); ++p) base[p + 1] = base[p] + size_t(shapes[p].K + 1) * shapes[p].Ns;
+  const long long none = -1;
+  // per (prob, k, n): first/last position of the coarse step's jobs, its
+  // stage-1 last position, stage-2 first position; per fine slice its position
+  std::vector<long long> cfirst(base.back(), none), clast(base.back(), none), s1last(base.back(), none),
+      s2first(base.back(), none), fpos(base.back(), none);
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const ap::PipeJob& j = jobs[i];
+    if (j.prob < 0 || size_t(j.prob) >= shapes.size()) return false;
+    const PipeShape& q = shapes[j.prob];
+    if (j.k < 0 || j.k > q.K || j.n < 1 || j.n > q.Ns) return false;
+    const size_t at = base[j.prob] + size_t(j.k) * q.Ns + (j.n - 1);
+    const long long pos = (long long)i;
+    if (j.type == ap::kJobFine) {
+      if (j.k >= q.K || fpos[at] != none) return false;
+      fpos[at] = pos;
+      continue;
+    }
+    if (cfirst[at] == none) cfirst[at] = pos;
+    clast[at] = pos;
+    if (j.type == ap::kJobStage1) s1last[at] = pos;
+    if (j.type == ap::kJobStage2 && s2first[at] == none) s2first[at] = pos;
+  }
+  for (size_t p = 0; p < shapes.size(); ++p) {
+    const PipeShape& q = shapes[p];
+    auto idx = [&](int k, int n) { return base[p] + size_t(k) * q.Ns + (n - 1); };
+    for (int k = 0; k <= q.K; ++k)
+      for (int n = 1; n <= q.Ns; ++n) {
+        const size_t at = idx(k, n);
+        if (cfirst[at] == none) return false;
+        if (k < q.K && fpos[at] == none) return false;
+        const long long prev_done = n > 1 ? clast[idx(k, n - 1)] : none;
+        if (k < q.K && prev_done >= fpos[at]) return false;
+        if (prev_done >= cfirst[at]) return false;
+        // the step's completion point: the whole job, or the stage-2 jobs
+        const long long finish_from = q.split ? s2first[at] : cfirst[at];
+        if (q.split && (s1last[at] == none || s2first[at] == none || s1last[at] >= s2first[at])) return false;
+        if (k >= 1 && (fpos[idx(k - 1, n)] >= finish_from || clast[idx(k - 1, n)] >= finish_from)) return false;
+      }
+  }
+  return true;
+}
+
+// Hand-out order of the jobs of several problems: by estimated ready time,
+// then longer problems first, then stage 1 before stage 2 before fine slices.
+std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes) {
+  std::vector<SchedItem> it;
+  for (size_t p = 0; p < shapes.size(); ++p) problem_jobs(int(p), shapes[p], it);
+  std::stable_sort(it.begin(), it.end(), [](const SchedItem& a, const SchedItem& b) {
+    if (a.t != b.t) return a.t < b.t;
+    if (a.crit != b.crit) return a.crit > b.crit;
+    if (a.rank != b.rank) return a.rank < b.rank;
+    if (a.j.prob != b.j.prob) return a.j.prob < b.j.prob;
+    if (a.j.k != b.j.k) return a.j.k < b.j.k;
+    if (a.j.n != b.j.n) return a.j.n < b.j.n;
+    return a.j.g < b.j.g;
+  });
+  std::vector<ap::PipeJob> out;
+  out.reserve(it.size());
+  for (auto& x : it) out.push_back(x.j);
+  return out;
+}
+
+// ---------------------------------------------------------- pipelined solve -
+// One problem of a pipelined launch: its context (tables, per-problem device
+// workspace), arguments and derived sizes.
+struct PlanItem {
+  ap_ctx* c = nullptr;
+  const double* u0 = nullptr;
+  ap_solve_params p{};
+  double* U_out = nullptr;
+  double* resid = nullptr;
+  FineTables* ft = nullptr;
+  AvgTables* at = nullptr;
+  PipeShape q;
+};
+
+// Validates the solve parameters and derives the problem's shape and tables.
+int plan_item(ap_ctx* c, const double* u0, const ap_solve_params* p, double* U_out, double* resid, PlanItem* it) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!p || !u0 || !U_out) return fail(AP_EINVAL, "null argument");
+  if ((rc = check_prec(p->precision))) return rc;
+  if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(AP_EINVAL, "T must be > 0");
+  if (p->slices < 1) return fail(AP_EINVAL, "slices must be >= 1");
+  if (p->K < 0) return fail(AP_EINVAL, "K must be >= 0");
+  if (p->K > 0 && !resid) return fail(AP_EINVAL, "resid must hold K entries");
+  if (!(p->dt_fine > 0.0) || !std::isfinite(p->dt_fine)) return fail(AP_EINVAL, "dt_fine must be > 0");
+  if (p->M_avg < 2) return fail(AP_EINVAL, "M_avg must be >= 2");
+  if (!std::isfinite(p->T0) || !std::isfinite(p->tol)) return fail(AP_EINVAL, "T0, tol must be finite");
+  if (size_t(2 * p->K + 1) * size_t(p->slices) > (size_t(1) << 30)) return fail(AP_EINVAL, "problem too large");
+  const int Ns = p->slices;
+  const double dT = p->T / Ns;
+  const double ratio = dT / p->dt_fine;
+  if (ratio > 1e7) return fail(AP_EINVAL, "dT/dt_fine too large");
+  const int steps = std::max(1, int(std::ceil(ratio - 1e-9)));
+  const double win = p->T0 > 0.0 ? p->T0 : dT / c->eps;
+  it->c = c;
+  it->u0 = u0;
+  it->p = *p;
+  it->U_out = U_out;
+  it->resid = resid;
+  if ((rc = fine_tables(c, dT / steps, &it->ft))) return rc;
+  if ((rc = avg_tables(c, dT, win, p->M_avg, &it->at))) return rc;
+  PipeShape& q = it->q;
+  q.nx = c->N;
+  q.Ns = Ns;
+  q.K = p->K;
+  q.steps = steps;
+  q.M = p->M_avg;
+  q.gs = group_size(c);
+  q.groups = ap::avg_groups(q.M, q.gs);
+  q.fp64 = p->precision == AP_PREC_FP64;
+  q.split = c->opt_split < 0 ? q.groups >= 2 : c->opt_split != 0;
+  q.cal = c->cost;
+  return AP_OK;
+}
+
+template <typename T>
+ap::PipeProb<T> make_prob(const PlanItem& it, int* cnt);
+template <>
+ap::PipeProb<double> make_prob<double>(const PlanItem& it, int* cnt) {
+  ap_ctx* c = it.c;
+  return ap::PipeProb<double>{c->pp_U.as<cx<double>>(), c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(),
+                              c->pp_part.as<double2>(), cnt, c->pp_P1.as<cx<double>>(), c->pp_P2.as<cx<double>>(),
+                              it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups,
+                              it.ft->coef64.as<cx<double>>(), it.ft->coef64.as<cx<double>>(), it.at->c64,
+                              c->tabs.tw64, c->tabs.basis64};
+}
+template <>
+ap::PipeProb<float> make_prob<float>(const PlanItem& it, int* cnt) {
+  ap_ctx* c = it.c;
+  return ap::PipeProb<float>{c->pp_U.as<cx<double>>(), c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(),
+                             c->pp_part.as<double2>(), cnt, c->pp_P1.as<cx<float>>(), c->pp_P2.as<cx<float>>(),
+                             it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups,
+                             it.ft->coef64.as<cx<double>>(), it.ft->coef32.as<cx<float>>(), it.at->c32,
+                             c->tabs.tw32, c->tabs.basis32};
+}
+
+// Uploads `bytes` to a device buffer only when they differ from what it holds
+// (the host copy `last`); the device buffer is in use by earlier launches on
+// the owner's stream, so that stream is drained first.
+hipError_t upload_if_changed(ap_ctx* owner, DevBuf& dev, std::vector<unsigned char>& last,
+                             const std::vector<unsigned char>& bytes) {
+  if (dev.p && last == bytes) return hipSuccess;
+  hipError_t e = ensure(owner, dev, std::max<size_t>(bytes.size(), 1));
+  if (e != hipSuccess) return e;
+  if (owner->has_last && (e = hipStreamSynchronize(owner->last_stream)) != hipSuccess) return e;
+  if (!bytes.empty() && (e = hipMemcpy(dev.p, bytes.data(), bytes.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  last = bytes;
+  return hipSuccess;
+}
+
+template <typename V>
+std::vector<unsigned char> as_bytes(const std::vector<V>& v) {
+  std::vector<unsigned char> b(v.size() * sizeof(V));
+  if (!v.empty()) std::memcpy(b.data(), v.data(), b.size());
+  return b;
+}
+
+// Runs the problems of `items` (same precision, distinct contexts) as one
+// persistent launch on stream s.  `owner` holds the launch's job list,
+// descriptors and counters; each item's context holds its problem's states.
+int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
   hipError_t e;
-  if ((e = ensure(c, c->pp_U, sb * size_t(K + 1) * (Ns + 1))) != hipSuccess ||
-      (e = ensure(c, c->pp_F, sb * size_t(std::max(K, 1)) * (Ns + 1))) != hipSuccess ||
-      (e = ensure(c, c->pp_G, sb * size_t(K + 1) * (Ns + 1))) != hipSuccess ||
-      (e = ensure(c, c->pp_part, sizeof(double2) * size_t(Ns) * std::max(1, K))) != hipSuccess ||
-      (e = ensure(c, c->pp_flags, sizeof(int) * size_t(nflags))) != hipSuccess ||
-      (e = ensure(c, c->pp_prob, sizeof(ap::PipeProb<double>))) != hipSuccess)
-    return hip_fail(e, "pipeline workspace");
-  const auto key = std::make_tuple(Ns, K, steps, p->M_avg);
-  if (key != c->pp_jobs_key) {
-    c->pp_jobs_host = pipeline_jobs(0, Ns, K, steps, p->M_avg);
-    c->pp_njobs = int(c->pp_jobs_host.size());
-    if ((e = ensure(c, c->pp_jobs, sizeof(ap::PipeJob) * c->pp_jobs_host.size())) != hipSuccess ||
-        (e = hipMemcpy(c->pp_jobs.p, c->pp_jobs_host.data(), sizeof(ap::PipeJob) * c->pp_jobs_host.size(),
-                       hipMemcpyHostToDevice)) != hipSuccess)
-      return hip_fail(e, "job list upload");
-    c->pp_jobs_key = key;
+  const bool f64 = items[0].q.fp64;
+  std::vector<PipeShape> shapes;
+  long long ncnt = 0;
+  int nx_common = items[0].q.nx, nx_max = 0;
+  for (auto& it : items) {
+    const PipeShape& q = it.q;
+    if (q.fp64 != f64) return fail(AP_EINVAL, "all problems of a batch need the same precision");
+    ap_ctx* c = it.c;
+    const size_t sb = state_bytes(c);
+    const size_t pb = size_t(3) * c->KP * (f64 ? sizeof(cx<double>) : sizeof(cx<float>));
+    const size_t pbytes = q.split ? pb * size_t(q.K + 1) * q.groups : pb;
+    if ((e = ensure(c, c->pp_U, sb * size_t(q.K + 1) * (q.Ns + 1))) != hipSuccess ||
+        (e = ensure(c, c->pp_F, sb * size_t(std::max(q.K, 1)) * (q.Ns + 1))) != hipSuccess ||
+        (e = ensure(c, c->pp_G, sb * size_t(q.K + 1) * (q.Ns + 1))) != hipSuccess ||
+        (e = ensure(c, c->pp_part, sizeof(double2) * size_t(q.Ns) * std::max(1, q.K))) != hipSuccess ||
+        (e = ensure(c, c->pp_P1, pbytes)) != hipSuccess || (e = ensure(c, c->pp_P2, pbytes)) != hipSuccess)
+      return hip_fail(e, "pipeline workspace");
+    shapes.push_back(q);
+    ncnt += ap::pipe_counters(q.Ns, q.K);
+    if (q.nx != nx_common) nx_common = 0;
+    nx_max = std::max(nx_max, q.nx);
   }
-  const bool f64 = p->precision == AP_PREC_FP64;
-  cx<double>* U = c->pp_U.as<cx<double>>();
-  int* flags = c->pp_flags.as<int>();
-  int* ticket = flags + (2 * K + 1) * Ns;
+  if (ncnt > (1LL << 30)) return fail(AP_EINVAL, "batch too large");
+  // counters, then ticket, stall record [3], per-workgroup progress [2][1024]
+  const long long nflags = ncnt + 4 + 2 * 1024;
+  if ((e = ensure(owner, owner->pp_flags, sizeof(int) * size_t(nflags))) != hipSuccess)
+    return hip_fail(e, "pipeline counters");
+  int* flags = owner->pp_flags.as<int>();
+  int* ticket = flags + ncnt;
   int* abort = ticket + 1;
-  c->pp_prob_host.resize(sizeof(ap::PipeProb<double>));
-  if (f64) {
-    ap::PipeProb<double> pr{U, c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(), c->pp_part.as<double2>(),
-                            flags, Ns, K, steps, ft->coef64.as<cx<double>>(), ft->coef64.as<cx<double>>(), at->c64};
-    std::memcpy(c->pp_prob_host.data(), &pr, sizeof(pr));
-  } else {
-    ap::PipeProb<float> pr{U, c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(), c->pp_part.as<double2>(),
-                           flags, Ns, K, steps, ft->coef64.as<cx<double>>(), ft->coef32.as<cx<float>>(), at->c32};
-    std::memcpy(c->pp_prob_host.data(), &pr, sizeof(pr));
+  // job list, cached by the problems' shapes
+  std::string key;
+  for (auto& q : shapes)
+    key += std::to_string(q.nx) + ":" + std::to_string(q.Ns) + ":" + std::to_string(q.K) + ":" +
+           std::to_string(q.steps) + ":" + std::to_string(q.M) + ":" + std::to_string(q.gs) + ":" +
+           std::to_string(int(q.split)) + ":" + std::to_string(int(q.fp64)) + ":" +
+           (q.cal.valid ? std::to_string(q.cal.fine_step) + "," + std::to_string(q.cal.stage1) + "," +
+                              std::to_string(q.cal.stage2) + "," + std::to_string(q.cal.whole)
+                        : std::string("-")) + ";";
+  if (key != owner->pp_jobs_key) {
+    std::vector<ap::PipeJob> jobs = schedule_jobs(shapes);
+    if (!order_is_valid(jobs, shapes)) return fail(AP_EINVAL, "internal: job order is not topological");
+    if (jobs.size() > size_t(1) << 30) return fail(AP_EINVAL, "batch too large");
+    owner->pp_jobs_key.clear();
+    std::vector<unsigned char> last;
+    if ((e = upload_if_changed(owner, owner->pp_jobs, last, as_bytes(jobs))) != hipSuccess)
+      return hip_fail(e, "job list upload");
+    owner->pp_jobs_host = std::move(jobs);
+    owner->pp_njobs = int(owner->pp_jobs_host.size());
+    owner->pp_jobs_key = key;
   }
-  if ((e = hipMemcpyAsync(c->pp_prob.p, c->pp_prob_host.data(), c->pp_prob_host.size(), hipMemcpyHostToDevice, s)) !=
-      hipSuccess)
+  // descriptors and residual rows
+  std::vector<ap::ResidRow> rows;
+  std::vector<unsigned char> probs;
+  long long off = 0;
+  for (auto& it : items) {
+    int* cnt = flags + off;
+    off += ap::pipe_counters(it.q.Ns, it.q.K);
+    if (f64) {
+      const ap::PipeProb<double> pr = make_prob<double>(it, cnt);
+      const auto* b = reinterpret_cast<const unsigned char*>(&pr);
+      probs.insert(probs.end(), b, b + sizeof(pr));
+    } else {
+      const ap::PipeProb<float> pr = make_prob<float>(it, cnt);
+      const auto* b = reinterpret_cast<const unsigned char*>(&pr);
+      probs.insert(probs.end(), b, b + sizeof(pr));
+    }
+    for (int k = 0; k < it.q.K; ++k)
+      rows.push_back({it.c->pp_part.as<double2>() + size_t(k) * it.q.Ns, it.resid + k, it.q.Ns});
+  }
+  if ((e = upload_if_changed(owner, owner->pp_prob, owner->pp_prob_host, probs)) != hipSuccess)
     return hip_fail(e, "problem descriptor upload");
-  const size_t st = size_t(3) * c->KP;
-  e = timed(c, AP_K_TO_MODAL, s, [&] { return ap::launch_to_modal(c->N, u0, U, 1, c->tabs, s); });
-  if (e != hipSuccess) return hip_fail(e, "to_modal");
-  if (K > 0 && (e = hipMemcpyAsync(U + size_t(K) * (Ns + 1) * st, U, sb, hipMemcpyDeviceToDevice, s)) != hipSuccess)
-    return hip_fail(e, "initial state copy");
-  if ((e = ap::launch_zero_ints(flags, nflags, s)) != hipSuccess) return hip_fail(e, "flag reset");
-  c->pp_diag = abort;
-  const int grid = std::min(c->pp_njobs, 256);
+  if ((e = upload_if_changed(owner, owner->pp_rows, owner->pp_rows_host, as_bytes(rows))) != hipSuccess)
+    return hip_fail(e, "residual table upload");
+  int grid = ap::pipeline_max_grid(nx_common, nx_max, f64);
+  if (grid <= 0) return fail(AP_EDEVICE, "pipeline kernel does not fit the device");
+  if (owner->opt_grid > 0) grid = std::min(grid, owner->opt_grid);
+  grid = std::max(1, std::min({grid, owner->pp_njobs, 1024}));   // progress record holds 1024 workgroups
   unsigned long long* trace = nullptr;
-  if (c->trace_on) {
-    if ((e = ensure(c, c->pp_trace, sizeof(unsigned long long) * 3 * size_t(c->pp_njobs))) != hipSuccess)
+  if (owner->trace_on) {
+    if ((e = ensure(owner, owner->pp_trace, sizeof(unsigned long long) * 3 * size_t(owner->pp_njobs))) !=
+        hipSuccess)
       return hip_fail(e, "trace buffer");
-    trace = c->pp_trace.as<unsigned long long>();
-    c->pp_trace_jobs = c->pp_njobs;
+    trace = owner->pp_trace.as<unsigned long long>();
+    owner->pp_trace_jobs = owner->pp_njobs;
   }
-  e = timed(c, AP_K_PIPELINE, s, [&] {
-    return ap::launch_pipeline(c->N, f64, c->pp_jobs.p, c->pp_njobs, c->pp_prob.p, ticket, abort, abort + 3, trace,
-                               grid, c->tabs, s);
+  // enqueue: boundary transforms in, counters, the persistent launch,
+  // residuals, boundary transforms out
+  for (auto& it : items) {
+    ap_ctx* c = it.c;
+    cx<double>* U = c->pp_U.as<cx<double>>();
+    const size_t sb = state_bytes(c);
+    e = timed(owner, AP_K_TO_MODAL, s, [&] { return ap::launch_to_modal(c->N, it.u0, U, 1, c->tabs, s); });
+    if (e != hipSuccess) return hip_fail(e, "to_modal");
+    if (it.q.K > 0 &&
+        (e = hipMemcpyAsync(U + size_t(it.q.K) * (it.q.Ns + 1) * (sb / sizeof(cx<double>)), U, sb,
+                            hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return hip_fail(e, "initial state copy");
+  }
+  if ((e = ap::launch_zero_ints(flags, int(nflags), s)) != hipSuccess) return hip_fail(e, "counter reset");
+  owner->pp_diag = abort;
+  e = timed(owner, AP_K_PIPELINE, s, [&] {
+    return ap::launch_pipeline(nx_common, nx_max, f64, owner->pp_jobs.p, owner->pp_njobs, owner->pp_prob.p, ticket,
+                               abort, abort + 3, trace, grid, s);
   });
   if (e != hipSuccess) return hip_fail(e, "pipeline launch");
-  if (K > 0) {
-    e = timed(c, AP_K_RESID, s,
-              [&] { return ap::launch_resid(c->pp_part.as<double2>(), Ns, K, resid, abort, s); });
+  if (!rows.empty()) {
+    e = timed(owner, AP_K_RESID, s, [&] {
+      return ap::launch_resid_rows(owner->pp_rows.as<ap::ResidRow>(), int(rows.size()), abort, s);
+    });
     if (e != hipSuccess) return hip_fail(e, "resid");
   }
-  cx<double>* UK = U + size_t(K) * (Ns + 1) * st;
-  e = timed(c, AP_K_TO_PHYSICAL, s, [&] { return ap::launch_to_physical(c->N, UK, U_out, Ns + 1, c->tabs, s); });
-  if (e != hipSuccess) return hip_fail(e, "to_physical");
+  for (auto& it : items) {
+    ap_ctx* c = it.c;
+    const cx<double>* UK = c->pp_U.as<cx<double>>() + size_t(it.q.K) * (it.q.Ns + 1) * 3 * c->KP;
+    e = timed(owner, AP_K_TO_PHYSICAL, s,
+              [&] { return ap::launch_to_physical(c->N, UK, it.U_out, it.q.Ns + 1, c->tabs, s); });
+    if (e != hipSuccess) return hip_fail(e, "to_physical");
+  }
   return AP_OK;
 }
 
@@ -671,31 +971,176 @@ int aparareal_solve(ap_ctx* c, const double* u0, const ap_solve_params* p, doubl
   hipStream_t s = static_cast<hipStream_t>(stream);
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (!p || !u0 || !U_out) return fail(AP_EINVAL, "null argument");
-  if ((rc = check_prec(p->precision))) return rc;
-  if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(AP_EINVAL, "T must be > 0");
-  if (p->slices < 1) return fail(AP_EINVAL, "slices must be >= 1");
-  if (p->K < 0) return fail(AP_EINVAL, "K must be >= 0");
-  if (p->K > 0 && !resid) return fail(AP_EINVAL, "resid must hold K entries");
-  if (!(p->dt_fine > 0.0) || !std::isfinite(p->dt_fine)) return fail(AP_EINVAL, "dt_fine must be > 0");
-  if (p->M_avg < 2) return fail(AP_EINVAL, "M_avg must be >= 2");
-  if (!std::isfinite(p->T0) || !std::isfinite(p->tol)) return fail(AP_EINVAL, "T0, tol must be finite");
-  if (size_t(2 * p->K + 1) * size_t(p->slices) > (size_t(1) << 30)) return fail(AP_EINVAL, "problem too large");
-  const int Ns = p->slices;
-  const double dT = p->T / Ns;
-  const double ratio = dT / p->dt_fine;
-  if (ratio > 1e7) return fail(AP_EINVAL, "dT/dt_fine too large");
-  const int steps = std::max(1, int(std::ceil(ratio - 1e-9)));
-  const double h = dT / steps;
-  const double win = p->T0 > 0.0 ? p->T0 : dT / c->eps;
   hipError_t e = order_stream(c, s);
   if (e != hipSuccess) return hip_fail(e, "stream ordering");
-  FineTables* ft = nullptr;
-  AvgTables* at = nullptr;
-  if ((rc = fine_tables(c, h, &ft))) return rc;
-  if ((rc = avg_tables(c, dT, win, p->M_avg, &at))) return rc;
-  if (p->tol > 0.0) return solve_sweeps(c, u0, p, U_out, resid, s, steps, ft, at);
-  return solve_pipelined(c, u0, p, U_out, resid, s, steps, ft, at);
+  std::vector<PlanItem> items(1);
+  if ((rc = plan_item(c, u0, p, U_out, resid, &items[0]))) return rc;
+  if (p->tol > 0.0) return solve_sweeps(c, u0, p, U_out, resid, s, items[0].q.steps, items[0].ft, items[0].at);
+  return plan_launch(c, items, s);
+}
+
+int aparareal_solve_batch(const ap_batch_item* batch, int count, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (count < 0 || (count > 0 && !batch)) return fail(AP_EINVAL, "bad batch");
+  if (count == 0) return AP_OK;
+  std::vector<PlanItem> items(static_cast<size_t>(count));
+  for (int i = 0; i < count; ++i) {
+    ap_ctx* c = batch[i].ctx;
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    for (int j = 0; j < i; ++j)
+      if (batch[j].ctx == c) return fail(AP_EINVAL, "a context may appear only once in a batch");
+    if (batch[i].params.tol > 0.0) return fail(AP_EINVAL, "batched solves run exactly K iterations (tol <= 0)");
+    hipError_t e = order_stream(c, s);
+    if (e != hipSuccess) return hip_fail(e, "stream ordering");
+    if ((rc = plan_item(c, batch[i].u0, &batch[i].params, batch[i].U_out, batch[i].resid, &items[size_t(i)])))
+      return rc;
+  }
+  return plan_launch(batch[0].ctx, items, s);
+}
+
+int aparareal_autotune(const ap_batch_item* batch, int count, void* stream, double* best_ms) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (count < 1 || !batch) return fail(AP_EINVAL, "bad autotune batch");
+  for (int i = 0; i < count; ++i) {
+    int rc = check_ctx(batch[i].ctx);
+    if (rc) return rc;
+    for (int j = 0; j < i; ++j)
+      if (batch[j].ctx == batch[i].ctx) return fail(AP_EINVAL, "a context may appear only once in a batch");
+    if (batch[i].params.tol > 0.0) return fail(AP_EINVAL, "autotuning covers pipelined solves (tol <= 0)");
+    hipError_t e = order_stream(batch[i].ctx, s);
+    if (e != hipSuccess) return hip_fail(e, "stream ordering");
+  }
+  ap_ctx* owner = batch[0].ctx;
+  auto run = [&]() -> int {
+    std::vector<PlanItem> items(static_cast<size_t>(count));
+    for (int i = 0; i < count; ++i) {
+      int rc = plan_item(batch[i].ctx, batch[i].u0, &batch[i].params, batch[i].U_out, batch[i].resid, &items[i]);
+      if (rc) return rc;
+    }
+    return plan_launch(owner, items, s);
+  };
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    return fail(AP_EDEVICE, "event creation");
+  }
+  const bool trace_was = owner->trace_on;
+  const int split_was = owner->opt_split;
+  std::vector<CostCal> cal_was;
+  for (int i = 0; i < count; ++i) cal_was.push_back(batch[i].ctx->cost);
+  double best = -1.0;
+  int best_split = split_was;
+  std::vector<CostCal> best_cal = cal_was;
+  int rc = AP_OK;
+  for (int split = 0; split <= 1 && rc == AP_OK; ++split) {
+    for (int i = 0; i < count; ++i) {
+      batch[i].ctx->opt_split = split;
+      batch[i].ctx->cost = CostCal{};
+    }
+    if ((rc = run())) break;   // warm-up (tables, workspaces, job list)
+    // two rounds: measure job durations, re-order with them
+    for (int round = 0; round < 2 && rc == AP_OK; ++round) {
+      owner->trace_on = true;
+      rc = run();
+      owner->trace_on = trace_was;
+      if (rc) break;
+      hipError_t e = hipStreamSynchronize(s);
+      const int nj = owner->pp_trace_jobs;
+      std::vector<unsigned long long> raw(size_t(3) * nj);
+      if (e == hipSuccess)
+        e = hipMemcpy(raw.data(), owner->pp_trace.p, raw.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "autotune trace");
+        break;
+      }
+      // per problem and job type: median duration (us, 100 MHz ticks)
+      std::vector<std::vector<double>> d(size_t(count) * 4);
+      for (int j = 0; j < nj; ++j) {
+        const ap::PipeJob& jb = owner->pp_jobs_host[j];
+        if (jb.prob < 0 || jb.prob >= count || jb.type < 0 || jb.type > 3) continue;
+        const double us = double(raw[3 * j + 1] - raw[3 * j]) / 100.0;
+        d[size_t(jb.prob) * 4 + jb.type].push_back(us);
+      }
+      auto median = [](std::vector<double>& v) {
+        if (v.empty()) return 0.0;
+        std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+        return v[v.size() / 2];
+      };
+      for (int i = 0; i < count; ++i) {
+        CostCal cc;
+        cc.valid = true;
+        const double fine = median(d[size_t(i) * 4 + ap::kJobFine]);
+        const ap_solve_params& p = batch[i].params;
+        const int steps = std::max(1, int(std::ceil(p.T / p.slices / p.dt_fine - 1e-9)));
+        cc.fine_step = fine / steps;
+        cc.whole = median(d[size_t(i) * 4 + ap::kJobCoarse]);
+        cc.stage1 = median(d[size_t(i) * 4 + ap::kJobStage1]);
+        cc.stage2 = median(d[size_t(i) * 4 + ap::kJobStage2]);
+        batch[i].ctx->cost = cc;
+      }
+    }
+    if (rc) break;
+    double ms = -1.0;
+    for (int rep = 0; rep < 3 && rc == AP_OK; ++rep) {
+      (void)hipEventRecord(ev[0], s);
+      rc = run();
+      (void)hipEventRecord(ev[1], s);
+      float t = 0.f;
+      if (rc == AP_OK && (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess))
+        rc = fail(AP_EDEVICE, "autotune timing");
+      if (rc == AP_OK && (ms < 0.0 || t < ms)) ms = t;
+    }
+    if (rc == AP_OK && (best < 0.0 || ms < best)) {
+      best = ms;
+      best_split = split;
+      best_cal.clear();
+      for (int i = 0; i < count; ++i) best_cal.push_back(batch[i].ctx->cost);
+    }
+  }
+  for (int i = 0; i < count; ++i) {
+    batch[i].ctx->opt_split = rc == AP_OK ? best_split : split_was;
+    batch[i].ctx->cost = rc == AP_OK ? best_cal[size_t(i)] : cal_was[size_t(i)];
+  }
+  owner->trace_on = trace_was;
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (rc) return rc;
+  if (best_ms) *best_ms = best;
+  return AP_OK;
+}
+
+int aparareal_set_option(ap_ctx* c, int option, int value) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  switch (option) {
+    case AP_OPT_SPLIT:
+      if (value < -1 || value > 1) return fail(AP_EINVAL, "AP_OPT_SPLIT takes -1, 0 or 1");
+      c->opt_split = value;
+      return AP_OK;
+    case AP_OPT_GROUP:
+      if (value < 0 || value > 4096) return fail(AP_EINVAL, "AP_OPT_GROUP takes 0..4096");
+      c->opt_group = value;
+      return AP_OK;
+    case AP_OPT_GRID:
+      if (value < 0) return fail(AP_EINVAL, "AP_OPT_GRID takes a value >= 0");
+      c->opt_grid = value;
+      return AP_OK;
+    default:
+      return fail(AP_EINVAL, "unknown option");
+  }
+}
+
+int aparareal_get_option(ap_ctx* c, int option, int* value) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!value) return fail(AP_EINVAL, "null value");
+  switch (option) {
+    case AP_OPT_SPLIT: *value = c->opt_split; return AP_OK;
+    case AP_OPT_GROUP: *value = group_size(c); return AP_OK;
+    case AP_OPT_GRID: *value = c->opt_grid; return AP_OK;
+    default: return fail(AP_EINVAL, "unknown option");
+  }
 }
 
 int aparareal_pipeline_status(ap_ctx* c, int* info) {
@@ -710,15 +1155,34 @@ int aparareal_pipeline_status(ap_ctx* c, int* info) {
   return AP_OK;
 }
 
-int aparareal_pipeline_schedule(int slices, int K, int steps, int M_avg, int* out) {
-  if (slices < 1 || K < 0 || steps < 1 || M_avg < 2 || !out) return fail(AP_EINVAL, "bad schedule query");
-  if (size_t(2 * K + 1) * size_t(slices) > (size_t(1) << 30)) return fail(AP_EINVAL, "problem too large");
-  const std::vector<ap::PipeJob> jobs = pipeline_jobs(0, slices, K, steps, M_avg);
-  for (size_t i = 0; i < jobs.size(); ++i) {
-    out[3 * i] = jobs[i].type;
-    out[3 * i + 1] = jobs[i].k;
-    out[3 * i + 2] = jobs[i].n;
-  }
+int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int group, int* out, int max_jobs) {
+  if (!p || !is_pow2(N) || N < 64 || N > 2048 || p->slices < 1 || p->K < 0 || p->M_avg < 2 || group < 0 ||
+      split < -1 || split > 1 || !(p->T > 0.0) || !(p->dt_fine > 0.0) || max_jobs < 0)
+    return fail(AP_EINVAL, "bad schedule query");
+  if (size_t(2 * p->K + 1) * size_t(p->slices) > (size_t(1) << 24)) return fail(AP_EINVAL, "problem too large");
+  const double dT = p->T / p->slices;
+  const double ratio = dT / p->dt_fine;
+  if (ratio > 1e7) return fail(AP_EINVAL, "dT/dt_fine too large");
+  PipeShape q;
+  q.nx = N;
+  q.Ns = p->slices;
+  q.K = p->K;
+  q.steps = std::max(1, int(std::ceil(ratio - 1e-9)));
+  q.M = p->M_avg;
+  q.gs = group > 0 ? group : default_group_size(N);
+  q.groups = ap::avg_groups(q.M, q.gs);
+  q.fp64 = p->precision == AP_PREC_FP64;
+  q.split = split < 0 ? q.groups >= 2 : split != 0;
+  const std::vector<PipeShape> shapes{q};
+  const std::vector<ap::PipeJob> jobs = schedule_jobs(shapes);
+  if (!order_is_valid(jobs, shapes)) return fail(AP_EINVAL, "internal: job order is not topological");
+  if (out)
+    for (size_t i = 0; i < jobs.size() && i < size_t(max_jobs); ++i) {
+      out[4 * i] = jobs[i].type;
+      out[4 * i + 1] = jobs[i].k;
+      out[4 * i + 2] = jobs[i].n;
+      out[4 * i + 3] = jobs[i].g;
+    }
   return int(jobs.size());
 }
 
@@ -732,18 +1196,22 @@ int aparareal_pipeline_trace(ap_ctx* c, int enable, long long* out, int max_jobs
   if (!out || max_jobs < 0) return fail(AP_EINVAL, "bad trace query");
   if (!c->pp_trace.p || c->pp_trace_jobs == 0) return 0;
   const int n = std::min(max_jobs, c->pp_trace_jobs);
-  std::vector<unsigned long long> raw(size_t(3) * n);
+  std::vector<unsigned long long> raw(size_t(3) * n);   // start, end, workgroup
   hipError_t e = c->has_last ? hipStreamSynchronize(c->last_stream) : hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(raw.data(), c->pp_trace.p, raw.size() * sizeof(unsigned long long),
                                      hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "trace readback");
   for (int i = 0; i < n; ++i) {
-    out[6 * i + 0] = c->pp_jobs_host[i].type;
-    out[6 * i + 1] = c->pp_jobs_host[i].k;
-    out[6 * i + 2] = c->pp_jobs_host[i].n;
-    out[6 * i + 3] = (long long)raw[3 * i];
-    out[6 * i + 4] = (long long)raw[3 * i + 1];
-    out[6 * i + 5] = (long long)raw[3 * i + 2];
+    const ap::PipeJob& j = c->pp_jobs_host[i];
+    long long* o = out + size_t(8) * i;
+    o[0] = j.prob;
+    o[1] = j.type;
+    o[2] = j.k;
+    o[3] = j.n;
+    o[4] = j.g;
+    o[5] = (long long)raw[3 * i];
+    o[6] = (long long)raw[3 * i + 1];
+    o[7] = (long long)raw[3 * i + 2];
   }
   return n;
 }

@@ -17,7 +17,8 @@
 //                                order from one ticket counter, each waiting on
 //                                the done flags of the jobs it reads
 //   k_resid_rows               : r^k = max_n sqrt(num_n / den_n) per iteration
-#include "engine.hpp"
+#include "dispatch.hpp"
+#include "pipeline.hpp"
 
 namespace ap {
 
@@ -161,14 +162,8 @@ __global__ void __launch_bounds__(NT) k_average(const cx<double>* __restrict__ U
   const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * E_::KP;
   cx<double>* dst = Nout + size_t(blockIdx.x) * 3 * E_::KP;
   cx<T> y[E_::MPT][3], acc[E_::MPT][3];
-  Basis<T> bs[E_::MPT];
-#pragma unroll
-  for (int j = 0; j < E_::MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : 0;
-    bs[j] = basis[k];
-    for (int al = 0; al < 3; ++al) y[j][al] = E_::valid(j) ? cvt<T>(src[al * E_::KP + k]) : czero<T>();
-  }
-  nbar_owned<T, NX, NT, S>(en, y, acc, bs, av, basis);
+  load_owned<T, NX, NT, S>(src, y);
+  nbar_owned<T, NX, NT, S>(en, y, acc, av, basis);
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j)
     if (E_::valid(j))
@@ -208,133 +203,13 @@ __global__ void __launch_bounds__(NT) k_sweep(cx<double>* __restrict__ U, const 
   }
 }
 
-// ---------------------------------------------------- pipelined solve -----
-// Per problem (all of one grid size and precision in a launch):
-//   U [K+1][Ns+1], F [K][Ns+1], G [K+1][Ns+1] modal FP64 states (U(k,0) is
-//   read from U(0,0) = u0 for every k), part [K][Ns], done flags
-//   C(k,n) at k*Ns + n-1 (k = 0..K) and F(k,n) at (K+1)*Ns + k*Ns + n-1.
-// C(k,n): G(U(k,n-1)) -> G(k,n); U(k,n) = G (k = 0) or F(k-1,n) + (G - G(k-1,n)),
-//         needs C(k,n-1), F(k-1,n), C(k-1,n).
-// F(k,n): Fine(U(k,n-1)) -> F(k,n), needs C(k,n-1).
-// A wait that sees no progress for kStallTicks of the constant-rate device
-// clock (100 MHz: 0.5 s) declares a stall: the scheduler's order guarantees
-// progress, so this only fires on a defect, and it ends the launch instead of
-// hanging the device.
-constexpr unsigned long long kStallTicks = 50000000ull;
-
-// Thread 0 waits for *flag != 0 (relaxed polls, then an acquire fence).  On a
-// stall it records (1, job, flag) in diag[0..2] and returns false; it also
-// returns false once another workgroup has recorded one.
-constexpr int kStallPolls = 1 << 21;   // second bound, independent of the clock
-
-__device__ __forceinline__ bool wait_flag(int* flag, int* diag, int job, int flag_index) {
-  const unsigned long long t0 = wall_clock64();
-  int polls = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-    if (__hip_atomic_load(diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    if (wall_clock64() - t0 > kStallTicks || ++polls > kStallPolls) {
-      if (__hip_atomic_fetch_add(diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        __hip_atomic_store(diag + 1, job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(diag + 2, flag_index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  return true;
-}
-
-template <typename T, int NX, int NT, int S>
-__global__ void __launch_bounds__(NT) k_pipeline(const PipeJob* __restrict__ jobs, int njobs,
-                                                 const PipeProb<T>* __restrict__ probs, int* ticket, int* abort,
-                                                 int* progress, unsigned long long* trace,
-                                                 const cx<T>* __restrict__ tw, const Basis<T>* __restrict__ basis) {
-  using E_ = Engine<T, NX, NT, S>;
-  extern __shared__ unsigned char smem_raw[];
-  E_ en(smem_raw, tw);
-  __shared__ int s_job, s_ok;
-  const size_t st = size_t(3) * E_::KP;
-  // Thread 0's scheduling work (publish the previous job's flag, take a ticket,
-  // wait on the new job's dependencies) is one region at the top of the body,
-  // between the end-of-job barrier and the hand-out barrier; the body ends
-  // with a barrier and nothing thread-specific.  Thread-0 regions on both
-  // sides of the back-edge would form a single divergent region across it,
-  // which the compiler may turn into a loop the other lanes never leave.  The
-  // exit values are read with readfirstlane so every branch on them is uniform.
-  int done_flag = -1;          // flag of the job this workgroup finished last
-  const PipeProb<T>* done_prob = nullptr;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      if (done_flag >= 0) {
-        __threadfence();
-        __hip_atomic_store(&done_prob->done[done_flag], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (progress) {
-          progress[2 * blockIdx.x] += 1;
-          progress[2 * blockIdx.x + 1] = done_flag;
-        }
-      }
-      const int jt = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      bool ok = true;
-      if (jt < njobs) {
-        const PipeJob jb = jobs[jt];
-        const PipeProb<T>& p = probs[jb.prob];
-        const int Ns = p.Ns, K = p.K, k = jb.k, n = jb.n;
-        if (n > 1) {
-          const int f = k * Ns + (n - 2);
-          ok = wait_flag(&p.done[f], abort, jt, f);
-        }
-        if (ok && jb.type == 0 && k >= 1) {
-          const int f1 = (K + 1) * Ns + (k - 1) * Ns + (n - 1), f2 = (k - 1) * Ns + (n - 1);
-          ok = wait_flag(&p.done[f1], abort, jt, f1);
-          if (ok) ok = wait_flag(&p.done[f2], abort, jt, f2);
-        }
-      }
-      s_job = jt;
-      s_ok = ok;
-    }
-    __syncthreads();
-    const int j = __builtin_amdgcn_readfirstlane(s_job);
-    const int ok = __builtin_amdgcn_readfirstlane(s_ok);
-    if (j >= njobs || !ok) break;
-    if (trace && threadIdx.x == 0) {
-      trace[3 * j] = wall_clock64();
-      trace[3 * j + 2] = blockIdx.x;
-    }
-    const PipeJob jb = jobs[j];
-    const PipeProb<T>& p = probs[jb.prob];
-    const int Ns = p.Ns, K = p.K, k = jb.k, n = jb.n;
-    auto state = [&](cx<double>* A, int lvl, int slice) { return A + (size_t(lvl) * (Ns + 1) + slice) * st; };
-    const cx<double>* uprev = n == 1 ? state(p.U, 0, 0) : state(p.U, k, n - 1);
-    if (jb.type == 0) {
-      if (k == 0) {
-        coarse_job<T, NX, NT, S>(en, p.ct, basis, uprev, state(p.U, 0, n), state(p.G, 0, n), nullptr, nullptr,
-                                 nullptr, nullptr);
-      } else {
-        coarse_job<T, NX, NT, S>(en, p.ct, basis, uprev, state(p.U, k, n), state(p.G, k, n),
-                                 state(p.G, k - 1, n), state(p.F, k - 1, n), state(p.U, k - 1, n),
-                                 p.part + size_t(k - 1) * Ns + (n - 1));
-      }
-      done_flag = k * Ns + (n - 1);
-    } else {
-      fine_job<T, NX, NT, S>(en, uprev, state(p.F, k, n), p.steps, p.coef64, p.coef, basis);
-      done_flag = (K + 1) * Ns + k * Ns + (n - 1);
-    }
-    done_prob = &p;
-    __syncthreads();
-    if (trace && threadIdx.x == 0) trace[3 * j + 1] = wall_clock64();
-  }
-}
-
 __global__ void k_zero_ints(int* p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // rows r = 0..R-1: out[r] = max_n sqrt(part[r][n].x / part[r][n].y); NaN after an abort.
-__global__ void __launch_bounds__(256) k_resid_rows(const double2* __restrict__ part, int Ns,
-                                                     double* __restrict__ out, const int* __restrict__ abort) {
+__device__ __forceinline__ void resid_row(const double2* __restrict__ row, int Ns, double* out, bool aborted) {
   __shared__ double red[256];
-  const double2* row = part + size_t(blockIdx.x) * Ns;
   double m = 0.0;
   for (int n = threadIdx.x; n < Ns; n += 256) {
     const double2 p = row[n];
@@ -350,7 +225,18 @@ __global__ void __launch_bounds__(256) k_resid_rows(const double2* __restrict__ 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = (abort && *abort) ? NAN : red[0];
+  if (threadIdx.x == 0) *out = aborted ? NAN : red[0];
+}
+
+__global__ void __launch_bounds__(256) k_resid_rows(const double2* __restrict__ part, int Ns,
+                                                     double* __restrict__ out, const int* __restrict__ abort) {
+  resid_row(part + size_t(blockIdx.x) * Ns, Ns, out + blockIdx.x, abort && *abort);
+}
+
+__global__ void __launch_bounds__(256) k_resid_table(const ResidRow* __restrict__ rows,
+                                                      const int* __restrict__ abort) {
+  const ResidRow r = rows[blockIdx.x];
+  resid_row(r.part, r.Ns, r.out, abort && *abort);
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -363,18 +249,6 @@ __global__ void __launch_bounds__(256) k_resid_rows(const double2* __restrict__ 
 template <typename T, int NX>
 constexpr int avg_threads() {
   return 512;
-}
-
-// Raise the dynamic-LDS limit for launches above 64 KiB (gfx950 has 160 KiB per
-// workgroup).  Best effort: a launch that still exceeds the limit fails and is
-// reported by the hipGetLastError() that follows it.
-template <typename K>
-static void prep_lds(K kernel, size_t bytes) {
-  if (bytes > 65536) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              int(bytes));
-    (void)hipGetLastError();
-  }
 }
 
 template <int NX>
@@ -449,31 +323,6 @@ static hipError_t sweep_nx(cx<double>* U, const cx<double>* Fine, cx<double>* Go
   return hipGetLastError();
 }
 
-template <typename T, int NX>
-static hipError_t pipeline_nx(const PipeJob* jobs, int njobs, const void* probs, int* ticket, int* abort,
-                              int* progress, unsigned long long* trace, int grid, const DevTables& t,
-                              hipStream_t s) {
-  constexpr int NT = avg_threads<T, NX>();
-  constexpr int S = max_slots<T, NX, NT>();
-  const size_t lds = Engine<T, NX, NT, S>::lds_bytes();
-  prep_lds(k_pipeline<T, NX, NT, S>, lds);
-  hipLaunchKernelGGL((k_pipeline<T, NX, NT, S>), dim3(grid), dim3(NT), lds, s, jobs, njobs,
-                     static_cast<const PipeProb<T>*>(probs), ticket, abort, progress, trace, t.tw<T>(),
-                     t.basis<T>());
-  return hipGetLastError();
-}
-
-#define AP_DISPATCH_NX(NXV, CALL)                        \
-  switch (NXV) {                                         \
-    case 64: { constexpr int NX = 64; return CALL; }     \
-    case 128: { constexpr int NX = 128; return CALL; }   \
-    case 256: { constexpr int NX = 256; return CALL; }   \
-    case 512: { constexpr int NX = 512; return CALL; }   \
-    case 1024: { constexpr int NX = 1024; return CALL; } \
-    case 2048: { constexpr int NX = 2048; return CALL; } \
-    default: return hipErrorInvalidValue;                \
-  }
-
 hipError_t launch_to_modal(int nx, const double* phys, cx<double>* modal, int batch, const DevTables& t,
                            hipStream_t s) {
   AP_DISPATCH_NX(nx, to_modal_nx<NX>(phys, modal, batch, t, s));
@@ -508,14 +357,52 @@ hipError_t launch_sweep(int nx, cx<double>* U, const cx<double>* Fine, cx<double
   if (c64) AP_DISPATCH_NX(nx, (sweep_nx<double, NX>(U, Fine, Gold, part, Ns, initial, *c64, t, s)));
   AP_DISPATCH_NX(nx, (sweep_nx<float, NX>(U, Fine, Gold, part, Ns, initial, *c32, t, s)));
 }
-hipError_t launch_pipeline(int nx, bool fp64, const void* jobs, int njobs, const void* probs, int* ticket,
-                           int* abort, int* progress, unsigned long long* trace, int grid, const DevTables& t,
-                           hipStream_t s) {
-  const PipeJob* j = static_cast<const PipeJob*>(jobs);
-  if (fp64)
-    AP_DISPATCH_NX(nx, (pipeline_nx<double, NX>(j, njobs, probs, ticket, abort, progress, trace, grid, t, s)));
-  AP_DISPATCH_NX(nx, (pipeline_nx<float, NX>(j, njobs, probs, ticket, abort, progress, trace, grid, t, s)));
+// pipelined solve: the kernels live in the pipe_*.hip translation units
+size_t pipeline_lds(int nx, int nx_max, bool fp64) {
+  return fp64 ? pipeline_lds_t<double>(nx, nx_max) : pipeline_lds_t<float>(nx, nx_max);
 }
+
+using PipeLaunchFn = hipError_t (*)(int, size_t, const PipeJob*, int, const void*, int*, int*, int*,
+                                    unsigned long long*, int, hipStream_t);
+using PipeOccFn = int (*)(int, size_t);
+
+// kernel for grid size nx (0: several sizes up to nx_max in one launch)
+static bool pipe_kernel(int nx, int nx_max, bool fp64, PipeLaunchFn* fn, PipeOccFn* occ) {
+  if (nx > 0) {
+    *fn = fp64 ? pipe_launch_f64 : pipe_launch_f32;
+    *occ = fp64 ? pipe_occupancy_f64 : pipe_occupancy_f32;
+  } else if (fp64) {
+    *fn = pipe_launch_mix2048_f64;
+    *occ = pipe_occupancy_mix2048_f64;
+  } else if (nx_max <= 1024) {
+    *fn = pipe_launch_mix1024_f32;
+    *occ = pipe_occupancy_mix1024_f32;
+  } else {
+    *fn = pipe_launch_mix2048_f32;
+    *occ = pipe_occupancy_mix2048_f32;
+  }
+  return true;
+}
+
+int pipeline_max_grid(int nx, int nx_max, bool fp64) {
+  const size_t lds = pipeline_lds(nx, nx_max, fp64);
+  PipeLaunchFn fn;
+  PipeOccFn occ;
+  if (lds == 0 || !pipe_kernel(nx, nx_max, fp64, &fn, &occ)) return 0;
+  return occ(nx, lds);
+}
+
+hipError_t launch_pipeline(int nx, int nx_max, bool fp64, const void* jobs, int njobs, const void* probs,
+                           int* ticket, int* abort, int* progress, unsigned long long* trace, int grid,
+                           hipStream_t s) {
+  const size_t lds = pipeline_lds(nx, nx_max, fp64);
+  PipeLaunchFn fn;
+  PipeOccFn occ;
+  if (lds == 0 || !pipe_kernel(nx, nx_max, fp64, &fn, &occ)) return hipErrorInvalidValue;
+  return fn(nx, lds, static_cast<const PipeJob*>(jobs), njobs, probs, ticket, abort, progress, trace, grid, s);
+}
+
+
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int blocks = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
@@ -525,6 +412,11 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
 hipError_t launch_resid(const double2* part, int Ns, int rows, double* out, const int* abort, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_resid_rows, dim3(rows), dim3(256), 0, s, part, Ns, out, abort);
+  return hipGetLastError();
+}
+hipError_t launch_resid_rows(const ResidRow* rows, int nrows, const int* abort, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_resid_table, dim3(nrows), dim3(256), 0, s, rows, abort);
   return hipGetLastError();
 }
 

@@ -21,12 +21,18 @@ template <> inline const Basis<double>* DevTables::basis<double>() const { retur
 template <> inline const Basis<float>* DevTables::basis<float>() const { return basis32; }
 
 // Kernel-weighted time average: rot[m][k] = exp(-i omega_k s_m), w[m] = rho(m/M)/M.
+// The samples m = 1..M-1 are summed in groups of gs consecutive samples: each
+// group's contributions in increasing m, then the group sums in increasing
+// group order.  Every kernel uses this association, whatever the number of
+// workgroups that evaluate one average, so results do not depend on it.
 template <typename T>
 struct AvgTab {
   const cx<T>* rot;
   const T* w;
   int M;
+  int gs;
 };
+inline int avg_groups(int M, int gs) { return (M - 1 + gs - 1) / gs; }
 
 // Asymptotic coarse step of length dT: hd[k] = exp(-nu k^4 dT/2),
 // rotT[k] = exp(-i omega_k dT/eps) (the alpha = +1 factor of exp(-(dT/eps) L)).
@@ -38,24 +44,39 @@ struct CoarseTab {
   T dT;
 };
 
-// Pipelined solve: one job = one coarse step (type 0) or one fine slice
-// (type 1) of problem `prob` at iteration level k for slice n (1-based).
+// Pipelined solve: jobs of problem `prob` at iteration level k for slice n
+// (1-based).  A coarse step is either one job (kJobCoarse) or, split over
+// workgroups, one job per sample group g for each of its two averages
+// (kJobStage1, kJobStage2); the last stage-2 job of a step to finish applies
+// the step and the correction.
+enum : int { kJobCoarse = 0, kJobFine = 1, kJobStage1 = 2, kJobStage2 = 3 };
 struct PipeJob {
-  int prob, type, k, n;
+  int prob, type, k, n, g;
 };
 
-// Per-problem device descriptor of the pipelined solve (layout in kernels.hip).
+// Counter layout of one problem (int32, zeroed before the launch):
+//   C(k,n) done     at             k Ns + n-1   (k = 0..K)
+//   F(k,n) done     at (K+1) Ns +  k Ns + n-1   (k = 0..K-1)
+//   stage-1 count   at (2K+1) Ns + k Ns + n-1   (k = 0..K)
+//   stage-2 count   at (3K+2) Ns + k Ns + n-1   (k = 0..K)
+inline long long pipe_counters(int Ns, int K) { return (4LL * K + 3) * Ns; }
+
+// Per-problem device descriptor of the pipelined solve.
 template <typename T>
 struct PipeProb {
   cx<double>* U;       // [K+1][Ns+1][3][KP]
   cx<double>* F;       // [K][Ns+1][3][KP]
   cx<double>* G;       // [K+1][Ns+1][3][KP]
   double2* part;       // [K][Ns] residual partial sums
-  int* done;           // [(2K+1) Ns] job flags
-  int Ns, K, steps;
+  int* cnt;            // counters, layout above
+  cx<T>* P1;           // [K+1][groups][3][KP] stage-1 group sums (split steps)
+  cx<T>* P2;           // [K+1][groups][3][KP] stage-2 group sums
+  int nx, Ns, K, steps, groups;
   const cx<double>* coef64;
   const cx<T>* coef;
   CoarseTab<T> ct;
+  const cx<T>* tw;     // exp(-2 pi i t / nx)
+  const Basis<T>* basis;
 };
 
 hipError_t launch_to_modal(int nx, const double* phys, cx<double>* modal, int batch, const DevTables& t,
@@ -73,11 +94,39 @@ hipError_t launch_coarse(int nx, const cx<double>* in, cx<double>* out, int batc
 hipError_t launch_sweep(int nx, cx<double>* U, const cx<double>* Fine, cx<double>* Gold, double2* part, int Ns,
                         int initial, const CoarseTab<double>* c64, const CoarseTab<float>* c32,
                         const DevTables& t, hipStream_t s);
-hipError_t launch_pipeline(int nx, bool fp64, const void* jobs, int njobs, const void* probs, int* ticket,
-                           int* abort, int* progress, unsigned long long* trace, int grid, const DevTables& t,
+// nx = the grid size of every problem, or 0 for problems of several grid
+// sizes (up to nx_max) in one launch.
+hipError_t launch_pipeline(int nx, int nx_max, bool fp64, const void* jobs, int njobs, const void* probs,
+                           int* ticket, int* abort, int* progress, unsigned long long* trace, int grid,
                            hipStream_t s);
+// LDS bytes of one pipeline workgroup for grid size nx (0 if unsupported).
+size_t pipeline_lds(int nx, int nx_max, bool fp64);
+// Pipeline workgroups resident on the current device at once (0 on error).
+int pipeline_max_grid(int nx, int nx_max, bool fp64);
+// Per-translation-unit pipeline kernels (pipe_*.hip): launch with `lds`
+// bytes of LDS, and workgroups resident at once.
+#define AP_PIPE_TU(tag)                                                                                  \
+  hipError_t pipe_launch_##tag(int nx, size_t lds, const PipeJob* jobs, int njobs, const void* probs,    \
+                               int* ticket, int* abort, int* progress, unsigned long long* trace, int grid, \
+                               hipStream_t s);                                                           \
+  int pipe_occupancy_##tag(int nx, size_t lds);
+AP_PIPE_TU(f32)
+AP_PIPE_TU(f64)
+AP_PIPE_TU(mix1024_f32)
+AP_PIPE_TU(mix2048_f32)
+AP_PIPE_TU(mix2048_f64)
+#undef AP_PIPE_TU
+
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 // out[r] = max_n sqrt(part[r][n].x / part[r][n].y) for r < rows; NaN if *abort
 hipError_t launch_resid(const double2* part, int Ns, int rows, double* out, const int* abort, hipStream_t s);
+// Residual rows of several problems in one launch: row r reads Ns[r] partial
+// sums at part[r] and writes out[r].
+struct ResidRow {
+  const double2* part;
+  double* out;
+  int Ns;
+};
+hipError_t launch_resid_rows(const ResidRow* rows, int nrows, const int* abort, hipStream_t s);
 
 }  // namespace ap

@@ -1,0 +1,255 @@
+// The pipelined persistent parareal solve: device scheduler and jobs, and the
+// host helpers that launch it.  Instantiated per precision and set of grid
+// sizes in the pipe_*.hip translation units.
+#pragma once
+#include "dispatch.hpp"
+#include "engine.hpp"
+
+namespace ap {
+
+// ---------------------------------------------------- pipelined solve -----
+// Per problem (the descriptor PipeProb, counter layout in launch.hpp):
+//   U [K+1][Ns+1], F [K][Ns+1], G [K+1][Ns+1] modal FP64 states (U(k,0) is
+//   read from U(0,0) = u0 for every k), part [K][Ns].
+// C(k,n): G(U(k,n-1)) -> G(k,n); U(k,n) = G (k = 0) or F(k-1,n) + (G - G(k-1,n)),
+//         needs C(k,n-1), F(k-1,n), C(k-1,n).
+// F(k,n): Fine(U(k,n-1)) -> F(k,n), needs C(k,n-1).
+// Split C(k,n): stage-1 job of group g needs C(k,n-1); stage-2 job of group g
+//         needs every stage-1 job of the step; the stage-2 job that finishes
+//         last also needs F(k-1,n) and C(k-1,n) and publishes C(k,n).
+// A wait that sees no progress for kStallTicks of the constant-rate device
+// clock (100 MHz: 0.5 s) declares a stall: the scheduler's order guarantees
+// progress, so this only fires on a defect, and it ends the launch instead of
+// hanging the device.
+constexpr unsigned long long kStallTicks = 50000000ull;
+
+// Thread 0 waits for *ctr >= target (relaxed polls, then an acquire fence).
+// On a stall it records (1, job, counter index) in diag[0..2] and returns
+// false; it also returns false once another workgroup has recorded one.
+constexpr int kStallPolls = 1 << 21;   // second bound, independent of the clock
+
+__device__ __forceinline__ bool wait_count(int* ctr, int target, int* diag, int job, int index) {
+  const unsigned long long t0 = wall_clock64();
+  int polls = 0;
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (wall_clock64() - t0 > kStallTicks || ++polls > kStallPolls) {
+      if (__hip_atomic_fetch_add(diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        __hip_atomic_store(diag + 1, job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(diag + 2, index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  return true;
+}
+
+// Counter indices of one problem.
+struct PipeIdx {
+  int Ns, K;
+  __device__ int coarse(int k, int n) const { return k * Ns + n - 1; }
+  __device__ int fine(int k, int n) const { return (K + 1) * Ns + k * Ns + n - 1; }
+  __device__ int stage1(int k, int n) const { return (2 * K + 1) * Ns + k * Ns + n - 1; }
+  __device__ int stage2(int k, int n) const { return (3 * K + 2) * Ns + k * Ns + n - 1; }
+};
+
+// Dependencies a job waits for before it starts (thread 0).
+template <typename T>
+__device__ __forceinline__ bool wait_deps(const PipeJob& jb, const PipeProb<T>& p, int* diag, int jt) {
+  const PipeIdx ix{p.Ns, p.K};
+  const int k = jb.k, n = jb.n;
+  if (jb.type == kJobStage2) return wait_count(&p.cnt[ix.stage1(k, n)], p.groups, diag, jt, ix.stage1(k, n));
+  if (n > 1 && !wait_count(&p.cnt[ix.coarse(k, n - 1)], 1, diag, jt, ix.coarse(k, n - 1))) return false;
+  if (jb.type == kJobCoarse && k >= 1) {
+    if (!wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n))) return false;
+    if (!wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n))) return false;
+  }
+  return true;
+}
+
+// Threads per pipeline workgroup: eight wavefronts with up to 256 VGPRs each
+// (a job keeps the ETDRK4 state, coefficients and a register DFT live at once).
+constexpr int kPipeThreads = 512;
+template <typename T, int NX>
+constexpr int pipe_slots() {
+  return max_slots<T, NX, kPipeThreads>();
+}
+template <typename T, int NX>
+constexpr size_t pipe_lds() {
+  return Engine<T, NX, kPipeThreads, pipe_slots<T, NX>()>::lds_bytes();
+}
+
+// Runs job jb of problem p (grid size NX) in this workgroup.  Returns the
+// counter index to publish when the job's results are complete, or -1.
+// `staged` tracks the twiddle table held in LDS across jobs.
+template <typename T, int NX>
+__device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
+                                       const void*& staged, int* diag, int jt, int* s_flag) {
+  constexpr int NT = kPipeThreads;
+  constexpr int S = pipe_slots<T, NX>();
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int MPT = E_::MPT;
+  const bool stage = staged != static_cast<const void*>(p.tw);
+  E_ en(smem, p.tw, stage);
+  staged = E_::TW_LDS ? static_cast<const void*>(p.tw) : nullptr;
+  const PipeIdx ix{p.Ns, p.K};
+  const int Ns = p.Ns, k = jb.k, n = jb.n;
+  const size_t st = size_t(3) * E_::KP;
+  auto state = [&](cx<double>* A, int lvl, int slice) { return A + (size_t(lvl) * (Ns + 1) + slice) * st; };
+  const cx<double>* uprev = n == 1 ? state(p.U, 0, 0) : state(p.U, k, n - 1);
+  if (jb.type == kJobFine) {
+    fine_job<T, NX, NT, S>(en, uprev, state(p.F, k, n), p.steps, p.coef64, p.coef, p.basis);
+    return ix.fine(k, n);
+  }
+  if (jb.type == kJobCoarse) {
+    if (k == 0)
+      coarse_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, state(p.U, 0, n), state(p.G, 0, n), nullptr, nullptr,
+                               nullptr, nullptr);
+    else
+      coarse_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, state(p.U, k, n), state(p.G, k, n),
+                               state(p.G, k - 1, n), state(p.F, k - 1, n), state(p.U, k - 1, n),
+                               p.part + size_t(k - 1) * Ns + (n - 1));
+    return ix.coarse(k, n);
+  }
+  // split step: group sums of level k live at P{1,2} + k * groups * st
+  const size_t lvl = size_t(k) * p.groups * st;
+  cx<T> w[MPT][3];
+  CoarseRegs<T, MPT> cr;
+  if (jb.type == kJobStage1) {
+    stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 1, jb.g, nullptr, p.groups, p.P1 + lvl + jb.g * st, w, cr);
+    return ix.stage1(k, n);
+  }
+  stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 2, jb.g, p.P1 + lvl, p.groups, p.P2 + lvl + jb.g * st, w, cr);
+  // Count this group in; the last group to arrive finishes the step.
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int before = __hip_atomic_fetch_add(&p.cnt[ix.stage2(k, n)], 1, __ATOMIC_ACQ_REL,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    int flag = 0;
+    if (before == p.groups - 1) {
+      __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      bool ok = true;
+      if (k >= 1) {
+        ok = wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n));
+        if (ok) ok = wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n));
+      }
+      flag = ok ? 1 : 0;
+    }
+    *s_flag = flag;
+  }
+  __syncthreads();
+  const int finish = __builtin_amdgcn_readfirstlane(*s_flag);
+  if (!finish) return -1;
+  cx<T> g[MPT][3];
+  stage_finish<T, NX, NT, S>(p.ct, p.P2 + lvl, p.groups, w, cr, g);
+  if (k == 0)
+    coarse_correct<T, NX, NT, S>(en, g, state(p.U, 0, n), state(p.G, 0, n), nullptr, nullptr, nullptr, nullptr);
+  else
+    coarse_correct<T, NX, NT, S>(en, g, state(p.U, k, n), state(p.G, k, n), state(p.G, k - 1, n),
+                                 state(p.F, k - 1, n), state(p.U, k - 1, n), p.part + size_t(k - 1) * Ns + (n - 1));
+  return ix.coarse(k, n);
+}
+
+template <typename T, int NX, int... REST>
+__device__ __forceinline__ int dispatch_job(int nx, unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
+                                            const void*& staged, int* diag, int jt, int* s_flag) {
+  if (nx == NX) return run_job<T, NX>(smem, jb, p, staged, diag, jt, s_flag);
+  if constexpr (sizeof...(REST) > 0)
+    return dispatch_job<T, REST...>(nx, smem, jb, p, staged, diag, jt, s_flag);
+  else
+    return -1;
+}
+
+// The persistent solve over the grid sizes NXS (one, or every supported size
+// for a batch of problems of several sizes).
+template <typename T, int... NXS>
+__global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __restrict__ jobs, int njobs,
+                                                           const PipeProb<T>* __restrict__ probs, int* ticket,
+                                                           int* abort, int* progress, unsigned long long* trace) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ int s_job, s_ok, s_flag;
+  // Thread 0's scheduling work (publish the previous job's counter, take a
+  // ticket, wait on the new job's dependencies) is one region at the top of
+  // the body, between the end-of-job barrier and the hand-out barrier; the
+  // body ends with a barrier and nothing thread-specific.  Thread-0 regions on
+  // both sides of the back-edge would form a single divergent region across
+  // it, which the compiler may turn into a loop the other lanes never leave.
+  // The values read back from LDS are made uniform with readfirstlane.
+  int pub = -1;                 // counter index of the job finished last
+  int* pub_cnt = nullptr;
+  const void* staged = nullptr;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (pub >= 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(&pub_cnt[pub], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (progress) {
+          progress[2 * blockIdx.x] += 1;
+          progress[2 * blockIdx.x + 1] = pub;
+        }
+      }
+      const int jt = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      bool ok = true;
+      if (jt < njobs) {
+        const PipeJob jb = jobs[jt];
+        ok = wait_deps(jb, probs[jb.prob], abort, jt);
+      }
+      s_job = jt;
+      s_ok = ok;
+    }
+    __syncthreads();
+    const int j = __builtin_amdgcn_readfirstlane(s_job);
+    const int ok = __builtin_amdgcn_readfirstlane(s_ok);
+    if (j >= njobs || !ok) break;
+    if (trace && threadIdx.x == 0) {
+      trace[3 * j] = wall_clock64();
+      trace[3 * j + 2] = blockIdx.x;
+    }
+    const PipeJob jb = jobs[j];
+    const PipeProb<T>& p = probs[jb.prob];
+    const int nx = __builtin_amdgcn_readfirstlane(p.nx);
+    pub = __builtin_amdgcn_readfirstlane(dispatch_job<T, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag));
+    pub_cnt = p.cnt;
+    __syncthreads();
+    if (trace && threadIdx.x == 0) trace[3 * j + 1] = wall_clock64();
+  }
+}
+
+template <typename T, int... NXS>
+inline hipError_t pipeline_launch(size_t lds, const PipeJob* jobs, int njobs, const void* probs, int* ticket,
+                                  int* abort, int* progress, unsigned long long* trace, int grid, hipStream_t s) {
+  prep_lds(k_pipeline<T, NXS...>, lds);
+  hipLaunchKernelGGL((k_pipeline<T, NXS...>), dim3(grid), dim3(kPipeThreads), lds, s, jobs, njobs,
+                     static_cast<const PipeProb<T>*>(probs), ticket, abort, progress, trace);
+  return hipGetLastError();
+}
+
+template <typename T>
+inline size_t pipeline_lds_t(int nx, int nx_max) {
+  const int sizes[6] = {64, 128, 256, 512, 1024, 2048};
+  const size_t lds[6] = {pipe_lds<T, 64>(), pipe_lds<T, 128>(), pipe_lds<T, 256>(),
+                         pipe_lds<T, 512>(), pipe_lds<T, 1024>(), pipe_lds<T, 2048>()};
+  size_t out = 0;
+  for (int i = 0; i < 6; ++i)
+    if (nx > 0 ? sizes[i] == nx : sizes[i] <= nx_max) out = lds[i] > out ? lds[i] : out;
+  return out;
+}
+
+template <typename T, int... NXS>
+inline int pipeline_occupancy(size_t lds) {
+  prep_lds(k_pipeline<T, NXS...>, lds);
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_pipeline<T, NXS...>),
+                                                   kPipeThreads, lds) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return per_cu * cus;
+}
+
+}  // namespace ap

@@ -1,6 +1,7 @@
 """The C-ABI library loads on a machine without a GPU, exports every symbol
 include/aparareal.h declares, and rejects bad arguments before touching a device."""
 import ctypes
+import math
 import os
 
 import pytest
@@ -50,42 +51,69 @@ def test_solve_params_layout_matches_header():
     assert ctypes.sizeof(binding.SolveParams) == 56
 
 
-def _deps(job, K):
-    t, k, n = job
-    d = []
+def _deps(job, K, groups, split):
+    """Jobs that must precede `job` = (type, k, n, g) in the hand-out order."""
+    t, k, n, g = job
+    prev = []
     if n > 1:
-        d.append((0, k, n - 1))
-    if t == 0 and k >= 1:
-        d += [(1, k - 1, n), (0, k - 1, n)]
-    return d
+        prev = [(3, k, n - 1, x) for x in range(groups)] if split else [(0, k, n - 1, 0)]
+    if t in (1, 2):
+        return prev
+    before = []
+    if k >= 1:
+        before = [(1, k - 1, n, 0)] + ([(3, k - 1, n, x) for x in range(groups)] if split else [(0, k - 1, n, 0)])
+    if t == 0:
+        return prev + before
+    return [(2, k, n, x) for x in range(groups)] + before     # stage 2 (any may finish the step)
 
 
-@pytest.mark.parametrize("Ns,K,steps,M", [(16, 5, 125, 16), (64, 8, 63, 32), (7, 3, 1, 2), (5, 0, 10, 8),
-                                          (256, 10, 40, 64), (3, 9, 1250, 32)])
-def test_pipeline_schedule_is_topological_and_drains(L, Ns, K, steps, M):
-    jobs = binding.pipeline_schedule(Ns, K, steps, M)
-    want = {(0, k, n) for k in range(K + 1) for n in range(1, Ns + 1)} | \
-           {(1, k, n) for k in range(K) for n in range(1, Ns + 1)}
+@pytest.mark.parametrize("N,T,Ns,K,dt,M,split,group", [
+    (64, 1.0, 16, 5, 0.0005, 16, -1, 0), (256, 2.0, 64, 8, 0.0005, 32, -1, 0),
+    (256, 2.0, 64, 8, 0.0005, 32, 0, 0), (128, 0.7, 7, 3, 0.1, 2, 1, 0), (512, 1.0, 5, 0, 0.01, 8, -1, 3),
+    (1024, 1.0, 256, 10, 0.0001, 64, -1, 0), (2048, 1.0, 3, 9, 1e-4, 32, 1, 7), (64, 1.0, 4, 2, 0.05, 9, 1, 1)])
+def test_pipeline_schedule_is_topological_and_drains(L, N, T, Ns, K, dt, M, split, group):
+    jobs = binding.pipeline_schedule(N, T, Ns, K, dt, M, split=split, group=group)
+    gs = group if group > 0 else max(1, 8 * (64 // (8 if N <= 64 else 16 if N <= 128 else 32 if N <= 256 else 64)) // 3)
+    groups = (M - 1 + gs - 1) // gs
+    is_split = (groups >= 2) if split < 0 else bool(split)
+    steps = max(1, math.ceil(T / Ns / dt - 1e-9))
+    want = {(1, k, n, 0) for k in range(K) for n in range(1, Ns + 1)}
+    if is_split:
+        want |= {(t, k, n, x) for t in (2, 3) for k in range(K + 1) for n in range(1, Ns + 1) for x in range(groups)}
+    else:
+        want |= {(0, k, n, 0) for k in range(K + 1) for n in range(1, Ns + 1)}
     assert len(jobs) == len(want) and set(jobs) == want
     pos = {j: i for i, j in enumerate(jobs)}
     for j in jobs:
-        for d in _deps(j, K):
+        for d in _deps(j, K, groups, is_split):
             assert pos[d] < pos[j], (j, d)
     # ticket scheduling with W workers: each takes the next job and waits for
-    # its dependencies; durations = nonlinear evaluations (coarse 2(M-1), fine 4*steps)
-    dur = {0: 2 * (M - 1), 1: 4 * steps}
+    # its dependencies (durations in nonlinear evaluations)
+    dur = {0: 2 * (M - 1), 1: 4 * steps, 2: gs, 3: gs}
     for W in (1, 3, 256):
         free = [0.0] * W
         end = {}
         for j in jobs:
             w = min(range(W), key=lambda i: free[i])
-            start = max([free[w]] + [end[d] for d in _deps(j, K)])
+            start = max([free[w]] + [end[d] for d in _deps(j, K, groups, is_split)])
             end[j] = start + dur[j[0]]
             free[w] = end[j]
-        makespan = max(end.values())
-        serial_bound = sum(dur[j[0]] for j in jobs)
-        assert makespan <= serial_bound + 1e-9
-    # with enough workers the critical path is Ns coarse steps plus K fine slices
-    # (not (K+1) sweeps): the pipelining across iterations
-    crit = Ns * dur[0] + K * max(dur[1], dur[0]) + K * dur[0]
-    assert makespan <= crit + 1e-9, (makespan, crit)
+        assert max(end.values()) <= sum(dur[j[0]] for j in jobs) + 1e-9
+
+
+def test_batch_and_options_reject_bad_arguments(L):
+    assert L.aparareal_solve_batch(None, 1, None) == -1
+    assert L.aparareal_solve_batch(None, -1, None) == -1
+    assert L.aparareal_solve_batch(None, 0, None) == 0
+    items = (binding.BatchItem * 1)()
+    assert L.aparareal_solve_batch(items, 1, None) == -1           # null context
+    assert b"null context" in L.aparareal_last_error()
+    assert L.aparareal_set_option(None, binding.AP_OPT_SPLIT, 1) == -1
+    v = ctypes.c_int(0)
+    assert L.aparareal_get_option(None, binding.AP_OPT_GROUP, ctypes.byref(v)) == -1
+
+
+def test_batch_item_layout_matches_header():
+    names = [f[0] for f in binding.BatchItem._fields_]
+    assert names == ["ctx", "u0", "params", "U_out", "resid"]
+    assert ctypes.sizeof(binding.BatchItem) == 8 + 8 + 56 + 8 + 8

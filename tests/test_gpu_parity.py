@@ -168,3 +168,117 @@ def test_tolerance_stops_early(torch_cuda):
     ran = r[r >= 0]
     assert 0 < ran.size < cfg.K and ran[-1] <= 1e-6 and np.all(ran[:-1] > 1e-6)
     assert np.all(r[ran.size:] == -1.0)
+
+
+def _solve(ctx, torch, cfg, prec, **kw):
+    U, r = ctx.solve(torch.tensor(cfg.initial_state(), device="cuda"), cfg.T, cfg.slices, cfg.K, cfg.dt,
+                     cfg.Mbar, precision=prec, **kw)
+    torch.cuda.synchronize()
+    return U, r
+
+
+@pytest.mark.parametrize("cfg,prec", [(C1, FP64), (C2, FP32)])
+def test_split_coarse_steps_equal_single_workgroup_steps_bitwise(torch_cuda, cfg, prec):
+    # A coarse step split over one workgroup per sample group sums the groups
+    # in the same order as one workgroup does: identical bits, for the default
+    # and an uneven group size.
+    from paper_1303_6615_amd.binding import AP_OPT_SPLIT, AP_OPT_GROUP
+    torch = torch_cuda
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        for group in (0, 3):
+            ctx.set_option(AP_OPT_GROUP, group)
+            ctx.set_option(AP_OPT_SPLIT, 1)
+            Us, rs = _solve(ctx, torch, cfg, prec)
+            ctx.set_option(AP_OPT_SPLIT, 0)
+            Uw, rw = _solve(ctx, torch, cfg, prec)
+            Uq, rq = _solve(ctx, torch, cfg, prec, tol=1e-300)
+            assert torch.equal(Us, Uw) and torch.equal(rs, rw), group
+            assert torch.equal(Us, Uq) and torch.equal(rs, rq), group
+
+
+def test_group_size_changes_rounding_only(torch_cuda):
+    from paper_1303_6615_amd.binding import AP_OPT_GROUP
+    torch = torch_cuda
+    cfg = C1
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        ctx.set_option(AP_OPT_GROUP, 1)
+        U1, _ = _solve(ctx, torch, cfg, FP64)
+        ctx.set_option(AP_OPT_GROUP, 0)
+        U0, _ = _solve(ctx, torch, cfg, FP64)
+    assert _rel(U1.cpu().numpy(), U0.cpu().numpy()) < 1e-13
+
+
+# uneven problems of one batch: (N, eps, slices, K, T, M, seed); nu by grid size
+_BATCH = [(128, 0.1, 8, 3, 0.4, 16, 11), (256, 0.01, 16, 4, 0.2, 32, 12), (512, 0.01, 6, 2, 0.06, 16, 13),
+          (256, 0.001, 5, 5, 0.02, 8, 14)]
+
+
+def _batch_problem(n, eps, S, K, T, M, seed):
+    nu = NU_BY_NX[n]
+    u0 = seeded_state(n, n // 8, seed)
+    return dict(n=n, eps=eps, nu=nu, u0=u0, prm=dict(T=T, slices=S, K=K, dt_fine=eps / 20, M=M))
+
+
+@pytest.mark.parametrize("prec,tol,which", [(FP32, 2e-5, [0, 1, 2, 3]), (FP32, 2e-5, [1, 3]),
+                                            (FP64, 1e-11, [0, 1])])
+def test_batch_of_uneven_problems(torch_cuda, prec, tol, which):
+    # one persistent launch over problems of different N, eps, slices and K
+    # (several grid sizes, or one); each problem's result equals its solve
+    # alone bitwise, and the oracle within the precision's tolerance
+    from paper_1303_6615_amd.binding import solve_batch
+    torch = torch_cuda
+    probs = [_batch_problem(*_BATCH[i]) for i in which]
+    ctxs = [_ctx(q["n"], q["eps"], q["nu"]) for q in probs]
+    try:
+        items = [(c, torch.tensor(q["u0"], device="cuda"), q["prm"]) for c, q in zip(ctxs, probs)]
+        got = solve_batch(items, precision=prec)
+        torch.cuda.synchronize()
+        for c, (_, u0, prm), (U, r), q in zip(ctxs, items, got, probs):
+            Ua, ra = c.solve(u0, prm["T"], prm["slices"], prm["K"], prm["dt_fine"], prm["M"], precision=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(U, Ua) and torch.equal(r, ra), q["n"]
+            steps = int(np.ceil(prm["T"] / prm["slices"] / prm["dt_fine"] - 1e-9))
+            Uref, _, _ = O.parareal_solve(q["u0"], q["n"], q["eps"], 1.0, q["nu"], prm["T"], prm["slices"],
+                                          prm["K"], steps, prm["M"], prm["T"] / prm["slices"] / q["eps"])
+            assert _rel(U.cpu().numpy(), Uref) < tol, q["n"]
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_large_solve_first_slices_match_serial_oracle(torch_cuda):
+    # The full 1024-point, 256-slice, K = 10 solve as the benchmark times it:
+    # after K iterations the first K slices equal the serial fine solution
+    # (parareal property), which the oracle computes slice by slice.
+    from paper_1303_6615_amd.inputs import C3
+    torch = torch_cuda
+    cfg = C3
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        U, r = _solve(ctx, torch, cfg, FP32)
+        U = U.cpu().numpy()
+        U64, _ = _solve(ctx, torch, cfg, FP64)
+        U64 = U64.cpu().numpy()
+    assert np.all(np.isfinite(U)) and np.all(np.isfinite(r.cpu().numpy()))
+    u = O.project(O.to_spectral(cfg.initial_state()), cfg.nx)
+    dT = cfg.T / cfg.slices
+    for n in range(1, 4):
+        u = O.fine_propagate(u, cfg.nx, cfg.eps, cfg.F, cfg.nu, dT, cfg.fine_steps)
+        x = O.to_physical(u, cfg.nx)
+        assert _rel(U[n], x) < 2e-5, n
+        assert _rel(U64[n], x) < 1e-11, n
+    # FP32 propagators with the FP64 correction against the all-FP64 run
+    assert _rel(U, U64) < 2e-5
+
+
+def test_autotune_keeps_results_and_picks_a_mapping(torch_cuda):
+    from paper_1303_6615_amd.binding import AP_OPT_SPLIT, autotune
+    torch = torch_cuda
+    cfg = C2
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        U0, r0 = _solve(ctx, torch, cfg, FP32)
+        U0, r0 = U0.clone(), r0.clone()
+        u0 = torch.tensor(cfg.initial_state(), device="cuda")
+        ms = autotune([(ctx, u0, dict(T=cfg.T, slices=cfg.slices, K=cfg.K, dt_fine=cfg.dt, M=cfg.Mbar))])
+        assert ms > 0 and ctx.get_option(AP_OPT_SPLIT) in (0, 1)
+        U1, r1 = _solve(ctx, torch, cfg, FP32)
+        assert torch.equal(U0, U1) and torch.equal(r0, r1)
