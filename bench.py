@@ -35,8 +35,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the schedule autotuner (analytic job durations, default mapping)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -118,52 +120,27 @@ def main():
     import torch
 
     from paper_1303_6615_amd import metrics
-    from paper_1303_6615_amd.binding import Context, autotune
-    from paper_1303_6615_amd.inputs import C1, C2, C3
 
-    cfg = {"c1": C1, "c2": C2, "c3": C3}[args.workload]
     torch.cuda.set_device(0)
-    ctx = Context(cfg.nx, cfg.eps, cfg.F, cfg.nu)
-    u0 = torch.tensor(cfg.initial_state(), device="cuda")
-    out = torch.empty((cfg.slices + 1, 3, cfg.nx), dtype=torch.float64, device="cuda")
-    resid = torch.empty((cfg.K,), dtype=torch.float64, device="cuda")
+    W = single_workload(args) if args.workload != "c4" else batch_workload(args)
 
-    def step():
-        ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=cfg.precision,
-                  out=out, resid=resid)
-
-    tuned_ms = None
-    if not args.no_autotune:
-        # untimed: measures job durations on the device and picks the mapping
-        tuned_ms = autotune([(ctx, u0, dict(T=cfg.T, slices=cfg.slices, K=cfg.K, dt_fine=cfg.dt, M=cfg.Mbar))],
-                            precision=cfg.precision)
     for _ in range(args.warmup):
-        step()
+        W["step"]()
     torch.cuda.synchronize()
 
-    ctx.profile(True)
+    owner = W["owner"]
+    owner.profile(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        W["step"]()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    r = resid.cpu().numpy()
-    if not np.all(np.isfinite(r)) or not np.all(np.isfinite(out.cpu().numpy())):
-        raise SystemExit("non-finite result")
+    prof = owner.profile_read()
+    owner.profile(False)
+    W["check"]()
 
-    total_gp = cfg.fine_gp_steps() * args.steps
-    value = total_gp / elapsed
-    # per-kernel algorithmic flops per launch
-    fine_f = metrics.fine_flops(cfg.nx, cfg.slices, cfg.fine_steps)
-    sweep_f = metrics.sweep_flops(cfg.nx, cfg.Mbar, cfg.slices)
-    flops = {
-        "fine": fine_f,
-        "sweep": sweep_f,
-        # the persistent launch runs all K fine batches and K+1 coarse sweeps
-        "pipeline": cfg.K * fine_f + (cfg.K + 1) * sweep_f,
-    }
+    value = W["gp_steps"] * args.steps / elapsed
+    flops = {"pipeline": W["pipeline_flops"]}
     kern = {}
     tot_ms = sum(ms for (_, ms) in prof.values())
     for name, (n, ms) in prof.items():
@@ -173,17 +150,14 @@ def main():
         if name in flops:
             d["tflops"] = round(flops[name] / (ms / n * 1e-3) / 1e12, 4)
         kern[name] = d
-    dominant = max((k for k in kern if k in flops), key=lambda k: kern[k]["share"])
-    avg_s = prof[dominant][1] / prof[dominant][0] * 1e-3
-    achieved = flops[dominant] / avg_s / 1e12
-    kernel_names = {"fine": f"k_fine<float,{cfg.nx}>", "sweep": f"k_sweep<float,{cfg.nx}>",
-                    "pipeline": f"k_pipeline<float,{cfg.nx}>"}
-    if cfg.precision == 1:
-        kernel_names = {k: v.replace("float", "double") for k, v in kernel_names.items()}
-    peak = metrics.PEAK_FP32_TFLOPS if cfg.precision == 0 else metrics.PEAK_FP64_TFLOPS
+    n_launch, ms_total = prof["pipeline"]
+    avg_s = ms_total / n_launch * 1e-3
+    achieved = flops["pipeline"] / avg_s / 1e12
+    fp32 = W["precision"] == 0
+    peak = metrics.PEAK_FP32_TFLOPS if fp32 else metrics.PEAK_FP64_TFLOPS
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 6), "traffic": measured_traffic(cfg.name),
-                "kernel": kernel_names[dominant], "flops_per_launch": flops[dominant],
+                "frac": round(achieved / peak, 6), "traffic": measured_traffic(W["name"]),
+                "kernel": W["kernel"], "flops_per_launch": flops["pipeline"],
                 "avg_launch_ms": round(avg_s * 1e3, 5)}
     line = {
         "metric": "fine grid-point-steps/s at 1 GPU",
@@ -196,23 +170,124 @@ def main():
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f32" if cfg.precision == 0 else "f64",
+        "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
+        "config": W["config"],
+        "roofline": roofline,
+        "kernels": kern,
+        "final_residual": W["final_residual"](),
+        "autotune": W["autotune"],
+    }
+    if args.serve_requests > 0:
+        from paper_1303_6615_amd import serving
+        line["serving"] = serving.run(n_requests=args.serve_requests, warmup=8)
+        line["serving"]["unit"] = "solves/s, latency s"
+    if not args.no_cpu_baseline and args.workload != "c4":
+        line["cpu_baseline"] = cpu_baseline(W["cfg"])
+    print(json.dumps(line), flush=True)
+    W["close"]()
+
+
+def single_workload(args):
+    """One parareal solve per step (workloads c1-c3)."""
+    import numpy as np
+    import torch
+
+    from paper_1303_6615_amd import metrics
+    from paper_1303_6615_amd.binding import Context, autotune
+    from paper_1303_6615_amd.inputs import C1, C2, C3
+
+    cfg = {"c1": C1, "c2": C2, "c3": C3}[args.workload]
+    ctx = Context(cfg.nx, cfg.eps, cfg.F, cfg.nu)
+    u0 = torch.tensor(cfg.initial_state(), device="cuda")
+    out = torch.empty((cfg.slices + 1, 3, cfg.nx), dtype=torch.float64, device="cuda")
+    resid = torch.empty((cfg.K,), dtype=torch.float64, device="cuda")
+
+    def step():
+        ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=cfg.precision, out=out, resid=resid)
+
+    tuned = None
+    if not args.no_autotune:
+        # untimed: measures job durations on the device and picks the mapping
+        ms = autotune([(ctx, u0, dict(T=cfg.T, slices=cfg.slices, K=cfg.K, dt_fine=cfg.dt, M=cfg.Mbar))],
+                      precision=cfg.precision)
+        tuned = {"best_ms": round(ms, 4), "split_coarse": ctx.get_option(0)}
+
+    def check():
+        if not np.all(np.isfinite(resid.cpu().numpy())) or not np.all(np.isfinite(out.cpu().numpy())):
+            raise SystemExit("non-finite result")
+
+    fine_f = metrics.fine_flops(cfg.nx, cfg.slices, cfg.fine_steps)
+    sweep_f = metrics.sweep_flops(cfg.nx, cfg.Mbar, cfg.slices)
+    typ = "float" if cfg.precision == 0 else "double"
+    return {
+        "name": cfg.name, "cfg": cfg, "owner": ctx, "step": step, "check": check, "precision": cfg.precision,
+        "gp_steps": cfg.fine_gp_steps(),
+        # the persistent launch runs all K fine batches and K+1 coarse sweeps
+        "pipeline_flops": cfg.K * fine_f + (cfg.K + 1) * sweep_f,
+        "kernel": f"k_pipeline<{typ},{cfg.nx}>",
         "config": {"workload": cfg.name, "N": cfg.nx, "eps": cfg.eps, "nu": cfg.nu, "F": cfg.F,
                    "T": cfg.T, "slices": cfg.slices, "K": cfg.K, "fine_steps": cfg.fine_steps,
                    "M_avg": cfg.Mbar, "T0": cfg.window,
                    "precision": "fp32 propagators, fp64 correction" if cfg.precision == 0 else "fp64",
                    "parallelism": "time slices as batch, 1 GPU"},
-        "roofline": roofline,
-        "kernels": kern,
-        "final_residual": float(r[-1]) if r.size else None,
-        "autotune": None if tuned_ms is None else {"best_ms": round(tuned_ms, 4),
-                                                   "split_coarse": ctx.get_option(0)},
+        "final_residual": lambda: float(resid[-1].item()) if cfg.K else None,
+        "autotune": tuned,
+        "close": ctx.close,
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg)
-    print(json.dumps(line), flush=True)
-    ctx.close()
+
+
+def batch_workload(args):
+    """64 uneven problems (N 128-1024, eps 0.1-0.001, 16-256 slices, K = 8) in
+    one persistent launch per step."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_1303_6615_amd import metrics
+    from paper_1303_6615_amd.binding import Context, _batch_items, _check, _stream, autotune, lib
+    from paper_1303_6615_amd.inputs import mixed_batch
+
+    probs = mixed_batch(64)
+    ctxs = [Context(c.nx, c.eps, c.F, c.nu) for c in probs]
+    items = [(x, torch.tensor(c.initial_state(), device="cuda"),
+              dict(T=c.T, slices=c.slices, K=c.K, dt_fine=c.dt, M=c.Mbar)) for x, c in zip(ctxs, probs)]
+    arr, outs = _batch_items(items, 0)
+
+    def step():
+        _check(lib().aparareal_solve_batch(arr, len(items), _stream(torch)))
+
+    tuned = None
+    if not args.no_autotune:
+        ms = autotune(items, precision=0)
+        tuned = {"best_ms": round(ms, 4), "split_coarse": ctxs[0].get_option(0)}
+
+    def check():
+        for U, r, _ in outs:
+            if not np.all(np.isfinite(r.cpu().numpy())) or not np.all(np.isfinite(U.cpu().numpy())):
+                raise SystemExit("non-finite result")
+
+    flops = sum(c.K * metrics.fine_flops(c.nx, c.slices, c.fine_steps)
+                + (c.K + 1) * metrics.sweep_flops(c.nx, c.Mbar, c.slices) for c in probs)
+
+    def close():
+        for x in ctxs:
+            x.close()
+
+    return {
+        "name": "rsw-mixed64-n128-1024-fp32c64", "cfg": None, "owner": ctxs[0], "step": step, "check": check,
+        "precision": 0, "gp_steps": sum(c.fine_gp_steps() for c in probs), "pipeline_flops": flops,
+        "kernel": "k_pipeline<float,64,128,256,512,1024>",
+        "config": {"workload": "rsw-mixed64-n128-1024-fp32c64", "problems": len(probs),
+                   "N": sorted({c.nx for c in probs}), "eps": sorted({c.eps for c in probs}),
+                   "slices": [min(c.slices for c in probs), max(c.slices for c in probs)], "K": 8, "T": 1.0,
+                   "M_avg": 32, "precision": "fp32 propagators, fp64 correction",
+                   "parallelism": "problems x time slices as batch, 1 GPU"},
+        "final_residual": lambda: max(float(r[-1].item()) for _, r, _ in outs),
+        "autotune": tuned,
+        "close": close,
+    }
 
 
 if __name__ == "__main__":

@@ -190,8 +190,8 @@ int aparareal_profile_read(ap_ctx* ctx, int kernel_class, int* launches, double*
 int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int group, int* out, int max_jobs);
 
 /* Stall record of the context's last pipelined solve (waits for it): host
- * info[3] = (stalled, job index, flag index).  A stall means a job saw no
- * progress on a dependency for 0.5 s; the launch then ends early and the
+ * info[3] = (stalled, job index, flag index).  A stall means a job waited on
+ * a dependency while no job of the launch completed for 1 s; the launch then ends early and the
  * solve's residuals are NaN.  It does not occur in correct operation.        */
 int aparareal_pipeline_status(ap_ctx* ctx, int* info);
 
@@ -202,6 +202,48 @@ int aparareal_pipeline_status(ap_ctx* ctx, int* info);
  * with start/end in ticks of the device's constant-rate clock (100 MHz on
  * MI355X).  Returns the number of jobs written (reading waits for the solve). */
 int aparareal_pipeline_trace(ap_ctx* ctx, int enable, long long* out, int max_jobs);
+
+/* ---------------------------------------------------------------- serving ---
+ * A request loop over parareal solves (Alg. 4 per request).  Requests are
+ * admitted in arrival order while their HBM footprint fits the budget and
+ * fewer than max_slots run; admitted requests are batched (one persistent
+ * launch per batch, as aparareal_solve_batch) and up to four batches run at
+ * once on separate streams, so requests that arrive while others are on the
+ * device start as soon as memory and slots free up, and their work overlaps.
+ * Each request's states stay in device memory for its whole solve.  A
+ * request's result does not depend on what it was batched with.
+ * One worker thread owns the device work; submit, poll and stats may be
+ * called from any thread.                                                   */
+typedef struct ap_server ap_server;
+
+/* hbm_budget_bytes: device memory the admitted requests may hold at once
+ * (footprint per request: its states at all K+1 iteration levels, tables,
+ * job list and buffers); max_slots >= 1: requests running at once.  NULL on
+ * error.  Uses the current HIP device.                                      */
+ap_server* aparareal_serve_create(size_t hbm_budget_bytes, int max_slots);
+
+/* Queue one solve of the problem (N, eps, F, nu) from u0 (HOST [3][N],
+ * copied before returning) with `params` (tol must be <= 0: exactly K
+ * iterations).  *ticket receives the request's id.  AP_ENOMEM if the request
+ * alone exceeds the budget, AP_EINVAL on bad arguments, AP_EBUSY while the
+ * server shuts down.                                                        */
+int aparareal_serve_submit(ap_server* server, int N, double eps, double F, double nu, const double* u0,
+                           const ap_solve_params* params, unsigned long long* ticket);
+
+/* AP_PENDING while the request is queued or running.  Once it has finished:
+ * copies U (HOST [slices+1][3][N]) and resid (HOST [K]) if not NULL, sets
+ * *latency_s (submit to completion, seconds) if not NULL, releases the
+ * ticket and returns AP_OK, or the request's error code (then the ticket is
+ * released too).  AP_ENOTFOUND for an unknown or released ticket.          */
+int aparareal_serve_poll(ap_server* server, unsigned long long ticket, double* U_out, double* resid,
+                         double* latency_s);
+
+/* Counters (host out[7]): completed, failed, queued, running, batched
+ * launches, device bytes held by running requests, peak of the latter.     */
+int aparareal_serve_stats(ap_server* server, unsigned long long* out);
+
+/* Finish every queued and running request, then release the server.       */
+int aparareal_serve_destroy(ap_server* server);
 
 #ifdef __cplusplus
 }

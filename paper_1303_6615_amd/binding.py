@@ -63,6 +63,12 @@ _SIGNATURES = {
     "aparareal_pipeline_status": (_i, [_vp, ctypes.POINTER(_i)]),
     "aparareal_pipeline_trace": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), _i]),
     "aparareal_profile_read": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+    "aparareal_serve_create": (_vp, [ctypes.c_size_t, _i]),
+    "aparareal_serve_submit": (_i, [_vp, _i, _d, _d, _d, _dp, ctypes.POINTER(SolveParams),
+                                    ctypes.POINTER(ctypes.c_ulonglong)]),
+    "aparareal_serve_poll": (_i, [_vp, ctypes.c_ulonglong, _dp, _dp, ctypes.POINTER(_d)]),
+    "aparareal_serve_stats": (_i, [_vp, ctypes.POINTER(ctypes.c_ulonglong)]),
+    "aparareal_serve_destroy": (_i, [_vp]),
 }
 
 KERNEL_CLASSES = {0: "fine", 1: "sweep", 2: "to_modal", 3: "to_physical", 4: "resid",
@@ -79,6 +85,10 @@ def lib() -> ctypes.CDLL:
     """Load the library (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime; loading it first lets this library's
+        # runtime bind to the same HSA runtime (loading this library first
+        # leaves torch without a device)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1303_6615_amd.build`")
@@ -266,3 +276,66 @@ class Context:
                                      ctypes.c_void_p(out.data_ptr()),
                                      ctypes.c_void_p(resid.data_ptr()), _stream(torch)))
         return out, resid[:K]
+
+
+class Server:
+    """The library's serving loop (host arrays in and out)."""
+
+    STATS = ("completed", "failed", "queued", "running", "launches", "bytes_held", "peak_bytes")
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int):
+        h = lib().aparareal_serve_create(int(hbm_budget_bytes), int(max_slots))
+        if not h:
+            raise APError(-1, lib().aparareal_last_error().decode())
+        self._h = ctypes.c_void_p(h)
+        self._shape = {}
+
+    def submit(self, N: int, eps: float, F: float, nu: float, u0, T: float, slices: int, K: int,
+               dt_fine: float, M: int, T0: float = 0.0, precision: int = AP_PREC_FP32) -> int:
+        import numpy as np
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        if u0.shape != (3, N):
+            raise ValueError(f"u0 must have shape (3, {N})")
+        p = SolveParams(float(T), int(slices), int(K), float(dt_fine), int(M), float(T0), 0.0, int(precision))
+        t = ctypes.c_ulonglong(0)
+        _check(lib().aparareal_serve_submit(self._h, int(N), float(eps), float(F), float(nu),
+                                            ctypes.c_void_p(u0.ctypes.data), ctypes.byref(p), ctypes.byref(t)))
+        self._shape[t.value] = (int(N), int(slices), int(K))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (U [slices+1, 3, N], resid [K], latency_s) as numpy arrays."""
+        import numpy as np
+        N, S, K = self._shape[ticket]
+        U = np.empty((S + 1, 3, N), dtype=np.float64)
+        r = np.empty((max(K, 1),), dtype=np.float64)
+        lat = ctypes.c_double(0.0)
+        rc = lib().aparareal_serve_poll(self._h, ctypes.c_ulonglong(ticket), ctypes.c_void_p(U.ctypes.data),
+                                        ctypes.c_void_p(r.ctypes.data), ctypes.byref(lat))
+        if rc == AP_PENDING:
+            return None
+        del self._shape[ticket]
+        _check(rc)
+        return U, r[:K], lat.value
+
+    def stats(self) -> dict:
+        buf = (ctypes.c_ulonglong * 7)()
+        _check(lib().aparareal_serve_stats(self._h, buf))
+        return dict(zip(self.STATS, list(buf)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().aparareal_serve_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

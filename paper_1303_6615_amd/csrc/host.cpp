@@ -730,8 +730,9 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     nx_max = std::max(nx_max, q.nx);
   }
   if (ncnt > (1LL << 30)) return fail(AP_EINVAL, "batch too large");
-  // counters, then ticket, stall record [3], per-workgroup progress [2][1024]
-  const long long nflags = ncnt + 4 + 2 * 1024;
+  // counters, then ticket, stall record [4] (stalled, job, counter, jobs
+  // completed), per-workgroup progress [2][1024]
+  const long long nflags = ncnt + 5 + 2 * 1024;
   if ((e = ensure(owner, owner->pp_flags, sizeof(int) * size_t(nflags))) != hipSuccess)
     return hip_fail(e, "pipeline counters");
   int* flags = owner->pp_flags.as<int>();
@@ -810,7 +811,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
   owner->pp_diag = abort;
   e = timed(owner, AP_K_PIPELINE, s, [&] {
     return ap::launch_pipeline(nx_common, nx_max, f64, owner->pp_jobs.p, owner->pp_njobs, owner->pp_prob.p, ticket,
-                               abort, abort + 3, trace, grid, s);
+                               abort, abort + 4, trace, grid, s);
   });
   if (e != hipSuccess) return hip_fail(e, "pipeline launch");
   if (!rows.empty()) {
@@ -830,6 +831,10 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
 }
 
 }  // namespace
+
+namespace aplib {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace aplib
 
 extern "C" {
 

@@ -17,23 +17,33 @@ namespace ap {
 // Split C(k,n): stage-1 job of group g needs C(k,n-1); stage-2 job of group g
 //         needs every stage-1 job of the step; the stage-2 job that finishes
 //         last also needs F(k-1,n) and C(k-1,n) and publishes C(k,n).
-// A wait that sees no progress for kStallTicks of the constant-rate device
-// clock (100 MHz: 0.5 s) declares a stall: the scheduler's order guarantees
-// progress, so this only fires on a defect, and it ends the launch instead of
-// hanging the device.
-constexpr unsigned long long kStallTicks = 50000000ull;
+// Stall record `diag` of a launch: [0] stalled, [1] job, [2] counter index,
+// [3] jobs completed so far (every workgroup adds 1 per job it publishes).
+// A wait ends in a stall only when no job of the launch completes for
+// kStallTicks of the constant-rate device clock (100 MHz: 1 s) while it
+// waits: the scheduler's order guarantees progress, so this only fires on a
+// defect, and it ends the launch instead of hanging the device.  A long wait
+// while other jobs keep completing is ordinary (large batches hand out jobs
+// long before their inputs exist).
+constexpr unsigned long long kStallTicks = 100000000ull;
 
 // Thread 0 waits for *ctr >= target (relaxed polls, then an acquire fence).
 // On a stall it records (1, job, counter index) in diag[0..2] and returns
 // false; it also returns false once another workgroup has recorded one.
-constexpr int kStallPolls = 1 << 21;   // second bound, independent of the clock
+constexpr int kStallPolls = 1 << 22;   // polls without progress: a bound independent of the clock
 
 __device__ __forceinline__ bool wait_count(int* ctr, int target, int* diag, int job, int index) {
-  const unsigned long long t0 = wall_clock64();
+  unsigned long long t0 = wall_clock64();
+  int seen = __hip_atomic_load(diag + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int polls = 0;
   while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     if (__hip_atomic_load(diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    if (wall_clock64() - t0 > kStallTicks || ++polls > kStallPolls) {
+    const int now_done = __hip_atomic_load(diag + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (now_done != seen) {
+      seen = now_done;
+      t0 = wall_clock64();
+      polls = 0;
+    } else if (wall_clock64() - t0 > kStallTicks || ++polls > kStallPolls) {
       if (__hip_atomic_fetch_add(diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
         __hip_atomic_store(diag + 1, job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(diag + 2, index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -186,6 +196,7 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
       if (pub >= 0) {
         __threadfence();
         __hip_atomic_fetch_add(&pub_cnt[pub], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(abort + 3, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (progress) {
           progress[2 * blockIdx.x] += 1;
           progress[2 * blockIdx.x + 1] = pub;

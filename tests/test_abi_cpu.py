@@ -117,3 +117,14 @@ def test_batch_item_layout_matches_header():
     names = [f[0] for f in binding.BatchItem._fields_]
     assert names == ["ctx", "u0", "params", "U_out", "resid"]
     assert ctypes.sizeof(binding.BatchItem) == 8 + 8 + 56 + 8 + 8
+
+
+def test_serving_rejects_bad_arguments(L):
+    assert not L.aparareal_serve_create(0, 4)
+    assert not L.aparareal_serve_create(1 << 30, 0)
+    t = ctypes.c_ulonglong(0)
+    p = binding.SolveParams(1.0, 4, 2, 0.01, 8, 0.0, 0.0, 0)
+    assert L.aparareal_serve_submit(None, 64, 0.1, 1.0, 0.0, None, ctypes.byref(p), ctypes.byref(t)) == -1
+    assert L.aparareal_serve_poll(None, 1, None, None, None) == -1
+    assert L.aparareal_serve_destroy(None) == -1
+    assert b"null server" in L.aparareal_last_error()

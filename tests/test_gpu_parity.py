@@ -282,3 +282,61 @@ def test_autotune_keeps_results_and_picks_a_mapping(torch_cuda):
         assert ms > 0 and ctx.get_option(AP_OPT_SPLIT) in (0, 1)
         U1, r1 = _solve(ctx, torch, cfg, FP32)
         assert torch.equal(U0, U1) and torch.equal(r0, r1)
+
+
+def _serve_all(srv, reqs, precision=FP32):
+    import time
+    tickets = [srv.submit(c.nx, c.eps, c.F, c.nu, c.initial_state(), c.T, c.slices, c.K, c.dt, c.Mbar,
+                          precision=precision) for c in reqs]
+    out = {}
+    t_end = time.time() + 120
+    while len(out) < len(tickets) and time.time() < t_end:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.002)
+    assert len(out) == len(tickets), "serving did not finish in time"
+    return [out[t] for t in tickets]
+
+
+def test_serving_results_equal_alone_solves(torch_cuda):
+    # requests of uneven N, eps, T and slices through the serving loop: each
+    # result equals the same solve run alone (continuous batching changes only
+    # what runs beside a request), and within FP32 tolerance of the oracle
+    from paper_1303_6615_amd.binding import Server
+    from paper_1303_6615_amd.inputs import serving_requests
+    torch = torch_cuda
+    reqs = [c for c in serving_requests(40, seed=7, T_range=(0.05, 0.2)) if c.nx <= 512][:10]
+    assert len(reqs) >= 6
+    with Server(8 << 30, 8) as srv:
+        got = _serve_all(srv, reqs)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0 and st["bytes_held"] == 0
+    for c, (U, r, lat) in zip(reqs, got):
+        assert lat > 0
+        with _ctx(c.nx, c.eps, c.nu) as ctx:
+            Ua, ra = _solve(ctx, torch, c, FP32)
+        assert np.array_equal(U, Ua.cpu().numpy()) and np.array_equal(r, ra.cpu().numpy()), c.name
+    c = reqs[0]
+    Uref, _, _ = O.parareal_solve(c.initial_state(), c.nx, c.eps, c.F, c.nu, c.T, c.slices, c.K, c.fine_steps,
+                                  c.Mbar, c.window)
+    assert _rel(got[0][0], Uref) < 2e-5
+
+
+def test_serving_admission_by_memory_budget(torch_cuda):
+    # a budget that holds one request at a time still serves them all, in
+    # order; a request larger than the budget is refused at submission
+    from paper_1303_6615_amd.binding import APError, Server
+    from paper_1303_6615_amd.inputs import serving_requests
+    reqs = serving_requests(3, seed=8, nxs=(256,), T_range=(0.05, 0.1))
+    with Server(6 << 20, 8) as srv:
+        got = _serve_all(srv, reqs)
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["peak_bytes"] <= 6 << 20
+        big = serving_requests(1, seed=9, nxs=(2048,), T_range=(4.0, 4.0))[0]
+        with pytest.raises(APError):
+            srv.submit(big.nx, big.eps, big.F, big.nu, big.initial_state(), big.T, big.slices, big.K, big.dt,
+                       big.Mbar)
+    assert all(np.all(np.isfinite(U)) for U, _, _ in got)
