@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving measurement (0 skips it)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each step from a captured hipGraph (the pipeline timing then covers the "
+                         "whole replay, boundary kernels included)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the schedule autotuner (analytic job durations, default mapping)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -206,6 +209,8 @@ def single_workload(args):
     def step():
         ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=cfg.precision, out=out, resid=resid)
 
+    ctx.set_option(3, 1 if args.graph else 0)          # AP_OPT_GRAPH
+
     tuned = None
     if not args.no_autotune:
         # untimed: measures job durations on the device and picks the mapping
@@ -230,7 +235,7 @@ def single_workload(args):
                    "T": cfg.T, "slices": cfg.slices, "K": cfg.K, "fine_steps": cfg.fine_steps,
                    "M_avg": cfg.Mbar, "T0": cfg.window,
                    "precision": "fp32 propagators, fp64 correction" if cfg.precision == 0 else "fp64",
-                   "parallelism": "time slices as batch, 1 GPU"},
+                   "parallelism": "time slices as batch, 1 GPU", "graph": bool(args.graph)},
         "final_residual": lambda: float(resid[-1].item()) if cfg.K else None,
         "autotune": tuned,
         "close": ctx.close,
@@ -254,6 +259,7 @@ def batch_workload(args):
     items = [(x, torch.tensor(c.initial_state(), device="cuda"),
               dict(T=c.T, slices=c.slices, K=c.K, dt_fine=c.dt, M=c.Mbar)) for x, c in zip(ctxs, probs)]
     arr, outs = _batch_items(items, 0)
+    ctxs[0].set_option(3, 1 if args.graph else 0)      # AP_OPT_GRAPH (the first item owns the launch)
 
     def step():
         _check(lib().aparareal_solve_batch(arr, len(items), _stream(torch)))
@@ -283,7 +289,7 @@ def batch_workload(args):
                    "N": sorted({c.nx for c in probs}), "eps": sorted({c.eps for c in probs}),
                    "slices": [min(c.slices for c in probs), max(c.slices for c in probs)], "K": 8, "T": 1.0,
                    "M_avg": 32, "precision": "fp32 propagators, fp64 correction",
-                   "parallelism": "problems x time slices as batch, 1 GPU"},
+                   "parallelism": "problems x time slices as batch, 1 GPU", "graph": bool(args.graph)},
         "final_residual": lambda: max(float(r[-1].item()) for _, r, _ in outs),
         "autotune": tuned,
         "close": close,

@@ -139,8 +139,15 @@ int aparareal_solve_batch(const ap_batch_item* items, int count, void* stream);
  *                 each group in sample order, then over the groups in order);
  *                 0 (default) = by grid size.  Reading returns the size used.
  *   AP_OPT_GRID   workgroups of a persistent launch; 0 (default) = as many as
- *                 are resident on the device at once.                        */
-enum { AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2 };
+ *                 are resident on the device at once.
+ *   AP_OPT_GRAPH  1: a pipelined solve (or batch whose first item names this
+ *                 context) is captured into a hipGraph on its first call and
+ *                 replayed by later calls with the same arguments, device
+ *                 addresses and shapes (inputs are read at replay time); the
+ *                 graph holds kernels and device copies only.  With kernel
+ *                 timing on, the pipeline class then times the whole replay.
+ *                 0 (default): launches are enqueued one by one.             */
+enum { AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2, AP_OPT_GRAPH = 3 };
 int aparareal_set_option(ap_ctx* ctx, int option, int value);
 int aparareal_get_option(ap_ctx* ctx, int option, int* value);
 

@@ -164,6 +164,11 @@ struct ap_ctx {
   int opt_group = 0;         // samples per group of the average; 0 = by grid size
   int opt_grid = 0;          // workgroups of a persistent launch; 0 = all that fit
   CostCal cost;              // calibrated job durations (aparareal_autotune)
+  int opt_graph = 0;         // replay pipelined launches from a captured hipGraph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t graph_stream = nullptr;   // private stream the graph is captured on
+  std::string graph_key;
   int* pp_diag = nullptr;   // stall record of the last pipelined launch
   bool trace_on = false;     // record per-job device-clock intervals
   DevBuf pp_trace;
@@ -177,6 +182,9 @@ struct ap_ctx {
   int prof_count[AP_K_CLASSES] = {};
   double prof_ms[AP_K_CLASSES] = {};
   ~ap_ctx() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (graph_stream) (void)hipStreamDestroy(graph_stream);
     for (auto& t : ev_pending) {
       ev_pool.push_back(std::get<1>(t));
       ev_pool.push_back(std::get<2>(t));
@@ -795,38 +803,87 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     owner->pp_trace_jobs = owner->pp_njobs;
   }
   // enqueue: boundary transforms in, counters, the persistent launch,
-  // residuals, boundary transforms out
-  for (auto& it : items) {
-    ap_ctx* c = it.c;
-    cx<double>* U = c->pp_U.as<cx<double>>();
-    const size_t sb = state_bytes(c);
-    e = timed(owner, AP_K_TO_MODAL, s, [&] { return ap::launch_to_modal(c->N, it.u0, U, 1, c->tabs, s); });
-    if (e != hipSuccess) return hip_fail(e, "to_modal");
-    if (it.q.K > 0 &&
-        (e = hipMemcpyAsync(U + size_t(it.q.K) * (it.q.Ns + 1) * (sb / sizeof(cx<double>)), U, sb,
-                            hipMemcpyDeviceToDevice, s)) != hipSuccess)
-      return hip_fail(e, "initial state copy");
-  }
-  if ((e = ap::launch_zero_ints(flags, int(nflags), s)) != hipSuccess) return hip_fail(e, "counter reset");
+  // residuals, boundary transforms out (kernels and device copies only, so
+  // that the sequence can be captured into a graph)
   owner->pp_diag = abort;
-  e = timed(owner, AP_K_PIPELINE, s, [&] {
-    return ap::launch_pipeline(nx_common, nx_max, f64, owner->pp_jobs.p, owner->pp_njobs, owner->pp_prob.p, ticket,
-                               abort, abort + 4, trace, grid, s);
-  });
-  if (e != hipSuccess) return hip_fail(e, "pipeline launch");
-  if (!rows.empty()) {
-    e = timed(owner, AP_K_RESID, s, [&] {
-      return ap::launch_resid_rows(owner->pp_rows.as<ap::ResidRow>(), int(rows.size()), abort, s);
+  auto enqueue = [&](hipStream_t st, bool time_it) -> int {
+    auto run = [&](int cls, auto&& fn) { return time_it ? timed(owner, cls, st, fn) : fn(); };
+    hipError_t err;
+    for (auto& it : items) {
+      ap_ctx* c = it.c;
+      cx<double>* U = c->pp_U.as<cx<double>>();
+      const size_t sb = state_bytes(c);
+      err = run(AP_K_TO_MODAL, [&] { return ap::launch_to_modal(c->N, it.u0, U, 1, c->tabs, st); });
+      if (err != hipSuccess) return hip_fail(err, "to_modal");
+      if (it.q.K > 0 &&
+          (err = hipMemcpyAsync(U + size_t(it.q.K) * (it.q.Ns + 1) * (sb / sizeof(cx<double>)), U, sb,
+                                hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return hip_fail(err, "initial state copy");
+    }
+    if ((err = ap::launch_zero_ints(flags, int(nflags), st)) != hipSuccess) return hip_fail(err, "counter reset");
+    err = run(AP_K_PIPELINE, [&] {
+      return ap::launch_pipeline(nx_common, nx_max, f64, owner->pp_jobs.p, owner->pp_njobs, owner->pp_prob.p,
+                                 ticket, abort, abort + 4, trace, grid, st);
     });
-    if (e != hipSuccess) return hip_fail(e, "resid");
-  }
+    if (err != hipSuccess) return hip_fail(err, "pipeline launch");
+    if (!rows.empty()) {
+      err = run(AP_K_RESID, [&] {
+        return ap::launch_resid_rows(owner->pp_rows.as<ap::ResidRow>(), int(rows.size()), abort, st);
+      });
+      if (err != hipSuccess) return hip_fail(err, "resid");
+    }
+    for (auto& it : items) {
+      ap_ctx* c = it.c;
+      const cx<double>* UK = c->pp_U.as<cx<double>>() + size_t(it.q.K) * (it.q.Ns + 1) * 3 * c->KP;
+      err = run(AP_K_TO_PHYSICAL, [&] { return ap::launch_to_physical(c->N, UK, it.U_out, it.q.Ns + 1, c->tabs, st); });
+      if (err != hipSuccess) return hip_fail(err, "to_physical");
+    }
+    return AP_OK;
+  };
+  if (!owner->opt_graph || trace) return enqueue(s, true);
+  // Graph replay: the sequence is captured once per set of device addresses
+  // (arguments and workspaces) and launch shape, then replayed; inputs are
+  // read from device memory at replay time.
+  std::string gkey = key + "|" + std::to_string(grid);
+  auto addr = [&](const void* p) { gkey += ":" + std::to_string(reinterpret_cast<uintptr_t>(p)); };
+  addr(owner->pp_flags.p);
+  addr(owner->pp_jobs.p);
+  addr(owner->pp_prob.p);
+  addr(owner->pp_rows.p);
   for (auto& it : items) {
-    ap_ctx* c = it.c;
-    const cx<double>* UK = c->pp_U.as<cx<double>>() + size_t(it.q.K) * (it.q.Ns + 1) * 3 * c->KP;
-    e = timed(owner, AP_K_TO_PHYSICAL, s,
-              [&] { return ap::launch_to_physical(c->N, UK, it.U_out, it.q.Ns + 1, c->tabs, s); });
-    if (e != hipSuccess) return hip_fail(e, "to_physical");
+    addr(it.c);
+    addr(it.u0);
+    addr(it.U_out);
+    addr(it.resid);
+    addr(it.c->pp_U.p);
   }
+  if (!owner->graph_exec || gkey != owner->graph_key) {
+    if (owner->graph_exec) (void)hipGraphExecDestroy(owner->graph_exec);
+    if (owner->graph) (void)hipGraphDestroy(owner->graph);
+    owner->graph_exec = nullptr;
+    owner->graph = nullptr;
+    owner->graph_key.clear();
+    if (!owner->graph_stream && (e = hipStreamCreateWithFlags(&owner->graph_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "graph stream");
+    if ((e = hipStreamBeginCapture(owner->graph_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(e, "graph capture");
+    const int rc = enqueue(owner->graph_stream, false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(owner->graph_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    owner->graph = g;
+    if ((e = hipGraphInstantiate(&owner->graph_exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+      owner->graph_exec = nullptr;
+      return hip_fail(e, "graph instantiation");
+    }
+    owner->graph_key = gkey;
+  }
+  e = timed(owner, AP_K_PIPELINE, s, [&] { return hipGraphLaunch(owner->graph_exec, s); });
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
   return AP_OK;
 }
 
@@ -1131,6 +1188,10 @@ int aparareal_set_option(ap_ctx* c, int option, int value) {
       if (value < 0) return fail(AP_EINVAL, "AP_OPT_GRID takes a value >= 0");
       c->opt_grid = value;
       return AP_OK;
+    case AP_OPT_GRAPH:
+      if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_GRAPH takes 0 or 1");
+      c->opt_graph = value;
+      return AP_OK;
     default:
       return fail(AP_EINVAL, "unknown option");
   }
@@ -1144,6 +1205,7 @@ int aparareal_get_option(ap_ctx* c, int option, int* value) {
     case AP_OPT_SPLIT: *value = c->opt_split; return AP_OK;
     case AP_OPT_GROUP: *value = group_size(c); return AP_OK;
     case AP_OPT_GRID: *value = c->opt_grid; return AP_OK;
+    case AP_OPT_GRAPH: *value = c->opt_graph; return AP_OK;
     default: return fail(AP_EINVAL, "unknown option");
   }
 }

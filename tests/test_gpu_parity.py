@@ -340,3 +340,33 @@ def test_serving_admission_by_memory_budget(torch_cuda):
             srv.submit(big.nx, big.eps, big.F, big.nu, big.initial_state(), big.T, big.slices, big.K, big.dt,
                        big.Mbar)
     assert all(np.all(np.isfinite(U)) for U, _, _ in got)
+
+
+def test_graph_replay_equals_eager_solves(torch_cuda):
+    # the pipelined solve captured into a hipGraph and replayed: every replay,
+    # with eager work and host synchronisation between replays, equals the
+    # eagerly enqueued solve; a new input at the same address is picked up
+    from paper_1303_6615_amd.binding import AP_OPT_GRAPH
+    torch = torch_cuda
+    cfg = C2
+    u0 = torch.tensor(cfg.initial_state(), device="cuda")
+    u1 = torch.tensor(seeded_state(cfg.nx, cfg.k_ic, 99), device="cuda")
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        def solve(u, out, resid):
+            return ctx.solve(u, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=FP32, out=out, resid=resid)
+        out = torch.empty((cfg.slices + 1, 3, cfg.nx), dtype=torch.float64, device="cuda")
+        resid = torch.empty((cfg.K,), dtype=torch.float64, device="cuda")
+        ref0 = [t.clone() for t in solve(u0, out, resid)]
+        x = u0.clone()
+        solve(u1.clone(), out, resid)
+        ref1 = [t.clone() for t in (out, resid)]
+        ctx.set_option(AP_OPT_GRAPH, 1)
+        for rep in range(4):
+            src = u0 if rep % 2 == 0 else u1
+            x.copy_(src)
+            junk = torch.randn(1 << 16, device="cuda").sum()          # eager work between replays
+            solve(x, out, resid)
+            torch.cuda.synchronize()
+            want = ref0 if rep % 2 == 0 else ref1
+            assert torch.equal(out, want[0]) and torch.equal(resid, want[1]), rep
+            assert torch.isfinite(junk)
