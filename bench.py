@@ -12,8 +12,10 @@ workload
     seeded k^-2 initial spectrum up to k = 32, max|h| = 0.1.
 Inputs are resident on the device before timing starts.
 
-Metric: fine grid-point-steps per second of whole-solve wall time
-(K x slices x fine steps x N per solve).  The JSON line also carries the
+Metric: fine grid-point-steps per second of whole-solve wall time, counting
+the fine slices actually computed (K x slices x fine steps x N per solve,
+less the K(K-1)/2 slices that earlier iterations made exact and that are
+copied instead of recomputed).  The JSON line also carries the
 roofline of the dominant kernel (algorithmic flops per launch over its
 event-timed average duration) and the FP64 CPU oracle timed on one full
 solve of the same workload.
@@ -222,14 +224,13 @@ def single_workload(args):
         if not np.all(np.isfinite(resid.cpu().numpy())) or not np.all(np.isfinite(out.cpu().numpy())):
             raise SystemExit("non-finite result")
 
-    fine_f = metrics.fine_flops(cfg.nx, cfg.slices, cfg.fine_steps)
-    sweep_f = metrics.sweep_flops(cfg.nx, cfg.Mbar, cfg.slices)
+    gp, work = metrics.pipelined_work(cfg.nx, cfg.slices, cfg.K, cfg.fine_steps, cfg.Mbar)
     typ = "float" if cfg.precision == 0 else "double"
     return {
         "name": cfg.name, "cfg": cfg, "owner": ctx, "step": step, "check": check, "precision": cfg.precision,
-        "gp_steps": cfg.fine_gp_steps(),
-        # the persistent launch runs all K fine batches and K+1 coarse sweeps
-        "pipeline_flops": cfg.K * fine_f + (cfg.K + 1) * sweep_f,
+        # fine slices and coarse steps actually computed (exact slices are copied)
+        "gp_steps": gp,
+        "pipeline_flops": work,
         "kernel": f"k_pipeline<{typ},{cfg.nx}>",
         "config": {"workload": cfg.name, "N": cfg.nx, "eps": cfg.eps, "nu": cfg.nu, "F": cfg.F,
                    "T": cfg.T, "slices": cfg.slices, "K": cfg.K, "fine_steps": cfg.fine_steps,
@@ -274,8 +275,8 @@ def batch_workload(args):
             if not np.all(np.isfinite(r.cpu().numpy())) or not np.all(np.isfinite(U.cpu().numpy())):
                 raise SystemExit("non-finite result")
 
-    flops = sum(c.K * metrics.fine_flops(c.nx, c.slices, c.fine_steps)
-                + (c.K + 1) * metrics.sweep_flops(c.nx, c.Mbar, c.slices) for c in probs)
+    work = [metrics.pipelined_work(c.nx, c.slices, c.K, c.fine_steps, c.Mbar) for c in probs]
+    flops = sum(w[1] for w in work)
 
     def close():
         for x in ctxs:
@@ -283,7 +284,7 @@ def batch_workload(args):
 
     return {
         "name": "rsw-mixed64-n128-1024-fp32c64", "cfg": None, "owner": ctxs[0], "step": step, "check": check,
-        "precision": 0, "gp_steps": sum(c.fine_gp_steps() for c in probs), "pipeline_flops": flops,
+        "precision": 0, "gp_steps": sum(w[0] for w in work), "pipeline_flops": flops,
         "kernel": "k_pipeline<float,64,128,256,512,1024>",
         "config": {"workload": "rsw-mixed64-n128-1024-fp32c64", "problems": len(probs),
                    "N": sorted({c.nx for c in probs}), "eps": sorted({c.eps for c in probs}),

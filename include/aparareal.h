@@ -95,29 +95,35 @@ typedef struct {
   double dt_fine;    /* requested fine step; fine steps per slice = ceil(dT/dt)  */
   int M_avg;         /* averaging samples M >= 2                                 */
   double T0;         /* fast-time averaging window; <= 0 selects dT/eps          */
-  double tol;        /* > 0: stop once the residual drops to tol (host sync per  */
-                     /* iteration); <= 0: run exactly K iterations               */
+  double tol;        /* > 0: stop after the first iteration k with r^k <= tol     */
+                     /* (decided on the device); <= 0: run exactly K iterations  */
   int precision;     /* AP_PREC_FP32 or AP_PREC_FP64                              */
 } ap_solve_params;
 
 /* Parareal solve (Sec. 3, eq. HMM parareal iteration; Alg. 4):
  *   U_n^0 = G(U_{n-1}^0);  U_n^k = Fine(U_{n-1}^{k-1}) + (G(U_{n-1}^k) - G(U_{n-1}^{k-1}))
  * with the correction evaluated in FP64 and G(U^{k-1}) reused from the previous
- * sweep.  With tol <= 0 the K iterations run as one pipelined persistent
- * launch (iteration k+1 starts on a slice as soon as its inputs exist);
- * results are identical to the iteration-by-iteration order.  u0 physical [3][N]; U_out physical [slices+1][3][N] holds U_0..U_Ns
- * after the last iteration; resid (device, float64 [K]) receives
- * r^k = max_n ||U_n^k - U_n^{k-1}||_2 / ||U_n^k||_2 over the 3N grid values
- * (entries of iterations skipped by `tol` are set to -1).                     */
+ * sweep.  The iterations run as one pipelined persistent launch (iteration
+ * k+1 starts on a slice as soon as its inputs exist); the values are those of
+ * the iteration-by-iteration order.  Slices n <= k, which iteration k makes
+ * exact (they equal the serial fine solution), are copied instead of
+ * recomputed (AP_OPT_SKIP).  With tol > 0 the job that completes iteration k
+ * computes r^k on the device; once r^k <= tol the later iterations' jobs end
+ * without work, U_out holds U^k and the later resid entries are -1 (no host
+ * synchronisation; AP_OPT_SWEEPS = 1 instead runs the iterations one by one
+ * with a host check of each residual, the same results).
+ * u0 physical [3][N]; U_out physical [slices+1][3][N] holds U_0..U_Ns after
+ * the last iteration run; resid (device, float64 [K]) receives
+ * r^k = max_n ||U_n^k - U_n^{k-1}||_2 / ||U_n^k||_2 over the 3N grid values.  */
 int aparareal_solve(ap_ctx* ctx, const double* u0, const ap_solve_params* params,
                     double* U_out, double* resid, void* stream);
 
 /* Many independent problems in one persistent launch (the slices of every
  * problem are the batch of one launch; Alg. 4 per problem).  Each item names
  * its own context (grid size, eps, F, nu; a context may appear only once),
- * initial state, parameters (tol <= 0: exactly K iterations; the precision
- * must be the same for all items) and outputs, with the meaning and layout of
- * aparareal_solve.  Each problem's results equal those of aparareal_solve on
+ * initial state, parameters (each problem stops on its own tolerance; the
+ * precision must be the same for all items) and outputs, with the meaning and
+ * layout of aparareal_solve.  Each problem's results equal those of aparareal_solve on
  * its own.  The first item's context holds the launch's job list and
  * counters; every context keeps its problem's states.                       */
 typedef struct {
@@ -146,8 +152,14 @@ int aparareal_solve_batch(const ap_batch_item* items, int count, void* stream);
  *                 addresses and shapes (inputs are read at replay time); the
  *                 graph holds kernels and device copies only.  With kernel
  *                 timing on, the pipeline class then times the whole replay.
- *                 0 (default): launches are enqueued one by one.             */
-enum { AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2, AP_OPT_GRAPH = 3 };
+ *                 0 (default): launches are enqueued one by one.
+ *   AP_OPT_SKIP   1 (default): slices made exact by iteration k are copied
+ *                 (values unchanged); 0: every coarse step and fine slice of
+ *                 every iteration is computed.
+ *   AP_OPT_SWEEPS 1: aparareal_solve with tol > 0 runs the iterations one by
+ *                 one (a fine batch and a serial coarse sweep each) with a
+ *                 host check of the residual; 0 (default): pipelined.       */
+enum { AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2, AP_OPT_GRAPH = 3, AP_OPT_SKIP = 4, AP_OPT_SWEEPS = 5 };
 int aparareal_set_option(ap_ctx* ctx, int option, int value);
 int aparareal_get_option(ap_ctx* ctx, int option, int* value);
 
@@ -190,9 +202,11 @@ int aparareal_profile_read(ap_ctx* ctx, int kernel_class, int* launches, double*
  * parameters p, split / group as AP_OPT_SPLIT / AP_OPT_GROUP.  Writes up to
  * max_jobs (type, k, n, g) quadruples to the host array `out` (may be NULL):
  * type 0 = coarse step C(k,n) in one workgroup, k = 0..K; 1 = fine slice
- * F(k,n) = Fine(U_{n-1}^k), k = 0..K-1; 2 / 3 = first / second average of a
- * split coarse step C(k,n) for sample group g.  Jobs are ordered by their
- * estimated ready times, and every job comes after the jobs it depends on.
+ * F(k,n) = Fine(U_{n-1}^k), k = 0..K-1, n > k; 2 / 3 = first / second
+ * average of a split coarse step C(k,n) for sample group g; 4 = copy of the
+ * exact slice n <= k at level k >= 1 (slice skipping).  Jobs are ordered by
+ * their estimated ready times, and every job comes after the jobs it depends
+ * on.
  * Returns the job count or AP_EINVAL.                                        */
 int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int group, int* out, int max_jobs);
 
@@ -230,8 +244,7 @@ typedef struct ap_server ap_server;
 ap_server* aparareal_serve_create(size_t hbm_budget_bytes, int max_slots);
 
 /* Queue one solve of the problem (N, eps, F, nu) from u0 (HOST [3][N],
- * copied before returning) with `params` (tol must be <= 0: exactly K
- * iterations).  *ticket receives the request's id.  AP_ENOMEM if the request
+ * copied before returning) with `params` (as for aparareal_solve).  *ticket receives the request's id.  AP_ENOMEM if the request
  * alone exceeds the budget, AP_EINVAL on bad arguments, AP_EBUSY while the
  * server shuts down.                                                        */
 int aparareal_serve_submit(ap_server* server, int N, double eps, double F, double nu, const double* u0,

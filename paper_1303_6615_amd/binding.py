@@ -38,8 +38,8 @@ class BatchItem(ctypes.Structure):
                 ("U_out", ctypes.c_void_p), ("resid", ctypes.c_void_p)]
 
 
-AP_OPT_SPLIT, AP_OPT_GROUP, AP_OPT_GRID, AP_OPT_GRAPH = 0, 1, 2, 3
-JOB_COARSE, JOB_FINE, JOB_STAGE1, JOB_STAGE2 = 0, 1, 2, 3
+AP_OPT_SPLIT, AP_OPT_GROUP, AP_OPT_GRID, AP_OPT_GRAPH, AP_OPT_SKIP, AP_OPT_SWEEPS = 0, 1, 2, 3, 4, 5
+JOB_COARSE, JOB_FINE, JOB_STAGE1, JOB_STAGE2, JOB_COPY = 0, 1, 2, 3, 4
 
 
 _lib = None

@@ -97,6 +97,25 @@ struct Engine {
     if constexpr (S == 1) __syncthreads();
   }
 
+  // FP64 block maximum of x over the workgroup (NaN wins); result valid in
+  // every thread.  The scratch lives in `ib`, so wait for its last readers first.
+  __device__ __forceinline__ double block_max(double x) {
+    static_assert(S * SL::ib_elems * sizeof(cx<T>) >= NT * sizeof(double), "reduction scratch");
+    __syncthreads();
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) {
+        const double o = red[threadIdx.x + off];
+        if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
+      }
+      __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+  }
+
   // FP64 block sum of (x, y) over the workgroup; result valid in every thread.
   // The scratch lives in `ib`, so wait for its last readers first.
   __device__ __forceinline__ double2 block_sum2(double x, double yv) {
@@ -425,6 +444,49 @@ __device__ __forceinline__ void coarse_job(Engine<T, NX, NT, S>& en, const Coars
   load_owned<T, NX, NT, S>(uprev, u);
   coarse_owned<T, NX, NT, S>(en, u, g, ct, basis);
   coarse_correct<T, NX, NT, S>(en, g, unew, gnew, gold, fold, uold, part);
+}
+
+// The coarse job of a slice that the iteration has made exact (n <= k): the
+// state `src` (U(k-1,n) or F(k-1,k)) becomes U(k,n), G(k-1,n) becomes G(k,n),
+// and the residual parts are those of the full correction (whose coarse
+// difference is exactly zero here).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void copy_job(Engine<T, NX, NT, S>& en, const cx<double>* src, cx<double>* unew,
+                                         const cx<double>* gold, cx<double>* gnew, const cx<double>* uold,
+                                         double2* part) {
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int KP = E_::KP;
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int j = 0; j < E_::MPT; ++j) {
+    if (!E_::valid(j)) continue;
+    const int k = E_::mode(j);
+    const double wgt = k == 0 ? 1.0 : 2.0;
+    for (int al = 0; al < 3; ++al) {
+      const int o = al * KP + k;
+      const cx<double> un = src[o];
+      const cx<double> d = un - uold[o];
+      num += wgt * (d.x * d.x + d.y * d.y);
+      den += wgt * (un.x * un.x + un.y * un.y);
+      gnew[o] = gold[o];
+      unew[o] = un;
+    }
+  }
+  const double2 r = en.block_sum2(num, den);
+  if (threadIdx.x == 0) *part = r;
+}
+
+// r^k = max_n sqrt(num_n / den_n) over the residual parts of one level.
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ double level_residual(Engine<T, NX, NT, S>& en, const double2* part, int Ns) {
+  __syncthreads();   // the last part was written by thread 0 of this workgroup
+  double m = 0.0;
+  for (int n = threadIdx.x; n < Ns; n += NT) {
+    const double2 q = part[n];
+    const double r = q.y > 0.0 ? sqrt(q.x / q.y) : (q.x > 0.0 ? INFINITY : 0.0);
+    m = (r > m || r != r) ? r : m;
+  }
+  return en.block_max(m);
 }
 
 // ------------------------------------------------- split coarse step -------

@@ -165,6 +165,8 @@ struct ap_ctx {
   int opt_grid = 0;          // workgroups of a persistent launch; 0 = all that fit
   CostCal cost;              // calibrated job durations (aparareal_autotune)
   int opt_graph = 0;         // replay pipelined launches from a captured hipGraph
+  int opt_skip = 1;          // slice skipping: exact slices n <= k are copied, not recomputed
+  int opt_sweeps = 0;        // tol > 0: iteration-ordered sweeps with host residual checks
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;   // private stream the graph is captured on
@@ -465,6 +467,8 @@ int solve_sweeps(ap_ctx* c, const double* u0, const ap_solve_params* p, double* 
 struct PipeShape {
   int nx = 0, Ns = 0, K = 0, steps = 0, M = 0, gs = 1, groups = 1;
   bool split = false, fp64 = false;
+  bool skip = true;          // slices n <= k of level k copy their exact values
+  double tol = 0.0;
   CostCal cal;
 };
 
@@ -520,6 +524,14 @@ double problem_jobs(int prob, const PipeShape& q, std::vector<SchedItem>& out) {
   const size_t first = out.size();
   for (int k = 0; k <= K; ++k)
     for (int n = 1; n <= Ns; ++n) {
+      if (q.skip && k >= 1 && n <= k) {
+        // exact slice: U(k,n) from U(k-1,n) or F(k-1,k); no fine slice F(k,n)
+        double ready = C(k - 1, n);
+        if (n == k) ready = std::max(ready, Fd(k - 1, n));
+        out.push_back({ready, 0.0, 0, {prob, ap::kJobCopy, k, n, 0}});
+        C(k, n) = ready + 1.0;
+        continue;
+      }
       const double ready = n > 1 ? C(k, n - 1) : 0.0;
       if (k < K) {
         Fd(k, n) = ready + jc.fine;
@@ -571,6 +583,7 @@ bool order_is_valid(const std::vector<ap::PipeJob>& jobs, const std::vector<Pipe
     clast[at] = pos;
     if (j.type == ap::kJobStage1) s1last[at] = pos;
     if (j.type == ap::kJobStage2 && s2first[at] == none) s2first[at] = pos;
+    if (j.type == ap::kJobCopy && (!q.skip || j.k < 1 || j.n > j.k)) return false;
   }
   for (size_t p = 0; p < shapes.size(); ++p) {
     const PipeShape& q = shapes[p];
@@ -579,6 +592,12 @@ bool order_is_valid(const std::vector<ap::PipeJob>& jobs, const std::vector<Pipe
       for (int n = 1; n <= q.Ns; ++n) {
         const size_t at = idx(k, n);
         if (cfirst[at] == none) return false;
+        if (q.skip && k >= 1 && n <= k) {
+          // copy job: after C(k-1,n) and, for n = k, after F(k-1,k); no fine slice
+          if (fpos[at] != none || clast[idx(k - 1, n)] >= cfirst[at]) return false;
+          if (n == k && (fpos[idx(k - 1, n)] == none || fpos[idx(k - 1, n)] >= cfirst[at])) return false;
+          continue;
+        }
         if (k < q.K && fpos[at] == none) return false;
         const long long prev_done = n > 1 ? clast[idx(k, n - 1)] : none;
         if (k < q.K && prev_done >= fpos[at]) return false;
@@ -664,6 +683,8 @@ int plan_item(ap_ctx* c, const double* u0, const ap_solve_params* p, double* U_o
   q.fp64 = p->precision == AP_PREC_FP64;
   q.split = c->opt_split < 0 ? q.groups >= 2 : c->opt_split != 0;
   q.cal = c->cost;
+  q.skip = c->opt_skip != 0;
+  q.tol = p->tol > 0.0 ? p->tol : 0.0;
   return AP_OK;
 }
 
@@ -674,7 +695,7 @@ ap::PipeProb<double> make_prob<double>(const PlanItem& it, int* cnt) {
   ap_ctx* c = it.c;
   return ap::PipeProb<double>{c->pp_U.as<cx<double>>(), c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(),
                               c->pp_part.as<double2>(), cnt, c->pp_P1.as<cx<double>>(), c->pp_P2.as<cx<double>>(),
-                              it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups,
+                              it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups, it.q.tol,
                               it.ft->coef64.as<cx<double>>(), it.ft->coef64.as<cx<double>>(), it.at->c64,
                               c->tabs.tw64, c->tabs.basis64};
 }
@@ -683,7 +704,7 @@ ap::PipeProb<float> make_prob<float>(const PlanItem& it, int* cnt) {
   ap_ctx* c = it.c;
   return ap::PipeProb<float>{c->pp_U.as<cx<double>>(), c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(),
                              c->pp_part.as<double2>(), cnt, c->pp_P1.as<cx<float>>(), c->pp_P2.as<cx<float>>(),
-                             it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups,
+                             it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups, it.q.tol,
                              it.ft->coef64.as<cx<double>>(), it.ft->coef32.as<cx<float>>(), it.at->c32,
                              c->tabs.tw32, c->tabs.basis32};
 }
@@ -751,7 +772,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
   for (auto& q : shapes)
     key += std::to_string(q.nx) + ":" + std::to_string(q.Ns) + ":" + std::to_string(q.K) + ":" +
            std::to_string(q.steps) + ":" + std::to_string(q.M) + ":" + std::to_string(q.gs) + ":" +
-           std::to_string(int(q.split)) + ":" + std::to_string(int(q.fp64)) + ":" +
+           std::to_string(int(q.split)) + ":" + std::to_string(int(q.fp64)) + ":" + std::to_string(int(q.skip)) + ":" +
            (q.cal.valid ? std::to_string(q.cal.fine_step) + "," + std::to_string(q.cal.stage1) + "," +
                               std::to_string(q.cal.stage2) + "," + std::to_string(q.cal.whole)
                         : std::string("-")) + ";";
@@ -783,8 +804,9 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
       const auto* b = reinterpret_cast<const unsigned char*>(&pr);
       probs.insert(probs.end(), b, b + sizeof(pr));
     }
+    const int* stop = it.q.tol > 0.0 ? cnt + (ap::pipe_counters(it.q.Ns, it.q.K) - 1) : nullptr;
     for (int k = 0; k < it.q.K; ++k)
-      rows.push_back({it.c->pp_part.as<double2>() + size_t(k) * it.q.Ns, it.resid + k, it.q.Ns});
+      rows.push_back({it.c->pp_part.as<double2>() + size_t(k) * it.q.Ns, it.resid + k, stop, it.q.Ns, k + 1});
   }
   if ((e = upload_if_changed(owner, owner->pp_prob, owner->pp_prob_host, probs)) != hipSuccess)
     return hip_fail(e, "problem descriptor upload");
@@ -832,8 +854,14 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
       });
       if (err != hipSuccess) return hip_fail(err, "resid");
     }
+    long long foff = 0;
     for (auto& it : items) {
       ap_ctx* c = it.c;
+      foff += ap::pipe_counters(it.q.Ns, it.q.K);
+      if (it.q.tol > 0.0 && it.q.K > 1 &&
+          (err = ap::launch_select_level(c->pp_U.as<cx<double>>(), it.q.Ns, it.q.K, c->KP, flags + foff - 1, st)) !=
+              hipSuccess)
+        return hip_fail(err, "level selection");
       const cx<double>* UK = c->pp_U.as<cx<double>>() + size_t(it.q.K) * (it.q.Ns + 1) * 3 * c->KP;
       err = run(AP_K_TO_PHYSICAL, [&] { return ap::launch_to_physical(c->N, UK, it.U_out, it.q.Ns + 1, c->tabs, st); });
       if (err != hipSuccess) return hip_fail(err, "to_physical");
@@ -1037,7 +1065,8 @@ int aparareal_solve(ap_ctx* c, const double* u0, const ap_solve_params* p, doubl
   if (e != hipSuccess) return hip_fail(e, "stream ordering");
   std::vector<PlanItem> items(1);
   if ((rc = plan_item(c, u0, p, U_out, resid, &items[0]))) return rc;
-  if (p->tol > 0.0) return solve_sweeps(c, u0, p, U_out, resid, s, items[0].q.steps, items[0].ft, items[0].at);
+  if (p->tol > 0.0 && c->opt_sweeps)
+    return solve_sweeps(c, u0, p, U_out, resid, s, items[0].q.steps, items[0].ft, items[0].at);
   return plan_launch(c, items, s);
 }
 
@@ -1052,7 +1081,6 @@ int aparareal_solve_batch(const ap_batch_item* batch, int count, void* stream) {
     if (rc) return rc;
     for (int j = 0; j < i; ++j)
       if (batch[j].ctx == c) return fail(AP_EINVAL, "a context may appear only once in a batch");
-    if (batch[i].params.tol > 0.0) return fail(AP_EINVAL, "batched solves run exactly K iterations (tol <= 0)");
     hipError_t e = order_stream(c, s);
     if (e != hipSuccess) return hip_fail(e, "stream ordering");
     if ((rc = plan_item(c, batch[i].u0, &batch[i].params, batch[i].U_out, batch[i].resid, &items[size_t(i)])))
@@ -1069,7 +1097,6 @@ int aparareal_autotune(const ap_batch_item* batch, int count, void* stream, doub
     if (rc) return rc;
     for (int j = 0; j < i; ++j)
       if (batch[j].ctx == batch[i].ctx) return fail(AP_EINVAL, "a context may appear only once in a batch");
-    if (batch[i].params.tol > 0.0) return fail(AP_EINVAL, "autotuning covers pipelined solves (tol <= 0)");
     hipError_t e = order_stream(batch[i].ctx, s);
     if (e != hipSuccess) return hip_fail(e, "stream ordering");
   }
@@ -1192,6 +1219,14 @@ int aparareal_set_option(ap_ctx* c, int option, int value) {
       if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_GRAPH takes 0 or 1");
       c->opt_graph = value;
       return AP_OK;
+    case AP_OPT_SKIP:
+      if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_SKIP takes 0 or 1");
+      c->opt_skip = value;
+      return AP_OK;
+    case AP_OPT_SWEEPS:
+      if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_SWEEPS takes 0 or 1");
+      c->opt_sweeps = value;
+      return AP_OK;
     default:
       return fail(AP_EINVAL, "unknown option");
   }
@@ -1206,6 +1241,8 @@ int aparareal_get_option(ap_ctx* c, int option, int* value) {
     case AP_OPT_GROUP: *value = group_size(c); return AP_OK;
     case AP_OPT_GRID: *value = c->opt_grid; return AP_OK;
     case AP_OPT_GRAPH: *value = c->opt_graph; return AP_OK;
+    case AP_OPT_SKIP: *value = c->opt_skip; return AP_OK;
+    case AP_OPT_SWEEPS: *value = c->opt_sweeps; return AP_OK;
     default: return fail(AP_EINVAL, "unknown option");
   }
 }
@@ -1240,6 +1277,7 @@ int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int 
   q.groups = ap::avg_groups(q.M, q.gs);
   q.fp64 = p->precision == AP_PREC_FP64;
   q.split = split < 0 ? q.groups >= 2 : split != 0;
+  q.skip = true;
   const std::vector<PipeShape> shapes{q};
   const std::vector<ap::PipeJob> jobs = schedule_jobs(shapes);
   if (!order_is_valid(jobs, shapes)) return fail(AP_EINVAL, "internal: job order is not topological");

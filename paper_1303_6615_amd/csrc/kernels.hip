@@ -17,6 +17,8 @@
 //                                order from one ticket counter, each waiting on
 //                                the done flags of the jobs it reads
 //   k_resid_rows               : r^k = max_n sqrt(num_n / den_n) per iteration
+#include <algorithm>
+
 #include "dispatch.hpp"
 #include "pipeline.hpp"
 
@@ -236,7 +238,25 @@ __global__ void __launch_bounds__(256) k_resid_rows(const double2* __restrict__ 
 __global__ void __launch_bounds__(256) k_resid_table(const ResidRow* __restrict__ rows,
                                                       const int* __restrict__ abort) {
   const ResidRow r = rows[blockIdx.x];
+  if (r.stop && *r.stop > 0 && r.level > *r.stop) {       // iteration not run: the solve stopped before it
+    if (threadIdx.x == 0) *r.out = -1.0;
+    return;
+  }
   resid_row(r.part, r.Ns, r.out, abort && *abort);
+}
+
+// U(K, 1..Ns) <- U(k, 1..Ns) when the solve stopped at level k < K (the
+// output rows; slice 0, the initial state, is held at level K only).
+__global__ void __launch_bounds__(256) k_select_level(cx<double>* __restrict__ U, int Ns, int K, int KP,
+                                                       const int* __restrict__ stop) {
+  const int k = *stop;
+  if (k <= 0 || k >= K) return;
+  const size_t row = size_t(Ns + 1) * 3 * KP;
+  const size_t n = size_t(Ns) * 3 * KP;
+  const cx<double>* src = U + size_t(k) * row + 3 * KP;
+  cx<double>* dst = U + size_t(K) * row + 3 * KP;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -412,6 +432,12 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
 hipError_t launch_resid(const double2* part, int Ns, int rows, double* out, const int* abort, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_resid_rows, dim3(rows), dim3(256), 0, s, part, Ns, out, abort);
+  return hipGetLastError();
+}
+hipError_t launch_select_level(cx<double>* U, int Ns, int K, int KP, const int* stop, hipStream_t s) {
+  const size_t n = size_t(Ns) * 3 * KP;
+  const int blocks = int(std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 1024)));
+  hipLaunchKernelGGL(k_select_level, dim3(blocks), dim3(256), 0, s, U, Ns, K, KP, stop);
   return hipGetLastError();
 }
 hipError_t launch_resid_rows(const ResidRow* rows, int nrows, const int* abort, hipStream_t s) {

@@ -48,8 +48,11 @@ struct CoarseTab {
 // (1-based).  A coarse step is either one job (kJobCoarse) or, split over
 // workgroups, one job per sample group g for each of its two averages
 // (kJobStage1, kJobStage2); the last stage-2 job of a step to finish applies
-// the step and the correction.
-enum : int { kJobCoarse = 0, kJobFine = 1, kJobStage1 = 2, kJobStage2 = 3 };
+// the step and the correction.  kJobCopy is the step C(k,n) of a slice that
+// iteration k has made exact (n <= k): its inputs equal those of C(k-1,n), so
+// U(k,n) = U(k-1,n) (n < k) or F(k-1,k) (n = k) and G(k,n) = G(k-1,n), and
+// the fine slices F(k,n), n <= k, are not run at all.
+enum : int { kJobCoarse = 0, kJobFine = 1, kJobStage1 = 2, kJobStage2 = 3, kJobCopy = 4 };
 struct PipeJob {
   int prob, type, k, n, g;
 };
@@ -59,7 +62,8 @@ struct PipeJob {
 //   F(k,n) done     at (K+1) Ns +  k Ns + n-1   (k = 0..K-1)
 //   stage-1 count   at (2K+1) Ns + k Ns + n-1   (k = 0..K)
 //   stage-2 count   at (3K+2) Ns + k Ns + n-1   (k = 0..K)
-inline long long pipe_counters(int Ns, int K) { return (4LL * K + 3) * Ns; }
+//   stopped level   at (4K+3) Ns                (0: running; k: residual r^k <= tol)
+inline long long pipe_counters(int Ns, int K) { return (4LL * K + 3) * Ns + 1; }
 
 // Per-problem device descriptor of the pipelined solve.
 template <typename T>
@@ -72,6 +76,7 @@ struct PipeProb {
   cx<T>* P1;           // [K+1][groups][3][KP] stage-1 group sums (split steps)
   cx<T>* P2;           // [K+1][groups][3][KP] stage-2 group sums
   int nx, Ns, K, steps, groups;
+  double tol;          // > 0: stop after the first level k with r^k <= tol
   const cx<double>* coef64;
   const cx<T>* coef;
   CoarseTab<T> ct;
@@ -125,8 +130,11 @@ hipError_t launch_resid(const double2* part, int Ns, int rows, double* out, cons
 struct ResidRow {
   const double2* part;
   double* out;
-  int Ns;
+  const int* stop;     // the problem's stopped level (NULL: never stops); rows past it get -1
+  int Ns, level;
 };
 hipError_t launch_resid_rows(const ResidRow* rows, int nrows, const int* abort, hipStream_t s);
+// If *stop = k in 1..K-1, copies U(k, 1..Ns) over U(K, 1..Ns) (the output rows).
+hipError_t launch_select_level(cx<double>* U, int Ns, int K, int KP, const int* stop, hipStream_t s);
 
 }  // namespace ap

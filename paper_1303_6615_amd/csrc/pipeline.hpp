@@ -63,7 +63,18 @@ struct PipeIdx {
   __device__ int fine(int k, int n) const { return (K + 1) * Ns + k * Ns + n - 1; }
   __device__ int stage1(int k, int n) const { return (2 * K + 1) * Ns + k * Ns + n - 1; }
   __device__ int stage2(int k, int n) const { return (3 * K + 2) * Ns + k * Ns + n - 1; }
+  __device__ int stopped() const { return (4 * K + 3) * Ns; }
 };
+
+// The job's level lies past the level at which its problem stopped (the
+// residual reached the tolerance): it publishes its counters without work.
+template <typename T>
+__device__ __forceinline__ bool past_stop(const PipeJob& jb, const PipeProb<T>& p) {
+  if (!(p.tol > 0.0) || jb.k == 0) return false;
+  const int st = __hip_atomic_load(&p.cnt[PipeIdx{p.Ns, p.K}.stopped()], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+  return st > 0 && jb.k > st;
+}
 
 // Dependencies a job waits for before it starts (thread 0).
 template <typename T>
@@ -71,6 +82,10 @@ __device__ __forceinline__ bool wait_deps(const PipeJob& jb, const PipeProb<T>& 
   const PipeIdx ix{p.Ns, p.K};
   const int k = jb.k, n = jb.n;
   if (jb.type == kJobStage2) return wait_count(&p.cnt[ix.stage1(k, n)], p.groups, diag, jt, ix.stage1(k, n));
+  if (jb.type == kJobCopy) {
+    if (n == k && !wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n))) return false;
+    return wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n));
+  }
   if (n > 1 && !wait_count(&p.cnt[ix.coarse(k, n - 1)], 1, diag, jt, ix.coarse(k, n - 1))) return false;
   if (jb.type == kJobCoarse && k >= 1) {
     if (!wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n))) return false;
@@ -96,22 +111,55 @@ constexpr size_t pipe_lds() {
 // `staged` tracks the twiddle table held in LDS across jobs.
 template <typename T, int NX>
 __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
-                                       const void*& staged, int* diag, int jt, int* s_flag) {
+                                       const void*& staged, int* diag, int jt, int* s_flag, bool skip) {
   constexpr int NT = kPipeThreads;
   constexpr int S = pipe_slots<T, NX>();
   using E_ = Engine<T, NX, NT, S>;
   constexpr int MPT = E_::MPT;
+  const PipeIdx ix{p.Ns, p.K};
+  const int Ns = p.Ns, k = jb.k, n = jb.n;
+  if (skip) {
+    // past the stopped level: publish only (stage-2 jobs still count in so
+    // that the last one publishes the step)
+    if (jb.type == kJobFine) return ix.fine(k, n);
+    if (jb.type == kJobStage1) return ix.stage1(k, n);
+    if (jb.type != kJobStage2) return ix.coarse(k, n);
+    if (threadIdx.x == 0) {
+      const int before = __hip_atomic_fetch_add(&p.cnt[ix.stage2(k, n)], 1, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+      *s_flag = before == p.groups - 1;
+    }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*s_flag) ? ix.coarse(k, n) : -1;
+  }
   const bool stage = staged != static_cast<const void*>(p.tw);
   E_ en(smem, p.tw, stage);
   staged = E_::TW_LDS ? static_cast<const void*>(p.tw) : nullptr;
-  const PipeIdx ix{p.Ns, p.K};
-  const int Ns = p.Ns, k = jb.k, n = jb.n;
   const size_t st = size_t(3) * E_::KP;
   auto state = [&](cx<double>* A, int lvl, int slice) { return A + (size_t(lvl) * (Ns + 1) + slice) * st; };
   const cx<double>* uprev = n == 1 ? state(p.U, 0, 0) : state(p.U, k, n - 1);
+  // Completing C(k, Ns) completes level k: with a tolerance, its residual
+  // decides whether the problem stops here (levels complete in order).
+  auto level_done = [&]() {
+    if (p.tol > 0.0 && k >= 1 && n == Ns) {
+      const double r = level_residual<T, NX, NT, S>(en, p.part + size_t(k - 1) * Ns, Ns);
+      if (threadIdx.x == 0 && r <= p.tol) {
+        int zero = 0;
+        __hip_atomic_compare_exchange_strong(&p.cnt[ix.stopped()], &zero, k, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    return ix.coarse(k, n);
+  };
   if (jb.type == kJobFine) {
     fine_job<T, NX, NT, S>(en, uprev, state(p.F, k, n), p.steps, p.coef64, p.coef, p.basis);
     return ix.fine(k, n);
+  }
+  if (jb.type == kJobCopy) {
+    copy_job<T, NX, NT, S>(en, n < k ? state(p.U, k - 1, n) : state(p.F, k - 1, n), state(p.U, k, n),
+                           state(p.G, k - 1, n), state(p.G, k, n), state(p.U, k - 1, n),
+                           p.part + size_t(k - 1) * Ns + (n - 1));
+    return level_done();
   }
   if (jb.type == kJobCoarse) {
     if (k == 0)
@@ -121,7 +169,7 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
       coarse_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, state(p.U, k, n), state(p.G, k, n),
                                state(p.G, k - 1, n), state(p.F, k - 1, n), state(p.U, k - 1, n),
                                p.part + size_t(k - 1) * Ns + (n - 1));
-    return ix.coarse(k, n);
+    return level_done();
   }
   // split step: group sums of level k live at P{1,2} + k * groups * st
   const size_t lvl = size_t(k) * p.groups * st;
@@ -160,15 +208,15 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
   else
     coarse_correct<T, NX, NT, S>(en, g, state(p.U, k, n), state(p.G, k, n), state(p.G, k - 1, n),
                                  state(p.F, k - 1, n), state(p.U, k - 1, n), p.part + size_t(k - 1) * Ns + (n - 1));
-  return ix.coarse(k, n);
+  return level_done();
 }
 
 template <typename T, int NX, int... REST>
 __device__ __forceinline__ int dispatch_job(int nx, unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
-                                            const void*& staged, int* diag, int jt, int* s_flag) {
-  if (nx == NX) return run_job<T, NX>(smem, jb, p, staged, diag, jt, s_flag);
+                                            const void*& staged, int* diag, int jt, int* s_flag, bool skip) {
+  if (nx == NX) return run_job<T, NX>(smem, jb, p, staged, diag, jt, s_flag, skip);
   if constexpr (sizeof...(REST) > 0)
-    return dispatch_job<T, REST...>(nx, smem, jb, p, staged, diag, jt, s_flag);
+    return dispatch_job<T, REST...>(nx, smem, jb, p, staged, diag, jt, s_flag, skip);
   else
     return -1;
 }
@@ -180,7 +228,7 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
                                                            const PipeProb<T>* __restrict__ probs, int* ticket,
                                                            int* abort, int* progress, unsigned long long* trace) {
   extern __shared__ unsigned char smem_raw[];
-  __shared__ int s_job, s_ok, s_flag;
+  __shared__ int s_job, s_ok, s_flag, s_skip;
   // Thread 0's scheduling work (publish the previous job's counter, take a
   // ticket, wait on the new job's dependencies) is one region at the top of
   // the body, between the end-of-job barrier and the hand-out barrier; the
@@ -203,13 +251,15 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
         }
       }
       const int jt = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      bool ok = true;
+      bool ok = true, skip = false;
       if (jt < njobs) {
         const PipeJob jb = jobs[jt];
-        ok = wait_deps(jb, probs[jb.prob], abort, jt);
+        skip = past_stop(jb, probs[jb.prob]);
+        if (!skip) ok = wait_deps(jb, probs[jb.prob], abort, jt);
       }
       s_job = jt;
       s_ok = ok;
+      s_skip = skip;
     }
     __syncthreads();
     const int j = __builtin_amdgcn_readfirstlane(s_job);
@@ -222,7 +272,9 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
     const PipeJob jb = jobs[j];
     const PipeProb<T>& p = probs[jb.prob];
     const int nx = __builtin_amdgcn_readfirstlane(p.nx);
-    pub = __builtin_amdgcn_readfirstlane(dispatch_job<T, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag));
+    const bool skip = __builtin_amdgcn_readfirstlane(s_skip) != 0;
+    pub = __builtin_amdgcn_readfirstlane(
+        dispatch_job<T, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip));
     pub_cnt = p.cnt;
     __syncthreads();
     if (trace && threadIdx.x == 0) trace[3 * j + 1] = wall_clock64();

@@ -309,7 +309,6 @@ int check_params(int N, double eps, double F, double nu, const ap_solve_params* 
   if (!(p->T > 0.0) || !std::isfinite(p->T) || p->slices < 1 || p->K < 0 || p->M_avg < 2 ||
       !(p->dt_fine > 0.0) || !std::isfinite(p->dt_fine) || !std::isfinite(p->T0))
     return serve_fail(AP_EINVAL, "bad solve parameters");
-  if (p->tol > 0.0) return serve_fail(AP_EINVAL, "served solves run exactly K iterations (tol <= 0)");
   if (p->T / p->slices / p->dt_fine > 1e7) return serve_fail(AP_EINVAL, "dT/dt_fine too large");
   if (size_t(2 * p->K + 1) * size_t(p->slices) > (size_t(1) << 26)) return serve_fail(AP_EINVAL, "problem too large");
   return AP_OK;

@@ -58,3 +58,17 @@ def sweep_flops(nx: int, M: int, slices: int) -> float:
 def state_bytes_modal(nx: int) -> int:
     """FP64 modal state: 3 fields x (Kd+1) complex doubles."""
     return 3 * (kd(nx) + 1) * 16
+
+
+def pipelined_work(nx: int, slices: int, K: int, steps: int, M: int, skip: bool = True):
+    """(fine grid-point-steps, algorithmic flops) of one pipelined solve.
+
+    With slice skipping, iteration k+1 does not re-run the fine slices n <= k
+    (exact after k iterations) and copies their coarse steps: K(K-1)/2 fine
+    slices and K(K+1)/2 coarse steps fewer when slices >= K.  Only the work
+    actually done is counted."""
+    fine_slices = sum(max(0, slices - (k if skip else 0)) for k in range(K))
+    coarse_steps = slices + sum(max(0, slices - (k if skip else 0)) for k in range(1, K + 1))
+    gp = fine_slices * steps * nx
+    flops = fine_flops(nx, fine_slices, steps) + coarse_step_flops(nx, M) * coarse_steps
+    return gp, flops

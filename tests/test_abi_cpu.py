@@ -54,14 +54,17 @@ def test_solve_params_layout_matches_header():
 def _deps(job, K, groups, split):
     """Jobs that must precede `job` = (type, k, n, g) in the hand-out order."""
     t, k, n, g = job
-    prev = []
-    if n > 1:
-        prev = [(3, k, n - 1, x) for x in range(groups)] if split else [(0, k, n - 1, 0)]
+
+    def step(kk, nn):            # the jobs that complete C(kk, nn)
+        if kk >= 1 and nn <= kk:
+            return [(4, kk, nn, 0)]
+        return [(3, kk, nn, x) for x in range(groups)] if split else [(0, kk, nn, 0)]
+    if t == 4:                   # exact slice: after C(k-1, n) and, for n = k, F(k-1, k)
+        return step(k - 1, n) + ([(1, k - 1, n, 0)] if n == k else [])
+    prev = step(k, n - 1) if n > 1 else []
     if t in (1, 2):
         return prev
-    before = []
-    if k >= 1:
-        before = [(1, k - 1, n, 0)] + ([(3, k - 1, n, x) for x in range(groups)] if split else [(0, k - 1, n, 0)])
+    before = [(1, k - 1, n, 0)] + step(k - 1, n) if k >= 1 else []
     if t == 0:
         return prev + before
     return [(2, k, n, x) for x in range(groups)] + before     # stage 2 (any may finish the step)
@@ -77,11 +80,14 @@ def test_pipeline_schedule_is_topological_and_drains(L, N, T, Ns, K, dt, M, spli
     groups = (M - 1 + gs - 1) // gs
     is_split = (groups >= 2) if split < 0 else bool(split)
     steps = max(1, math.ceil(T / Ns / dt - 1e-9))
-    want = {(1, k, n, 0) for k in range(K) for n in range(1, Ns + 1)}
+    # fine slices F(k, n) for n > k; slices n <= k of level k >= 1 are copies
+    want = {(1, k, n, 0) for k in range(K) for n in range(k + 1, Ns + 1)}
+    want |= {(4, k, n, 0) for k in range(1, K + 1) for n in range(1, min(k, Ns) + 1)}
+    real = [(k, n) for k in range(K + 1) for n in range(1, Ns + 1) if not (k >= 1 and n <= k)]
     if is_split:
-        want |= {(t, k, n, x) for t in (2, 3) for k in range(K + 1) for n in range(1, Ns + 1) for x in range(groups)}
+        want |= {(t, k, n, x) for t in (2, 3) for (k, n) in real for x in range(groups)}
     else:
-        want |= {(0, k, n, 0) for k in range(K + 1) for n in range(1, Ns + 1)}
+        want |= {(0, k, n, 0) for (k, n) in real}
     assert len(jobs) == len(want) and set(jobs) == want
     pos = {j: i for i, j in enumerate(jobs)}
     for j in jobs:
@@ -89,7 +95,7 @@ def test_pipeline_schedule_is_topological_and_drains(L, N, T, Ns, K, dt, M, spli
             assert pos[d] < pos[j], (j, d)
     # ticket scheduling with W workers: each takes the next job and waits for
     # its dependencies (durations in nonlinear evaluations)
-    dur = {0: 2 * (M - 1), 1: 4 * steps, 2: gs, 3: gs}
+    dur = {0: 2 * (M - 1), 1: 4 * steps, 2: gs, 3: gs, 4: 0.1}
     for W in (1, 3, 256):
         free = [0.0] * W
         end = {}
@@ -128,3 +134,15 @@ def test_serving_rejects_bad_arguments(L):
     assert L.aparareal_serve_poll(None, 1, None, None, None) == -1
     assert L.aparareal_serve_destroy(None) == -1
     assert b"null server" in L.aparareal_last_error()
+
+
+@pytest.mark.parametrize("Ns,K", [(64, 8), (16, 5), (3, 9), (256, 10)])
+def test_counted_work_matches_the_jobs_run(L, Ns, K):
+    # the benchmark counts fine slices and coarse steps actually computed
+    from paper_1303_6615_amd import metrics
+    jobs = binding.pipeline_schedule(256, 1.0, Ns, K, 0.001, 32, split=0)
+    fine = sum(1 for j in jobs if j[0] == 1)
+    coarse = sum(1 for j in jobs if j[0] == 0)
+    gp, flops = metrics.pipelined_work(256, Ns, K, 7, 32)
+    assert gp == fine * 7 * 256
+    assert flops == pytest.approx(metrics.fine_flops(256, fine, 7) + coarse * metrics.coarse_step_flops(256, 32))

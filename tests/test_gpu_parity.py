@@ -145,29 +145,60 @@ def test_solve(torch_cuda, cfg, prec, tol):
 
 @pytest.mark.parametrize("cfg,prec", [(C1, FP64), (C2, FP32)])
 def test_pipelined_solve_equals_iteration_order_bitwise(torch_cuda, cfg, prec):
-    # tol > 0 runs the iteration-by-iteration sweeps (tol far below reach: all K
-    # iterations); tol <= 0 runs the pipelined persistent launch.  Same bits.
+    # AP_OPT_SWEEPS with tol > 0 runs the iteration-by-iteration sweeps (tol far
+    # below reach: all K iterations); otherwise the pipelined persistent launch
+    # with slice skipping.  Same values.
+    from paper_1303_6615_amd.binding import AP_OPT_SWEEPS
     torch = torch_cuda
     u0 = torch.tensor(cfg.initial_state(), device="cuda")
     with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
         Up, rp = ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=prec)
+        ctx.set_option(AP_OPT_SWEEPS, 1)
         Us, rs = ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, tol=1e-300, precision=prec)
+        ctx.set_option(AP_OPT_SWEEPS, 0)
         Up2, rp2 = ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, precision=prec)
         torch.cuda.synchronize()
         assert torch.equal(Up, Us) and torch.equal(rp, rs)
         assert torch.equal(Up, Up2) and torch.equal(rp, rp2)      # run to run
 
 
-def test_tolerance_stops_early(torch_cuda):
+@pytest.mark.parametrize("cfg,prec,tol", [(C1, FP64, 1e-6), (C2, FP32, 1e-5)])
+def test_tolerance_stops_early(torch_cuda, cfg, prec, tol):
+    # the pipelined launch decides on the device to stop after the first
+    # iteration with r^k <= tol; the host-checked sweeps give the same values,
+    # and the output equals a solve run for exactly that many iterations
+    from paper_1303_6615_amd.binding import AP_OPT_SWEEPS
     torch = torch_cuda
-    cfg = C1
+    u0 = torch.tensor(cfg.initial_state(), device="cuda")
     with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
-        U, r = ctx.solve(torch.tensor(cfg.initial_state(), device="cuda"), cfg.T, cfg.slices, cfg.K,
-                         cfg.dt, cfg.Mbar, tol=1e-6, precision=FP64)
+        U, r = ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, tol=tol, precision=prec)
+        ctx.set_option(AP_OPT_SWEEPS, 1)
+        Us, rs = ctx.solve(u0, cfg.T, cfg.slices, cfg.K, cfg.dt, cfg.Mbar, tol=tol, precision=prec)
+        ctx.set_option(AP_OPT_SWEEPS, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(U, Us) and torch.equal(r, rs)
         r = r.cpu().numpy()
-    ran = r[r >= 0]
-    assert 0 < ran.size < cfg.K and ran[-1] <= 1e-6 and np.all(ran[:-1] > 1e-6)
-    assert np.all(r[ran.size:] == -1.0)
+        ran = r[r >= 0]
+        assert 0 < ran.size < cfg.K and ran[-1] <= tol and np.all(ran[:-1] > tol)
+        assert np.all(r[ran.size:] == -1.0)
+        Uk, rk = ctx.solve(u0, cfg.T, cfg.slices, ran.size, cfg.dt, cfg.Mbar, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(U, Uk) and np.array_equal(rk.cpu().numpy(), ran)
+
+
+@pytest.mark.parametrize("cfg,prec,split", [(C1, FP64, 0), (C1, FP64, 1), (C2, FP32, 1)])
+def test_slice_skipping_changes_no_value(torch_cuda, cfg, prec, split):
+    # slices n <= k are exact after k iterations: copying them instead of
+    # recomputing them leaves every value unchanged
+    from paper_1303_6615_amd.binding import AP_OPT_SKIP, AP_OPT_SPLIT
+    torch = torch_cuda
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        ctx.set_option(AP_OPT_SPLIT, split)
+        ctx.set_option(AP_OPT_SKIP, 0)
+        Ua, ra = _solve(ctx, torch, cfg, prec)
+        ctx.set_option(AP_OPT_SKIP, 1)
+        Ub, rb = _solve(ctx, torch, cfg, prec)
+    assert torch.equal(Ua, Ub) and torch.equal(ra, rb)
 
 
 def _solve(ctx, torch, cfg, prec, **kw):
@@ -370,3 +401,28 @@ def test_graph_replay_equals_eager_solves(torch_cuda):
             want = ref0 if rep % 2 == 0 else ref1
             assert torch.equal(out, want[0]) and torch.equal(resid, want[1]), rep
             assert torch.isfinite(junk)
+
+
+def test_batch_problems_stop_on_their_own_tolerance(torch_cuda):
+    from paper_1303_6615_amd.binding import _batch_items, _check, _stream, lib
+    torch = torch_cuda
+    probs = [_batch_problem(*_BATCH[i]) for i in (0, 1, 3)]
+    tols = [1e-4, 0.0, 1e-5]
+    ctxs = [_ctx(q["n"], q["eps"], q["nu"]) for q in probs]
+    try:
+        items = [(c, torch.tensor(q["u0"], device="cuda"), q["prm"]) for c, q in zip(ctxs, probs)]
+        arr, outs = _batch_items(items, FP32)
+        for i, t in enumerate(tols):
+            arr[i].params.tol = t
+        _check(lib().aparareal_solve_batch(arr, len(items), _stream(torch)))
+        torch.cuda.synchronize()
+        stopped = 0
+        for c, (_, u0, prm), (U, r, _), t in zip(ctxs, items, outs, tols):
+            Ua, ra = c.solve(u0, prm["T"], prm["slices"], prm["K"], prm["dt_fine"], prm["M"], tol=t, precision=FP32)
+            torch.cuda.synchronize()
+            assert torch.equal(U, Ua) and torch.equal(r, ra)
+            stopped += int((r.cpu().numpy() < 0).any())
+        assert stopped >= 1
+    finally:
+        for c in ctxs:
+            c.close()
