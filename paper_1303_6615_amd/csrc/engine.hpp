@@ -24,12 +24,12 @@ constexpr size_t y_bytes() {
 
 template <typename T, int NX>
 constexpr bool twiddles_in_lds() {
-  return NX * sizeof(cx<T>) + Slot<T, NX>::bytes + y_bytes<T, NX>() <= kLdsBudget;
+  return tw_elems<NX / 2>() * sizeof(cx<T>) + Slot<T, NX>::bytes + y_bytes<T, NX>() <= kLdsBudget;
 }
 
 template <typename T, int NX, int NT>
 constexpr int max_slots() {
-  const size_t fixed = (twiddles_in_lds<T, NX>() ? NX * sizeof(cx<T>) : 0) + y_bytes<T, NX>();
+  const size_t fixed = (twiddles_in_lds<T, NX>() ? tw_elems<NX / 2>() * sizeof(cx<T>) : 0) + y_bytes<T, NX>();
   const size_t s = (kLdsBudget - fixed) / Slot<T, NX>::bytes;
   return s >= 32 ? 32 : (s < 1 ? 1 : int(s));
 }
@@ -42,10 +42,11 @@ struct Engine {
   static constexpr int KP = G::KP;
   static constexpr int MPT = (KP + NT - 1) / NT;
   static constexpr bool TW_LDS = twiddles_in_lds<T, NX>();
+  static constexpr int TWN = tw_elems<NX / 2>();   // twiddle table entries
   static_assert(NT % 64 == 0, "whole wavefronts");
   static_assert(SL::ib_elems >= size_t(3) * KP, "per-sample contributions fit a slot's ib");
   static constexpr size_t lds_bytes() {
-    return (TW_LDS ? NX * sizeof(cx<T>) : 0) + S * SL::bytes + y_bytes<T, NX>();
+    return (TW_LDS ? TWN * sizeof(cx<T>) : 0) + S * SL::bytes + y_bytes<T, NX>();
   }
   static_assert(lds_bytes() <= 160 * 1024, "LDS budget of gfx950 exceeded");
   const cx<T>* tw;
@@ -60,11 +61,11 @@ struct Engine {
     cx<T>* base = reinterpret_cast<cx<T>*>(smem);
     if constexpr (TW_LDS) {
       if (stage) {
-        for (int i = threadIdx.x; i < NX; i += NT) base[i] = tw_global[i];
+        for (int i = threadIdx.x; i < TWN; i += NT) base[i] = tw_global[i];
         __syncthreads();
       }
       tw = base;
-      base += NX;
+      base += TWN;
     } else {
       tw = tw_global;
     }

@@ -29,6 +29,7 @@
 
 #include "../../include/aparareal.h"
 #include "launch.hpp"
+#include "wavefft.hpp"
 
 namespace {
 
@@ -959,12 +960,25 @@ ap_ctx* aparareal_create(int N, double eps, double F, double nu) {
     b64[k] = {1.0 / w, a / w};
     b32[k] = {float(1.0 / w), float(a / w)};
   }
-  std::vector<cx<double>> t64(N);
-  std::vector<cx<float>> t32(N);
-  for (int t = 0; t < N; ++t) {
-    const double th = 2.0 * M_PI * double(t) / double(N);
-    t64[t] = cx<double>{std::cos(th), -std::sin(th)};
-    t32[t] = cx<float>{float(std::cos(th)), float(-std::sin(th))};
+  // twiddles: exp(-2 pi i t/N), t < N, then the per-pass tables of the
+  // wave-local FFT of length N/2 (exp(-2 pi i q k/(NS R)) at (q-1) NS + k)
+  std::vector<cx<double>> t64;
+  std::vector<cx<float>> t32;
+  auto push = [&](double th) {
+    t64.push_back(cx<double>{std::cos(th), -std::sin(th)});
+    t32.push_back(cx<float>{float(std::cos(th)), float(-std::sin(th))});
+  };
+  for (int t = 0; t < N; ++t) push(2.0 * M_PI * double(t) / double(N));
+  {
+    int r[3], npass = 0;
+    ap::wave_plan_radices(N / 2, r, &npass);
+    int NS = r[0];
+    for (int j = 1; j < npass; ++j) {
+      const int R = r[j];
+      for (int q = 1; q < R; ++q)
+        for (int k = 0; k < NS; ++k) push(2.0 * M_PI * double(q) * double(k) / double(NS * R));
+      NS *= R;
+    }
   }
   if ((e = c->tw64.upload(t64)) != hipSuccess || (e = c->tw32.upload(t32)) != hipSuccess ||
       (e = c->basis64.upload(b64)) != hipSuccess || (e = c->basis32.upload(b32)) != hipSuccess) {

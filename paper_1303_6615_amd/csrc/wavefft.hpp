@@ -95,13 +95,76 @@ template <> struct WavePlan<256>  { static constexpr int G = 64, n = 3, r0 = 4, 
 template <> struct WavePlan<512>  { static constexpr int G = 64, n = 3, r0 = 8,  r1 = 8, r2 = 8; };
 template <> struct WavePlan<1024> { static constexpr int G = 64, n = 3, r0 = 16, r1 = 8, r2 = 8; };
 
+// Twiddle table of a grid size N = 2P: entries t < N hold exp(-2 pi i t/N)
+// (real-signal pre/post-processing); then, for the passes after the first,
+// exp(-2 pi i q k / (NS R)) at [(q-1) NS + k] (q = 1..R-1, k < NS; NS points
+// combined before the pass, radix R), contiguous in k so that the lanes of a
+// pass read consecutive entries.
+template <int P>
+constexpr int pass1_tw_offset() { return 2 * P; }
+template <int P>
+constexpr int pass2_tw_offset() { return 2 * P + (WavePlan<P>::r1 - 1) * WavePlan<P>::r0; }
+template <int P>
+constexpr int tw_elems() {
+  using PL = WavePlan<P>;
+  return PL::n == 3 ? pass2_tw_offset<P>() + (PL::r2 - 1) * PL::r0 * PL::r1 : pass2_tw_offset<P>();
+}
+
+// The radices of the plan for transform length P (host side, for the tables).
+inline void wave_plan_radices(int P, int r[3], int* n) {
+  switch (P) {
+    case 32: r[0] = 4; r[1] = 8; r[2] = 1; *n = 2; return;
+    case 64: r[0] = 4; r[1] = 4; r[2] = 4; *n = 3; return;
+    case 128: r[0] = 4; r[1] = 4; r[2] = 8; *n = 3; return;
+    case 256: r[0] = 4; r[1] = 8; r[2] = 8; *n = 3; return;
+    case 512: r[0] = 8; r[1] = 8; r[2] = 8; *n = 3; return;
+    default: r[0] = 16; r[1] = 8; r[2] = 8; *n = 3; return;
+  }
+}
+
+// LDS layouts between passes.  A pass writes position pos to
+// (pos with the bits inside its bank row XORed by f(row)), row = pos / E with
+// E the elements per row of the 64 four-byte banks (32 complex floats, 16
+// complex doubles); the next pass reads through the same map.  Loads of
+// E consecutive positions stay one permuted row; f per pass makes the
+// stride-R stores of that pass hit distinct banks (chosen by a model of the
+// bank mapping).  The last pass writes natural order (its stores are
+// consecutive already), which is what the consumers read.
+enum : int { kSwzId = 0, kSwzR = 1, kSwzR5 = 2, kSwzR9 = 3, kSwzRx2 = 4, kSwzRx1 = 5 };
+template <typename T, int CODE>
+__device__ __forceinline__ int swz(int pos) {
+  if constexpr (CODE == kSwzId) {
+    return pos;
+  } else {
+    constexpr int rb = sizeof(T) == 4 ? 5 : 4;   // complex float: 32 per row; complex double: 16
+    constexpr int m = (1 << rb) - 1;
+    const int r = pos >> rb;
+    int f;
+    if constexpr (CODE == kSwzR) f = r;
+    else if constexpr (CODE == kSwzR5) f = r * 5;
+    else if constexpr (CODE == kSwzR9) f = r * 9;
+    else if constexpr (CODE == kSwzRx2) f = r ^ (r << 2);
+    else f = r ^ (r << 1);
+    return pos ^ (f & m);
+  }
+}
+// layout written by pass 0 / pass 1 (not the last) for transform length P
+template <typename T, int P>
+constexpr int swz_pass0() { return kSwzR; }
+template <typename T, int P>
+constexpr int swz_pass1() {
+  if constexpr (sizeof(T) == 4) return P <= 128 ? kSwzR5 : P == 256 ? kSwzR9 : kSwzRx2;
+  else return P <= 256 ? kSwzR5 : P == 512 ? kSwzRx1 : kSwzId;
+}
+
 // One in-place Stockham pass of radix R after NS points have been combined,
 // by the G lanes of one signal group: butterfly b (b = lig, lig + G, ...)
 // reads positions b + q P/R (through `load` on the first pass), twiddles by
-// exp(DIR 2 pi i q k / (NS R)), k = b mod NS, and writes (b - k) R + k + q NS.
-// tw[t] = exp(-2 pi i t / (2P)).  Every lane of the wavefront executes the
-// synchronisations; lanes of an inactive group skip loads and stores.
-template <typename T, int P, int R, int NS, int DIR, int G, typename Load>
+// exp(DIR 2 pi i q k / (NS R)), k = b mod NS (table at tw + TWO), and writes
+// (b - k) R + k + q NS through the layout map SWO.  Every lane of the
+// wavefront executes the synchronisations; lanes of an inactive group skip
+// loads and stores.
+template <typename T, int P, int R, int NS, int DIR, int G, int TWO, int SWO, typename Load>
 __device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, int lig, bool active, Load&& load) {
   constexpr int NB = P / R;
   constexpr int BPL = (NB + G - 1) / G;
@@ -116,7 +179,7 @@ __device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, int lig, 
         const int k = b & (NS - 1);
 #pragma unroll
         for (int q = 1; q < R; ++q) {
-          cx<T> w = tw[2 * (q * k * (P / (NS * R)))];
+          cx<T> w = tw[TWO + (q - 1) * NS + k];
           if (DIR > 0) w = conj(w);
           x[i][q] = x[i][q] * w;
         }
@@ -130,9 +193,9 @@ __device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, int lig, 
     const int b = lig + G * i;
     if (active && (NB % G == 0 || b < NB)) {
       const int k = b & (NS - 1);
-      cx<T>* d = buf + (b - k) * R + k;
+      const int d = (b - k) * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) d[q * NS] = x[i][q];
+      for (int q = 0; q < R; ++q) buf[swz<T, SWO>(d + q * NS)] = x[i][q];
     }
   }
   wave_sync();
@@ -143,10 +206,16 @@ __device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, int lig, 
 template <typename T, int P, int DIR, typename Load>
 __device__ __forceinline__ void wave_fft(cx<T>* buf, const cx<T>* tw, int lig, bool active, Load&& load) {
   using PL = WavePlan<P>;
-  auto self = [buf](int i) { return buf[i]; };
-  wave_pass<T, P, PL::r0, 1, DIR, PL::G>(buf, tw, lig, active, load);
-  wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G>(buf, tw, lig, active, self);
-  if constexpr (PL::n == 3) wave_pass<T, P, PL::r2, PL::r0 * PL::r1, DIR, PL::G>(buf, tw, lig, active, self);
+  constexpr int S0 = swz_pass0<T, P>();
+  constexpr int S1 = PL::n == 3 ? swz_pass1<T, P>() : kSwzId;
+  auto read0 = [buf](int i) { return buf[swz<T, S0>(i)]; };
+  wave_pass<T, P, PL::r0, 1, DIR, PL::G, 0, S0>(buf, tw, lig, active, load);
+  wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, pass1_tw_offset<P>(), S1>(buf, tw, lig, active, read0);
+  if constexpr (PL::n == 3) {
+    auto read1 = [buf](int i) { return buf[swz<T, S1>(i)]; };
+    wave_pass<T, P, PL::r2, PL::r0 * PL::r1, DIR, PL::G, pass2_tw_offset<P>(), kSwzId>(buf, tw, lig, active,
+                                                                                       read1);
+  }
 }
 
 // LDS per state slot: SP [3][P+1] (half spectra in; forward transforms out)
