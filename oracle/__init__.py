@@ -15,6 +15,8 @@ What each module follows:
   matfun     f(hA_k) for A_k = -L_k/eps + D_k via the eigenstructure of L
              (Sec. 6.1, eigenvalues i*omega_k^alpha); scalar exp and phi_j
   etdrk4     the fine propagator: Cox-Matthews ETDRK4 (cited in Sec. 6.2)
+  strang     the Strang-splitting propagator (Alg. 3), fine solver and the
+             coarse solver of standard parareal
   hmm        the kernel rho, the trapezoid-rule time average of the
              nonlinear term (eq. numerical average; Alg. 1) and the
              asymptotic slow solver (Alg. 2)
@@ -33,6 +35,7 @@ from .spectral import (  # noqa: F401
 )
 from .matfun import etdrk4_coefficients, fast_rotation, linear_propagator  # noqa: F401
 from .etdrk4 import fine_propagate  # noqa: F401
+from .strang import strang_propagate  # noqa: F401
 from .hmm import rho, rho_normaliser, average_weights, averaged_nonlinear, coarse_propagate  # noqa: F401
 from .parareal import parareal_solve, serial_fine  # noqa: F401
 from .model import estimated_speedup, speedup_upper_bound  # noqa: F401
