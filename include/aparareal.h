@@ -74,6 +74,15 @@ int aparareal_nonlinear(ap_ctx* ctx, const double* U_in, double* N_out, int batc
 int aparareal_fine_batch(ap_ctx* ctx, const double* U_in, double* U_out, int batch,
                          double dT, int steps, int precision, void* stream);
 
+/* Strang-splitting propagator (Alg. 3): `steps` steps of length h = dT/steps,
+ * each a half step of the exact linear flow exp((h/2)(-L/eps + D)), a
+ * midpoint step of the nonlinear flow v <- v + h N(v + (h/2) N(v)), and a
+ * second half step; for every state of the batch at once.  It is the fine
+ * solver of Alg. 3 and, with steps = 1, the coarse solver of standard
+ * parareal.  U_in, U_out physical [batch][3][N]; U_out may not alias U_in.   */
+int aparareal_strang_batch(ap_ctx* ctx, const double* U_in, double* U_out, int batch,
+                           double dT, int steps, int precision, void* stream);
+
 /* Kernel-weighted time average of the nonlinear term (Sec. 2, eq. numerical
  * average; Alg. 1): Nbar(u) = (1/M) sum_{m<M} rho(m/M) exp(s_m L) N(exp(-s_m L) u),
  * s_m = m T0 / M (fast time), rho the smooth bump of Sec. 2.
@@ -158,8 +167,18 @@ int aparareal_solve_batch(const ap_batch_item* items, int count, void* stream);
  *                 every iteration is computed.
  *   AP_OPT_SWEEPS 1: aparareal_solve with tol > 0 runs the iterations one by
  *                 one (a fine batch and a serial coarse sweep each) with a
- *                 host check of the residual; 0 (default): pipelined.       */
-enum { AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2, AP_OPT_GRAPH = 3, AP_OPT_SKIP = 4, AP_OPT_SWEEPS = 5 };
+ *                 host check of the residual; 0 (default): pipelined.
+ *                 ETDRK4 fine slices and asymptotic coarse steps only.
+ *   AP_OPT_FINE   fine solver of the pipelined solve: 0 (default) ETDRK4,
+ *                 1 Strang steps (Alg. 3, aparareal_strang_batch).
+ *   AP_OPT_COARSE coarse solver: 0 (default) the asymptotic step (Alg. 2);
+ *                 1 one Strang step of length dT, i.e. standard parareal
+ *                 on the full equation (the paper's comparison, Sec. 6.2);
+ *                 M_avg and T0 are then unused.                              */
+enum {
+  AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2, AP_OPT_GRAPH = 3, AP_OPT_SKIP = 4, AP_OPT_SWEEPS = 5,
+  AP_OPT_FINE = 6, AP_OPT_COARSE = 7
+};
 int aparareal_set_option(ap_ctx* ctx, int option, int value);
 int aparareal_get_option(ap_ctx* ctx, int option, int* value);
 

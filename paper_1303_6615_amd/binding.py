@@ -39,6 +39,7 @@ class BatchItem(ctypes.Structure):
 
 
 AP_OPT_SPLIT, AP_OPT_GROUP, AP_OPT_GRID, AP_OPT_GRAPH, AP_OPT_SKIP, AP_OPT_SWEEPS = 0, 1, 2, 3, 4, 5
+AP_OPT_FINE, AP_OPT_COARSE = 6, 7
 JOB_COARSE, JOB_FINE, JOB_STAGE1, JOB_STAGE2, JOB_COPY = 0, 1, 2, 3, 4
 
 
@@ -51,6 +52,7 @@ _SIGNATURES = {
     "aparareal_destroy": (_i, [_vp]),
     "aparareal_nonlinear": (_i, [_vp, _dp, _dp, _i, _i, _vp]),
     "aparareal_fine_batch": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
+    "aparareal_strang_batch": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
     "aparareal_average": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
     "aparareal_coarse": (_i, [_vp, _dp, _dp, _i, _d, _i, _d, _i, _vp]),
     "aparareal_solve": (_i, [_vp, _dp, ctypes.POINTER(SolveParams), _dp, _dp, _vp]),
@@ -214,6 +216,9 @@ class Context:
 
     def fine_batch(self, U, dT: float, steps: int, precision: int = AP_PREC_FP32, out=None):
         return self._batched(lib().aparareal_fine_batch, U, float(dT), int(steps), precision, out=out)
+
+    def strang_batch(self, U, dT: float, steps: int, precision: int = AP_PREC_FP32, out=None):
+        return self._batched(lib().aparareal_strang_batch, U, float(dT), int(steps), precision, out=out)
 
     def average(self, U, T0: float, M: int, precision: int = AP_PREC_FP32, out=None):
         return self._batched(lib().aparareal_average, U, float(T0), int(M), precision, out=out)

@@ -235,6 +235,81 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, const cx<doub
       for (int al = 0; al < 3; ++al) dst[al * KP + E_::mode(j)] = c[j][al];
 }
 
+// --------------------------------------------------------- Strang steps ---
+// Strang splitting (Alg. 3) on owned-mode registers c (FP64): per step of
+// size h, the half step of the linear flow (E2 = e^{(h/2) lambda} per
+// (k, alpha), FP64), the midpoint step of the nonlinear flow
+// v <- v + h N(v + (h/2) N(v)), and the second half step.  The evaluations and
+// the midpoint state run in T; the state and its update stay in FP64.
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void strang_regs(Engine<T, NX, NT, S>& en, cx<double> (&c)[Engine<T, NX, NT, S>::MPT][3],
+                                            int steps, const cx<double> (&cE2)[Engine<T, NX, NT, S>::MPT][3],
+                                            double h, const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT]) {
+  constexpr int MPT = Engine<T, NX, NT, S>::MPT;
+  const T hh = T(0.5 * h), hT = T(h);
+  int slot = 0;
+  cx<T> st[MPT][3], nv[MPT][3];
+  cx<double> v[MPT][3];
+  for (int step = 0; step < steps; ++step) {
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        v[j][al] = cE2[j][al] * c[j][al];
+        st[j][al] = cvt<T>(v[j][al]);
+      }
+    en.neval(slot, st, nv, bs);
+    if constexpr (S >= 2) slot ^= 1;
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+#pragma unroll
+      for (int al = 0; al < 3; ++al) st[j][al] = st[j][al] + hh * nv[j][al];
+    en.neval(slot, st, nv, bs);
+    if constexpr (S >= 2) slot ^= 1;
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+#pragma unroll
+      for (int al = 0; al < 3; ++al) c[j][al] = cE2[j][al] * (v[j][al] + cvt<double>(hT * nv[j][al]));
+  }
+}
+
+// Owned modes of the FP64 coefficient slot `slot` of a [8][3][KP] table.
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void load_coef64(const cx<double>* __restrict__ coef64, int slot,
+                                            cx<double> (&out)[Engine<T, NX, NT, S>::MPT][3]) {
+  using E_ = Engine<T, NX, NT, S>;
+#pragma unroll
+  for (int j = 0; j < E_::MPT; ++j) {
+    const int k = E_::valid(j) ? E_::mode(j) : E_::KP - 1;
+    for (int al = 0; al < 3; ++al) out[j][al] = coef64[size_t(slot) * 3 * E_::KP + al * E_::KP + k];
+  }
+}
+
+// `steps` Strang steps of size h from src to dst (modal FP64; the table's slot
+// 2 holds E2 = e^{(h/2) lambda}).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void strang_job(Engine<T, NX, NT, S>& en, const cx<double>* __restrict__ src,
+                                           cx<double>* __restrict__ dst, int steps,
+                                           const cx<double>* __restrict__ coef64, double h,
+                                           const Basis<T>* __restrict__ basis) {
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int MPT = E_::MPT;
+  cx<double> c[MPT][3], cE2[MPT][3];
+  Basis<T> bs[MPT];
+#pragma unroll
+  for (int j = 0; j < MPT; ++j) {
+    const int k = E_::valid(j) ? E_::mode(j) : E_::KP - 1;
+    bs[j] = basis[k];
+    for (int al = 0; al < 3; ++al) c[j][al] = src[al * E_::KP + k];
+  }
+  load_coef64<T, NX, NT, S>(coef64, 2, cE2);
+  strang_regs<T, NX, NT, S>(en, c, steps, cE2, h, bs);
+#pragma unroll
+  for (int j = 0; j < MPT; ++j)
+    if (E_::valid(j))
+      for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = c[j][al];
+}
+
 // ----------------------------------------------------------- time average ---
 // Nbar contributions of the samples m in [mb, me) of the owned-mode state yv,
 // with min(S, me - m0) samples in flight.  [mb, me) covers whole groups of
@@ -400,9 +475,9 @@ __device__ __forceinline__ void load_owned(const cx<double>* __restrict__ src,
 //   weights (1 for k = 0, 2 otherwise).
 // Every location is read before it is written by the same thread, so unew may
 // alias uold and gnew may alias gold (the in-place serial sweep).
-template <typename T, int NX, int NT, int S>
+template <typename T, int NX, int NT, int S, typename GT = T>
 __device__ __forceinline__ void coarse_correct(Engine<T, NX, NT, S>& en,
-                                               const cx<T> (&g)[Engine<T, NX, NT, S>::MPT][3], cx<double>* unew,
+                                               const cx<GT> (&g)[Engine<T, NX, NT, S>::MPT][3], cx<double>* unew,
                                                cx<double>* gnew, const cx<double>* gold, const cx<double>* fold,
                                                const cx<double>* uold, double2* part) {
   using E_ = Engine<T, NX, NT, S>;
@@ -431,6 +506,29 @@ __device__ __forceinline__ void coarse_correct(Engine<T, NX, NT, S>& en,
     const double2 r = en.block_sum2(num, den);
     if (threadIdx.x == 0) *part = r;
   }
+}
+
+// The coarse job of standard parareal: g = one Strang step of size dT
+// (table slot 2: e^{(dT/2) lambda}) from uprev, then the correction.
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void strang_coarse_job(Engine<T, NX, NT, S>& en, const cx<double>* __restrict__ ccoef64,
+                                                  double dT, const Basis<T>* __restrict__ basis,
+                                                  const cx<double>* uprev, cx<double>* unew, cx<double>* gnew,
+                                                  const cx<double>* gold, const cx<double>* fold,
+                                                  const cx<double>* uold, double2* part) {
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int MPT = E_::MPT;
+  cx<double> g[MPT][3], cE2[MPT][3];
+  Basis<T> bs[MPT];
+#pragma unroll
+  for (int j = 0; j < MPT; ++j) {
+    const int k = E_::valid(j) ? E_::mode(j) : 0;
+    bs[j] = basis[k];
+    for (int al = 0; al < 3; ++al) g[j][al] = E_::valid(j) ? uprev[al * E_::KP + k] : czero<double>();
+  }
+  load_coef64<T, NX, NT, S>(ccoef64, 2, cE2);
+  strang_regs<T, NX, NT, S>(en, g, 1, cE2, dT, bs);
+  coarse_correct<T, NX, NT, S, double>(en, g, unew, gnew, gold, fold, uold, part);
 }
 
 // One coarse job of the parareal iteration on modal FP64 states, in one

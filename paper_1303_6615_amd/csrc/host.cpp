@@ -168,6 +168,8 @@ struct ap_ctx {
   int opt_graph = 0;         // replay pipelined launches from a captured hipGraph
   int opt_skip = 1;          // slice skipping: exact slices n <= k are copied, not recomputed
   int opt_sweeps = 0;        // tol > 0: iteration-ordered sweeps with host residual checks
+  int opt_fine = 0;          // fine slices: 0 ETDRK4, 1 Strang steps (Alg. 3)
+  int opt_coarse = 0;        // coarse step: 0 asymptotic (Alg. 2), 1 one Strang step (standard parareal)
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;   // private stream the graph is captured on
@@ -469,6 +471,7 @@ struct PipeShape {
   int nx = 0, Ns = 0, K = 0, steps = 0, M = 0, gs = 1, groups = 1;
   bool split = false, fp64 = false;
   bool skip = true;          // slices n <= k of level k copy their exact values
+  int fine_kind = 0, coarse_kind = 0;
   double tol = 0.0;
   CostCal cal;
 };
@@ -491,11 +494,11 @@ JobCost job_cost(const PipeShape& q) {
   const int per_round = 8 * (64 / G);
   auto rounds = [&](int samples) { return double((3 * samples + per_round - 1) / per_round); };
   JobCost c;
-  c.fine = 4.0 * ev * q.steps + 2.0;
+  c.fine = (q.fine_kind == 1 ? 2.0 : 4.0) * ev * q.steps + 2.0;
   c.stage1 = 3.0 + 1.5 * rounds(q.gs) * ev;
   c.stage2 = c.stage1 + 3.0;
   c.finish = 0.5;
-  c.whole = 2.0 * (3.0 + 2.2 * rounds(q.M - 1) * ev) + 1.0;
+  c.whole = q.coarse_kind == 1 ? 2.0 * ev + 3.0 : 2.0 * (3.0 + 2.2 * rounds(q.M - 1) * ev) + 1.0;
   if (q.cal.valid) {
     if (q.cal.fine_step > 0) c.fine = q.cal.fine_step * q.steps;
     if (q.cal.stage1 > 0) c.stage1 = q.cal.stage1;
@@ -643,6 +646,7 @@ struct PlanItem {
   double* resid = nullptr;
   FineTables* ft = nullptr;
   AvgTables* at = nullptr;
+  FineTables* cft = nullptr;   // Strang coarse: tables for h = dT
   PipeShape q;
 };
 
@@ -683,6 +687,12 @@ int plan_item(ap_ctx* c, const double* u0, const ap_solve_params* p, double* U_o
   q.groups = ap::avg_groups(q.M, q.gs);
   q.fp64 = p->precision == AP_PREC_FP64;
   q.split = c->opt_split < 0 ? q.groups >= 2 : c->opt_split != 0;
+  q.fine_kind = c->opt_fine;
+  q.coarse_kind = c->opt_coarse;
+  if (q.coarse_kind == 1) {
+    q.split = false;                       // one Strang step: nothing to split
+    if ((rc = fine_tables(c, dT, &it->cft))) return rc;
+  }
   q.cal = c->cost;
   q.skip = c->opt_skip != 0;
   q.tol = p->tol > 0.0 ? p->tol : 0.0;
@@ -696,7 +706,9 @@ ap::PipeProb<double> make_prob<double>(const PlanItem& it, int* cnt) {
   ap_ctx* c = it.c;
   return ap::PipeProb<double>{c->pp_U.as<cx<double>>(), c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(),
                               c->pp_part.as<double2>(), cnt, c->pp_P1.as<cx<double>>(), c->pp_P2.as<cx<double>>(),
-                              it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups, it.q.tol,
+                              it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups, it.q.fine_kind, it.q.coarse_kind,
+                              it.p.T / it.q.Ns / it.q.steps, it.p.T / it.q.Ns,
+                              it.cft ? it.cft->coef64.as<cx<double>>() : nullptr, it.q.tol,
                               it.ft->coef64.as<cx<double>>(), it.ft->coef64.as<cx<double>>(), it.at->c64,
                               c->tabs.tw64, c->tabs.basis64};
 }
@@ -705,7 +717,9 @@ ap::PipeProb<float> make_prob<float>(const PlanItem& it, int* cnt) {
   ap_ctx* c = it.c;
   return ap::PipeProb<float>{c->pp_U.as<cx<double>>(), c->pp_F.as<cx<double>>(), c->pp_G.as<cx<double>>(),
                              c->pp_part.as<double2>(), cnt, c->pp_P1.as<cx<float>>(), c->pp_P2.as<cx<float>>(),
-                             it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups, it.q.tol,
+                             it.q.nx, it.q.Ns, it.q.K, it.q.steps, it.q.groups, it.q.fine_kind, it.q.coarse_kind,
+                             it.p.T / it.q.Ns / it.q.steps, it.p.T / it.q.Ns,
+                             it.cft ? it.cft->coef64.as<cx<double>>() : nullptr, it.q.tol,
                              it.ft->coef64.as<cx<double>>(), it.ft->coef32.as<cx<float>>(), it.at->c32,
                              c->tabs.tw32, c->tabs.basis32};
 }
@@ -774,6 +788,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     key += std::to_string(q.nx) + ":" + std::to_string(q.Ns) + ":" + std::to_string(q.K) + ":" +
            std::to_string(q.steps) + ":" + std::to_string(q.M) + ":" + std::to_string(q.gs) + ":" +
            std::to_string(int(q.split)) + ":" + std::to_string(int(q.fp64)) + ":" + std::to_string(int(q.skip)) + ":" +
+           std::to_string(q.fine_kind) + std::to_string(q.coarse_kind) + ":" +
            (q.cal.valid ? std::to_string(q.cal.fine_step) + "," + std::to_string(q.cal.stage1) + "," +
                               std::to_string(q.cal.stage2) + "," + std::to_string(q.cal.whole)
                         : std::string("-")) + ";";
@@ -1031,6 +1046,24 @@ int aparareal_fine_batch(ap_ctx* c, const double* U_in, double* U_out, int batch
   return batch_epilogue(c, U_out, batch, s);
 }
 
+int aparareal_strang_batch(ap_ctx* c, const double* U_in, double* U_out, int batch, double dT, int steps,
+                           int precision, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c && !(dT > 0.0 && std::isfinite(dT))) return fail(AP_EINVAL, "dT must be > 0");
+  if (c && steps < 1) return fail(AP_EINVAL, "steps must be >= 1");
+  if (c && U_in && U_in == U_out) return fail(AP_EINVAL, "U_out may not alias U_in");
+  int rc = batch_prologue(c, U_in, U_out, batch, precision, s);
+  if (rc || batch == 0) return rc;
+  FineTables* ft = nullptr;
+  if ((rc = fine_tables(c, dT / steps, &ft))) return rc;
+  hipError_t e = timed(c, AP_K_FINE, s, [&] {
+    return ap::launch_strang(c->N, precision == AP_PREC_FP64, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(),
+                             batch, steps, dT / steps, ft->coef64.as<cx<double>>(), c->tabs, s);
+  });
+  if (e != hipSuccess) return hip_fail(e, "strang launch");
+  return batch_epilogue(c, U_out, batch, s);
+}
+
 int aparareal_average(ap_ctx* c, const double* U_in, double* N_out, int batch, double T0, int M_avg,
                       int precision, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1079,8 +1112,11 @@ int aparareal_solve(ap_ctx* c, const double* u0, const ap_solve_params* p, doubl
   if (e != hipSuccess) return hip_fail(e, "stream ordering");
   std::vector<PlanItem> items(1);
   if ((rc = plan_item(c, u0, p, U_out, resid, &items[0]))) return rc;
-  if (p->tol > 0.0 && c->opt_sweeps)
+  if (p->tol > 0.0 && c->opt_sweeps) {
+    if (c->opt_fine || c->opt_coarse)
+      return fail(AP_EINVAL, "the host-checked sweeps run ETDRK4 fine slices and asymptotic coarse steps only");
     return solve_sweeps(c, u0, p, U_out, resid, s, items[0].q.steps, items[0].ft, items[0].at);
+  }
   return plan_launch(c, items, s);
 }
 
@@ -1241,6 +1277,14 @@ int aparareal_set_option(ap_ctx* c, int option, int value) {
       if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_SWEEPS takes 0 or 1");
       c->opt_sweeps = value;
       return AP_OK;
+    case AP_OPT_FINE:
+      if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_FINE takes 0 (ETDRK4) or 1 (Strang)");
+      c->opt_fine = value;
+      return AP_OK;
+    case AP_OPT_COARSE:
+      if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_COARSE takes 0 (asymptotic) or 1 (Strang)");
+      c->opt_coarse = value;
+      return AP_OK;
     default:
       return fail(AP_EINVAL, "unknown option");
   }
@@ -1257,6 +1301,8 @@ int aparareal_get_option(ap_ctx* c, int option, int* value) {
     case AP_OPT_GRAPH: *value = c->opt_graph; return AP_OK;
     case AP_OPT_SKIP: *value = c->opt_skip; return AP_OK;
     case AP_OPT_SWEEPS: *value = c->opt_sweeps; return AP_OK;
+    case AP_OPT_FINE: *value = c->opt_fine; return AP_OK;
+    case AP_OPT_COARSE: *value = c->opt_coarse; return AP_OK;
     default: return fail(AP_EINVAL, "unknown option");
   }
 }

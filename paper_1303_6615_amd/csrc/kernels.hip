@@ -153,6 +153,18 @@ __global__ void __launch_bounds__(NT) k_fine(const cx<double>* __restrict__ Uin,
                                                  coef, basis);
 }
 
+template <typename T, int NX, int NT>
+__global__ void __launch_bounds__(NT) k_strang(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
+                                               int steps, double h, const cx<double>* __restrict__ coef64,
+                                               const cx<T>* __restrict__ tw, const Basis<T>* __restrict__ basis) {
+  using E_ = Engine<T, NX, NT, fine_slots<T, NX, NT>()>;
+  extern __shared__ unsigned char smem_raw[];
+  E_ en(smem_raw, tw);
+  const size_t st = size_t(3) * E_::KP;
+  strang_job<T, NX, NT, fine_slots<T, NX, NT>()>(en, Uin + blockIdx.x * st, Uout + blockIdx.x * st, steps, coef64, h,
+                                                   basis);
+}
+
 // ---------------------------------------------------- average and coarse ---
 template <typename T, int NX, int NT, int S>
 __global__ void __launch_bounds__(NT) k_average(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Nout,
@@ -310,6 +322,17 @@ static hipError_t fine_nx(const cx<double>* in, cx<double>* out, int batch, int 
 }
 
 template <typename T, int NX>
+static hipError_t strang_nx(const cx<double>* in, cx<double>* out, int batch, int steps, double h,
+                            const cx<double>* coef64, const DevTables& t, hipStream_t s) {
+  constexpr int NT = fine_threads<NX>();
+  const size_t lds = Engine<T, NX, NT, fine_slots<T, NX, NT>()>::lds_bytes();
+  prep_lds(k_strang<T, NX, NT>, lds);
+  hipLaunchKernelGGL((k_strang<T, NX, NT>), dim3(batch), dim3(NT), lds, s, in, out, steps, h, coef64, t.tw<T>(),
+                     t.basis<T>());
+  return hipGetLastError();
+}
+
+template <typename T, int NX>
 static hipError_t average_nx(const cx<double>* in, cx<double>* out, int batch, const AvgTab<T>& av,
                              const DevTables& t, hipStream_t s) {
   constexpr int NT = avg_threads<T, NX>();
@@ -360,6 +383,11 @@ hipError_t launch_fine(int nx, bool fp64, const cx<double>* in, cx<double>* out,
                        const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s) {
   if (fp64) AP_DISPATCH_NX(nx, (fine_nx<double, NX>(in, out, batch, steps, coef64, coef64, t, s)));
   AP_DISPATCH_NX(nx, (fine_nx<float, NX>(in, out, batch, steps, coef64, coef32, t, s)));
+}
+hipError_t launch_strang(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch, int steps, double h,
+                         const cx<double>* coef64, const DevTables& t, hipStream_t s) {
+  if (fp64) AP_DISPATCH_NX(nx, (strang_nx<double, NX>(in, out, batch, steps, h, coef64, t, s)));
+  AP_DISPATCH_NX(nx, (strang_nx<float, NX>(in, out, batch, steps, h, coef64, t, s)));
 }
 hipError_t launch_average(int nx, const cx<double>* in, cx<double>* out, int batch, const AvgTab<double>* av64,
                           const AvgTab<float>* av32, const DevTables& t, hipStream_t s) {

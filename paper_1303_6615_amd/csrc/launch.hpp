@@ -76,6 +76,10 @@ struct PipeProb {
   cx<T>* P1;           // [K+1][groups][3][KP] stage-1 group sums (split steps)
   cx<T>* P2;           // [K+1][groups][3][KP] stage-2 group sums
   int nx, Ns, K, steps, groups;
+  int fine_kind;       // 0: ETDRK4 fine slices; 1: Strang steps (Alg. 3)
+  int coarse_kind;     // 0: asymptotic coarse step (Alg. 2); 1: one Strang step of dT
+  double hf, hc;       // fine step size; coarse (Strang) step size dT
+  const cx<double>* ccoef64;   // Strang coarse: [8][3][KP] table for h = dT (slot 2: e^{(dT/2) lambda})
   double tol;          // > 0: stop after the first level k with r^k <= tol
   const cx<double>* coef64;
   const cx<T>* coef;
@@ -92,6 +96,9 @@ hipError_t launch_nonlinear(int nx, bool fp64, const cx<double>* in, cx<double>*
                             const DevTables& t, hipStream_t s);
 hipError_t launch_fine(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch, int steps,
                        const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s);
+// `steps` Strang steps of size h (coef64 slot 2: e^{(h/2) lambda}) per state.
+hipError_t launch_strang(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch, int steps, double h,
+                         const cx<double>* coef64, const DevTables& t, hipStream_t s);
 hipError_t launch_average(int nx, const cx<double>* in, cx<double>* out, int batch, const AvgTab<double>* av64,
                           const AvgTab<float>* av32, const DevTables& t, hipStream_t s);
 hipError_t launch_coarse(int nx, const cx<double>* in, cx<double>* out, int batch, const CoarseTab<double>* c64,

@@ -152,13 +152,26 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
     return ix.coarse(k, n);
   };
   if (jb.type == kJobFine) {
-    fine_job<T, NX, NT, S>(en, uprev, state(p.F, k, n), p.steps, p.coef64, p.coef, p.basis);
+    if (p.fine_kind == 1)
+      strang_job<T, NX, NT, S>(en, uprev, state(p.F, k, n), p.steps, p.coef64, p.hf, p.basis);
+    else
+      fine_job<T, NX, NT, S>(en, uprev, state(p.F, k, n), p.steps, p.coef64, p.coef, p.basis);
     return ix.fine(k, n);
   }
   if (jb.type == kJobCopy) {
     copy_job<T, NX, NT, S>(en, n < k ? state(p.U, k - 1, n) : state(p.F, k - 1, n), state(p.U, k, n),
                            state(p.G, k - 1, n), state(p.G, k, n), state(p.U, k - 1, n),
                            p.part + size_t(k - 1) * Ns + (n - 1));
+    return level_done();
+  }
+  if (jb.type == kJobCoarse && p.coarse_kind == 1) {
+    if (k == 0)
+      strang_coarse_job<T, NX, NT, S>(en, p.ccoef64, p.hc, p.basis, uprev, state(p.U, 0, n), state(p.G, 0, n),
+                                      nullptr, nullptr, nullptr, nullptr);
+    else
+      strang_coarse_job<T, NX, NT, S>(en, p.ccoef64, p.hc, p.basis, uprev, state(p.U, k, n), state(p.G, k, n),
+                                      state(p.G, k - 1, n), state(p.F, k - 1, n), state(p.U, k - 1, n),
+                                      p.part + size_t(k - 1) * Ns + (n - 1));
     return level_done();
   }
   if (jb.type == kJobCoarse) {

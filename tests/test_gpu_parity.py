@@ -426,3 +426,38 @@ def test_batch_problems_stop_on_their_own_tolerance(torch_cuda):
     finally:
         for c in ctxs:
             c.close()
+
+
+@pytest.mark.parametrize("n,eps,dT,steps,prec,tol", [(64, 0.01, 0.0625, 125, FP64, 1e-11), (256, 0.01, 0.03125, 63, FP32, 2e-5),
+                                                     (1024, 0.001, 0.004, 40, FP32, 2e-5), (512, 0.1, 0.05, 1, FP64, 1e-11)])
+def test_strang_batch(torch_cuda, n, eps, dT, steps, prec, tol):
+    from oracle.strang import strang_propagate
+    torch = torch_cuda
+    nu = NU_BY_NX[n]
+    u = _states(n, 3, 300 + n)
+    ref = O.to_physical(strang_propagate(O.project(O.to_spectral(u), n), n, eps, 1.0, nu, dT, steps), n)
+    with _ctx(n, eps, nu) as ctx:
+        got = ctx.strang_batch(torch.tensor(u, device="cuda"), dT, steps, precision=prec).cpu().numpy()
+    assert _rel(got, ref) < tol
+
+
+@pytest.mark.parametrize("cfg,prec,tol,fine_kind,coarse_kind", [(C1, FP64, 1e-11, 1, 1), (C2, FP32, 2e-5, 1, 1),
+                                                                (C1, FP64, 1e-11, 1, 0), (C2, FP32, 2e-5, 0, 1)])
+def test_strang_and_standard_parareal_solves(torch_cuda, cfg, prec, tol, fine_kind, coarse_kind):
+    # Strang fine slices (Alg. 3) and/or the one-step Strang coarse solver of
+    # standard parareal, through the pipelined launch, against the oracle
+    from oracle.strang import strang_propagate
+    from paper_1303_6615_amd.binding import AP_OPT_COARSE, AP_OPT_FINE
+    torch = torch_cuda
+    dT = cfg.T / cfg.slices
+    coarse = (lambda v: strang_propagate(v, cfg.nx, cfg.eps, cfg.F, cfg.nu, dT, 1)) if coarse_kind else None
+    fine = (lambda v: strang_propagate(v, cfg.nx, cfg.eps, cfg.F, cfg.nu, dT, cfg.fine_steps)) if fine_kind else None
+    Uref, rref, _ = O.parareal_solve(cfg.initial_state(), cfg.nx, cfg.eps, cfg.F, cfg.nu, cfg.T, cfg.slices, cfg.K,
+                                     cfg.fine_steps, cfg.Mbar, cfg.window, coarse=coarse, fine=fine)
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        ctx.set_option(AP_OPT_FINE, fine_kind)
+        ctx.set_option(AP_OPT_COARSE, coarse_kind)
+        U, r = _solve(ctx, torch, cfg, prec)
+    assert _rel(U.cpu().numpy(), Uref) < tol
+    floor = 1e-13 if prec == FP64 else 1e-6
+    assert np.all(np.abs(r.cpu().numpy() - np.array(rref)) <= 1e-3 * np.array(rref) + floor)
