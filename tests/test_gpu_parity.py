@@ -461,3 +461,16 @@ def test_strang_and_standard_parareal_solves(torch_cuda, cfg, prec, tol, fine_ki
     assert _rel(U.cpu().numpy(), Uref) < tol
     floor = 1e-13 if prec == FP64 else 1e-6
     assert np.all(np.abs(r.cpu().numpy() - np.array(rref)) <= 1e-3 * np.array(rref) + floor)
+
+
+def test_paper_experiment_replay_converges(torch_cuda):
+    # the paper's eps = 1 experiment (analytic height, mu = 1e-4, dT = 3/10,
+    # dt = 1/200, 60 slices): the error against the serial fine solution falls
+    # with every iteration for asymptotic and standard parareal
+    from paper_1303_6615_amd.replay import run_case
+    out = run_case(1.0, torch=torch_cuda)
+    for method in ("asymptotic", "standard"):
+        e = out[method]["error_by_k"]
+        assert all(e[k + 1] < e[k] for k in range(len(e) - 1)), (method, e)
+        assert e[-1] < 1e-3, (method, e)
+        assert out[method]["tau_f_us"] > 0 and out[method]["measured_speedup_k5"] > 1
