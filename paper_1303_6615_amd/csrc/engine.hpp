@@ -87,6 +87,7 @@ struct Engine {
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
       if (valid(j)) put_fields<T, NX>(sps, 0, mode(j), x[j], bs[j]);
+    zero_tails<T, NX, NT>(sps, 1);
     __syncthreads();
     inverse_fields<T, NX, NT>(sps, ibs, 1, tw);
     __syncthreads();
@@ -351,6 +352,7 @@ __device__ __forceinline__ void nbar_range(Engine<T, NX, NT, S>& en,
       for (int al = 0; al < 3; ++al) x[al] = rot_in(en.y[al * KP + k], e, al);
       put_fields<T, NX>(en.sp, s, k, x, basis[k]);
     }
+    zero_tails<T, NX, NT>(en.sp, ns);
     __syncthreads();
     inverse_fields<T, NX, NT>(en.sp, en.ib, ns, en.tw);
     __syncthreads();
@@ -598,15 +600,27 @@ __device__ __forceinline__ void sum_groups(const cx<T>* __restrict__ P, int grou
                                            cx<T> (&acc)[Engine<T, NX, NT, S>::MPT][3]) {
   using E_ = Engine<T, NX, NT, S>;
   constexpr int KP = E_::KP;
+  constexpr int B = 8;   // group sums in flight per thread (written by other workgroups: long latency)
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j)
     for (int al = 0; al < 3; ++al) acc[j][al] = czero<T>();
-  for (int g = 0; g < groups; ++g) {
-    const cx<T>* Pg = P + size_t(g) * 3 * KP;
+  for (int g0 = 0; g0 < groups; g0 += B) {
+    const int nb = min(B, groups - g0);
+    cx<T> v[B][E_::MPT][3];
+    // issue the loads of up to B groups, then add them in increasing group order
 #pragma unroll
-    for (int j = 0; j < E_::MPT; ++j) {
-      if (!E_::valid(j)) continue;
-      for (int al = 0; al < 3; ++al) acc[j][al] = acc[j][al] + Pg[al * KP + E_::mode(j)];
+    for (int b = 0; b < B; ++b) {
+      const cx<T>* Pg = P + size_t(g0 + (b < nb ? b : 0)) * 3 * KP;
+#pragma unroll
+      for (int j = 0; j < E_::MPT; ++j)
+        for (int al = 0; al < 3; ++al) v[b][j][al] = E_::valid(j) ? Pg[al * KP + E_::mode(j)] : czero<T>();
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (b >= nb) break;
+#pragma unroll
+      for (int j = 0; j < E_::MPT; ++j)
+        for (int al = 0; al < 3; ++al) acc[j][al] = acc[j][al] + v[b][j][al];
     }
   }
 }

@@ -228,8 +228,9 @@ struct Slot {
   static constexpr size_t bytes = (sp_elems + ib_elems) * sizeof(cx<T>);
 };
 
-// Inverse transforms of the 3*ns field spectra in SP (k <= Kd written, the
-// rest read as zero) into IB, one signal per lane group at a time.
+// Inverse transforms of the 3*ns field spectra in SP (entries k <= Kd written,
+// entries Kd < k <= P zero: see zero_tails) into IB, one signal per lane group
+// at a time.  The loads of the first pass are unconditional.
 template <typename T, int NX, int NT>
 __device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, const cx<T>* tw) {
   using G_ = Geo<NX>;
@@ -246,17 +247,32 @@ __device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, con
     const bool active = v < nsig;
     const cx<T>* X = sp + (active ? v : 0) * (P + 1);
     auto load = [X, tw](int idx) {
-      const cx<T> xk = idx <= G_::KD ? X[idx] : czero<T>();
-      const int ic = P - idx;
-      const cx<T> xc = ic <= G_::KD ? conj(X[ic]) : czero<T>();
+      const cx<T> xk = X[idx];
+      const cx<T> xc = conj(X[P - idx]);
       return (xk + xc) + mul_i(conj(tw[idx]) * (xk - xc));
     };
     wave_fft<T, P, +1>(ib + (active ? v : 0) * P, tw, lig, active, load);
   }
 }
 
+// Zeroes the entries Kd < k <= P of the 3*ns field spectra in SP (the forward
+// transforms of the previous evaluation overwrote them).  Called by every
+// thread between the writes of the retained modes and the barrier before the
+// inverse transforms.
+template <typename T, int NX, int NT>
+__device__ __forceinline__ void zero_tails(cx<T>* sp, int ns) {
+  constexpr int P = Geo<NX>::P;
+  constexpr int KD = Geo<NX>::KD;
+  constexpr int TL = P - KD;
+  for (int i = threadIdx.x; i < 3 * ns * TL; i += NT) {
+    const int v = i / TL;
+    sp[v * (P + 1) + KD + 1 + (i - v * TL)] = czero<T>();
+  }
+}
+
 // Forward transforms of the packed products of each state's inverse outputs,
-// written into SP (stride P+1).
+// written into SP (stride P+1): v1^2/2, v1 v2x, h v1.  The first pass reads
+// both factors and scales by 1/2 or 1, with no branch on the product.
 template <typename T, int NX, int NT>
 __device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int ns, const cx<T>* tw) {
   constexpr int P = Geo<NX>::P;
@@ -273,12 +289,12 @@ __device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int
     const int vv = active ? v : 0;
     const int s = vv / 3, f = vv - 3 * s;
     const cx<T>* V1 = ib + (3 * s) * P;
-    const cx<T>* W = ib + (3 * s + (f == 2 ? 2 : 1)) * P;
-    auto load = [V1, W, f](int idx) {
+    const cx<T>* W = ib + (3 * s + (f == 2 ? 2 : f)) * P;   // v1 itself for the square
+    const T scale = f == 0 ? T(0.5) : T(1);
+    auto load = [V1, W, scale](int idx) {
       const cx<T> v1 = V1[idx];
-      if (f == 0) return cx<T>{T(0.5) * v1.x * v1.x, T(0.5) * v1.y * v1.y};
       const cx<T> w = W[idx];
-      return cx<T>{v1.x * w.x, v1.y * w.y};
+      return cx<T>{scale * (v1.x * w.x), scale * (v1.y * w.y)};
     };
     wave_fft<T, P, -1>(sp + vv * (P + 1), tw, lig, active, load);
   }
