@@ -152,7 +152,8 @@ int aparareal_solve_batch(const ap_batch_item* items, int count, void* stream);
  *                 0: one workgroup per coarse step; 1: always split.
  *   AP_OPT_GROUP  samples per group of the time average (the sum runs over
  *                 each group in sample order, then over the groups in order);
- *                 0 (default) = by grid size.  Reading returns the size used.
+ *                 0 (default) = by grid size, or the size aparareal_autotune
+ *                 chose.  Reading returns the size used.
  *   AP_OPT_GRID   workgroups of a persistent launch; 0 (default) = as many as
  *                 are resident on the device at once.
  *   AP_OPT_GRAPH  1: a pipelined solve (or batch whose first item names this
@@ -184,14 +185,19 @@ int aparareal_get_option(ap_ctx* ctx, int option, int* value);
 
 /* Autotuner of the pipelined schedule for the problems of `items` (one item:
  * a single solve; several: a batch as in aparareal_solve_batch, with the same
- * argument rules).  For each execution mapping (AP_OPT_SPLIT 0 and 1) it runs
- * the solve, records every job's duration on the device clock, re-orders the
- * jobs with the measured durations per problem and job type (twice), and
- * times three solves; it then keeps the fastest mapping and its measured
- * durations in the contexts, so that later solves of the same shape use
- * them.  The outputs receive the results of the last solve run.  *best_ms
- * (host, may be NULL) receives the best solve time.  Results of later solves
- * do not depend on the tuning (the group size is not tuned).                */
+ * argument rules).  Candidates: whole coarse steps (AP_OPT_SPLIT 0) with the
+ * default group size, and split steps (AP_OPT_SPLIT 1) with group sizes of
+ * 1, 3/2, 2 and 3 times the grid-size default (one multiple for all items;
+ * a context whose AP_OPT_GROUP is set keeps that size).  For each candidate
+ * it runs the solve, records every job's duration on the device clock,
+ * re-orders the jobs with the measured durations per problem and job type
+ * (twice), and times three solves; it then keeps the fastest candidate and
+ * its measured durations in the contexts, so that later solves of the same
+ * shape use them.  The outputs receive the results of the last solve run.
+ * *best_ms (host, may be NULL) receives the best solve time.  The mapping and
+ * the job order leave results unchanged; the chosen group size changes the
+ * summation order of the average (rounding only), and later solves equal
+ * solves with AP_OPT_SPLIT and AP_OPT_GROUP set to the values read back.    */
 int aparareal_autotune(const ap_batch_item* items, int count, void* stream, double* best_ms);
 
 /* Kernel timing (diagnostics, no effect on results).  While enabled, the

@@ -163,6 +163,7 @@ struct ap_ctx {
   // options (aparareal_set_option)
   int opt_split = -1;        // split coarse steps over workgroups: -1 auto, 0 no, 1 yes
   int opt_group = 0;         // samples per group of the average; 0 = by grid size
+  int tuned_group = 0;       // group size chosen by aparareal_autotune when opt_group is 0
   int opt_grid = 0;          // workgroups of a persistent launch; 0 = all that fit
   CostCal cost;              // calibrated job durations (aparareal_autotune)
   int opt_graph = 0;         // replay pipelined launches from a captured hipGraph
@@ -310,7 +311,15 @@ int default_group_size(int nx) {
   return std::max(1, 8 * (64 / G) / 3);
 }
 
-int group_size(const ap_ctx* c) { return c->opt_group > 0 ? c->opt_group : default_group_size(c->N); }
+int group_size(const ap_ctx* c) {
+  return c->opt_group > 0 ? c->opt_group : c->tuned_group > 0 ? c->tuned_group : default_group_size(c->N);
+}
+
+// Group sizes the autotuner tries for split coarse steps: multiples 1, 3/2, 2
+// and 3 of the grid-size default.  Larger groups mean longer stage jobs but
+// fewer group sums for the stage-2 jobs and the finisher to read back.
+constexpr int kTuneGroupMults2[] = {2, 3, 4, 6};   // twice the multiple
+int tune_group(int nx, int cand) { return std::max(1, default_group_size(nx) * kTuneGroupMults2[cand] / 2); }
 
 // dT == 0 builds the average-only tables.
 int avg_tables(ap_ctx* c, double dT, double T0, int M, AvgTables** out) {
@@ -1165,18 +1174,31 @@ int aparareal_autotune(const ap_batch_item* batch, int count, void* stream, doub
     return fail(AP_EDEVICE, "event creation");
   }
   const bool trace_was = owner->trace_on;
-  const int split_was = owner->opt_split;
+  std::vector<int> split_was, group_was;
   std::vector<CostCal> cal_was;
-  for (int i = 0; i < count; ++i) cal_was.push_back(batch[i].ctx->cost);
+  for (int i = 0; i < count; ++i) {
+    split_was.push_back(batch[i].ctx->opt_split);
+    group_was.push_back(batch[i].ctx->tuned_group);
+    cal_was.push_back(batch[i].ctx->cost);
+  }
+  // candidates: whole coarse steps with the default groups, then split steps
+  // with each tuned group size (contexts with AP_OPT_GROUP set keep theirs)
+  constexpr int kCands = 1 + int(sizeof(kTuneGroupMults2) / sizeof(kTuneGroupMults2[0]));
   double best = -1.0;
-  int best_split = split_was;
+  int best_cand = -1;
   std::vector<CostCal> best_cal = cal_was;
   int rc = AP_OK;
-  for (int split = 0; split <= 1 && rc == AP_OK; ++split) {
+  for (int cand = 0; cand < kCands && rc == AP_OK; ++cand) {
+    const int split = cand == 0 ? 0 : 1;
+    bool distinct = cand <= 1;
     for (int i = 0; i < count; ++i) {
-      batch[i].ctx->opt_split = split;
-      batch[i].ctx->cost = CostCal{};
+      ap_ctx* c = batch[i].ctx;
+      c->opt_split = split;
+      c->tuned_group = cand == 0 ? 0 : tune_group(c->N, cand - 1);
+      if (cand > 1 && c->opt_group == 0 && c->tuned_group != tune_group(c->N, cand - 2)) distinct = true;
+      c->cost = CostCal{};
     }
+    if (!distinct) continue;   // same groups as the previous candidate for every problem
     if ((rc = run())) break;   // warm-up (tables, workspaces, job list)
     // two rounds: measure job durations, re-order with them
     for (int round = 0; round < 2 && rc == AP_OK; ++round) {
@@ -1232,14 +1254,22 @@ int aparareal_autotune(const ap_batch_item* batch, int count, void* stream, doub
     }
     if (rc == AP_OK && (best < 0.0 || ms < best)) {
       best = ms;
-      best_split = split;
+      best_cand = cand;
       best_cal.clear();
       for (int i = 0; i < count; ++i) best_cal.push_back(batch[i].ctx->cost);
     }
   }
   for (int i = 0; i < count; ++i) {
-    batch[i].ctx->opt_split = rc == AP_OK ? best_split : split_was;
-    batch[i].ctx->cost = rc == AP_OK ? best_cal[size_t(i)] : cal_was[size_t(i)];
+    ap_ctx* c = batch[i].ctx;
+    if (rc == AP_OK && best_cand >= 0) {
+      c->opt_split = best_cand == 0 ? 0 : 1;
+      c->tuned_group = best_cand == 0 ? 0 : tune_group(c->N, best_cand - 1);
+      c->cost = best_cal[size_t(i)];
+    } else {
+      c->opt_split = split_was[size_t(i)];
+      c->tuned_group = group_was[size_t(i)];
+      c->cost = cal_was[size_t(i)];
+    }
   }
   owner->trace_on = trace_was;
   (void)hipEventDestroy(ev[0]);
