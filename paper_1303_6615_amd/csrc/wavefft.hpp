@@ -157,64 +157,147 @@ constexpr int swz_pass1() {
   else return P <= 256 ? kSwzR5 : P == 512 ? kSwzRx1 : kSwzId;
 }
 
+// Sources of a pass's inputs.  fetch(i) issues the LDS loads of input i
+// (returning raw values), make(raw) forms the input from them; a pass issues
+// every fetch before the first make, so its loads share one LDS round trip.
+// Later passes read the previous pass's output through its layout map.
+template <typename T, int CODE>
+struct ReadLayout {
+  const cx<T>* buf;
+  using Raw = cx<T>;
+  __device__ __forceinline__ Raw fetch(int i) const { return buf[swz<T, CODE>(i)]; }
+  __device__ __forceinline__ cx<T> make(const Raw& r) const { return r; }
+};
+
+// Twiddles of one Stockham pass, exp(-2 pi i q k/(NS R)), q = 1..R-1, for the
+// butterflies of this lane (k = b mod NS), from the pass's contiguous table
+// at tw + TWO.  PRE: loaded into registers by the previous pass, with its
+// inputs (load), so that they share that pass's LDS round trip; otherwise
+// each pass loads its own with its inputs (get).
+template <typename T, int P, int R, int NS, int G, int TWO, bool PRE>
+struct PassTw {
+  static constexpr int NB = P / R;
+  static constexpr int BPL = (NB + G - 1) / G;
+  cx<T> w[PRE ? BPL : 1][R > 1 ? R - 1 : 1];
+  static __device__ __forceinline__ int butterfly(int lig, int i) { return NB < G ? (lig & (NB - 1)) : lig + G * i; }
+  __device__ __forceinline__ void load(const cx<T>* tw, int lig) {
+    if constexpr (PRE) {
+#pragma unroll
+      for (int i = 0; i < BPL; ++i) {
+        const int k = butterfly(lig, i) & (NS - 1);
+#pragma unroll
+        for (int q = 1; q < R; ++q) w[i][q - 1] = tw[TWO + (q - 1) * NS + k];
+      }
+    }
+  }
+  __device__ __forceinline__ cx<T> get(const cx<T>* tw, int i, int q, int k) const {
+    if constexpr (PRE) return w[i][q - 1];
+    else return tw[TWO + (q - 1) * NS + k];
+  }
+};
+
+// No twiddles (the first pass, and the pass after the last).
+template <typename T>
+struct NoTw {
+  __device__ __forceinline__ void load(const cx<T>*, int) {}
+  __device__ __forceinline__ cx<T> get(const cx<T>*, int, int, int) const { return cx<T>{T(1), T(0)}; }
+};
+
+// Twiddles go to registers one pass ahead where they cost few of them
+// (FP32, P <= 128: at most 7 complex values per lane).
+template <typename T, int P>
+constexpr bool tw_in_registers() {
+  return sizeof(T) == 4 && P <= 128;
+}
+
 // One in-place Stockham pass of radix R after NS points have been combined,
-// by the G lanes of one signal group: butterfly b (b = lig, lig + G, ...)
-// reads positions b + q P/R (through `load` on the first pass), twiddles by
-// exp(DIR 2 pi i q k / (NS R)), k = b mod NS (table at tw + TWO), and writes
-// (b - k) R + k + q NS through the layout map SWO.  Every lane of the
-// wavefront executes the synchronisations; lanes of an inactive group skip
-// loads and stores.
-template <typename T, int P, int R, int NS, int DIR, int G, int TWO, int SWO, typename Load>
-__device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, int lig, bool active, Load&& load) {
+// by the G lanes of one signal group: butterfly b reads positions b + q P/R
+// from `src`, twiddles by exp(DIR 2 pi i q k/(NS R)) (k = b mod NS; from `w`,
+// NS > 1), and writes (b - k) R + k + q NS through the layout map SWO.  Lane
+// lig takes butterflies lig, lig + G, ...; when the pass has fewer
+// butterflies than lanes (P/R < G), lanes lig and lig + P/R repeat the same
+// butterfly and store the same values to the same places.  The pass has no
+// branch: a branch around the LDS accesses would make the compiler wait for
+// the previous pass's stores before the next loads, which the in-order LDS
+// queue of a wavefront does not need.  BATCH: all loads of the pass, then
+// those of the next pass's register twiddles (`next`), are issued before the
+// arithmetic (for small passes; large ones leave the order to the compiler,
+// which keeps fewer values live).
+template <typename T, int P, int R, int NS, int DIR, int G, int SWO, bool BATCH, typename Src, typename W,
+          typename WN>
+__device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, const W& w, WN& next, int lig,
+                                          const Src& src) {
   constexpr int NB = P / R;
   constexpr int BPL = (NB + G - 1) / G;
+  static_assert(NB % G == 0 || BPL == 1, "butterflies per lane");
+  cx<T> wt[BPL][R > 1 ? R - 1 : 1];
   cx<T> x[BPL][R];
+  if constexpr (BATCH) {
+    typename Src::Raw raw[BPL][R];
+#pragma unroll
+    for (int i = 0; i < BPL; ++i) {
+      const int b = NB < G ? (lig & (NB - 1)) : lig + G * i;
+#pragma unroll
+      for (int q = 0; q < R; ++q) raw[i][q] = src.fetch(b + q * NB);
+    }
+#pragma unroll
+    for (int i = 0; i < BPL; ++i)
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[i][q] = src.make(raw[i][q]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < BPL; ++i) {
+      const int b = NB < G ? (lig & (NB - 1)) : lig + G * i;
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[i][q] = src.make(src.fetch(b + q * NB));
+    }
+  }
 #pragma unroll
   for (int i = 0; i < BPL; ++i) {
-    const int b = lig + G * i;
-    if (active && (NB % G == 0 || b < NB)) {
+    const int b = NB < G ? (lig & (NB - 1)) : lig + G * i;
+    if constexpr (NS > 1) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) x[i][q] = load(b + q * NB);
-      if constexpr (NS > 1) {
-        const int k = b & (NS - 1);
-#pragma unroll
-        for (int q = 1; q < R; ++q) {
-          cx<T> w = tw[TWO + (q - 1) * NS + k];
-          if (DIR > 0) w = conj(w);
-          x[i][q] = x[i][q] * w;
-        }
-      }
-      dft_reg<T, R, DIR>(x[i]);
+      for (int q = 1; q < R; ++q) wt[i][q - 1] = w.get(tw, i, q, b & (NS - 1));
     }
+  }
+  next.load(tw, lig);
+#pragma unroll
+  for (int i = 0; i < BPL; ++i) {
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int q = 1; q < R; ++q) x[i][q] = x[i][q] * (DIR > 0 ? conj(wt[i][q - 1]) : wt[i][q - 1]);
+    }
+    dft_reg<T, R, DIR>(x[i]);
   }
   wave_sync();
 #pragma unroll
   for (int i = 0; i < BPL; ++i) {
-    const int b = lig + G * i;
-    if (active && (NB % G == 0 || b < NB)) {
-      const int k = b & (NS - 1);
-      const int d = (b - k) * R + k;
+    const int b = NB < G ? (lig & (NB - 1)) : lig + G * i;
+    const int k = b & (NS - 1);
+    const int d = (b - k) * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[swz<T, SWO>(d + q * NS)] = x[i][q];
-    }
+    for (int q = 0; q < R; ++q) buf[swz<T, SWO>(d + q * NS)] = x[i][q];
   }
   wave_sync();
 }
 
 // Unnormalised complex FFT of length P by one lane group, result in `buf`
-// (natural order); the first pass reads its inputs through load(index).
-template <typename T, int P, int DIR, typename Load>
-__device__ __forceinline__ void wave_fft(cx<T>* buf, const cx<T>* tw, int lig, bool active, Load&& load) {
+// (natural order); the first pass reads its inputs from `src`.
+template <typename T, int P, int DIR, typename Src>
+__device__ __forceinline__ void wave_fft(cx<T>* buf, const cx<T>* tw, int lig, const Src& src) {
   using PL = WavePlan<P>;
+  constexpr bool PRE = tw_in_registers<T, P>();
   constexpr int S0 = swz_pass0<T, P>();
   constexpr int S1 = PL::n == 3 ? swz_pass1<T, P>() : kSwzId;
-  auto read0 = [buf](int i) { return buf[swz<T, S0>(i)]; };
-  wave_pass<T, P, PL::r0, 1, DIR, PL::G, 0, S0>(buf, tw, lig, active, load);
-  wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, pass1_tw_offset<P>(), S1>(buf, tw, lig, active, read0);
+  NoTw<T> none;
+  PassTw<T, P, PL::r1, PL::r0, PL::G, pass1_tw_offset<P>(), PRE> w1;
+  wave_pass<T, P, PL::r0, 1, DIR, PL::G, S0, PRE>(buf, tw, none, w1, lig, src);
   if constexpr (PL::n == 3) {
-    auto read1 = [buf](int i) { return buf[swz<T, S1>(i)]; };
-    wave_pass<T, P, PL::r2, PL::r0 * PL::r1, DIR, PL::G, pass2_tw_offset<P>(), kSwzId>(buf, tw, lig, active,
-                                                                                       read1);
+    PassTw<T, P, PL::r2, PL::r0 * PL::r1, PL::G, pass2_tw_offset<P>(), PRE> w2;
+    wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
+    wave_pass<T, P, PL::r2, PL::r0 * PL::r1, DIR, PL::G, kSwzId, PRE>(buf, tw, w2, none, lig, ReadLayout<T, S1>{buf});
+  } else {
+    wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, none, lig, ReadLayout<T, S0>{buf});
   }
 }
 
@@ -231,6 +314,31 @@ struct Slot {
 // Inverse transforms of the 3*ns field spectra in SP (entries k <= Kd written,
 // entries Kd < k <= P zero: see zero_tails) into IB, one signal per lane group
 // at a time.  The loads of the first pass are unconditional.
+// First-pass source of an inverse transform: Z[k] = (X[k] + conj X[P-k])
+// + i conj(t_k) (X[k] - conj X[P-k]) from the half spectrum X (stride P+1),
+// t_k = exp(-2 pi i k/N).
+template <typename T, int P>
+struct ReadHalfSpectrum {
+  const cx<T>* X;
+  const cx<T>* tw;
+  struct Raw {
+    cx<T> xk, xm, t;
+  };
+  __device__ __forceinline__ Raw fetch(int idx) const { return Raw{X[idx], X[P - idx], tw[idx]}; }
+  __device__ __forceinline__ cx<T> make(const Raw& r) const {
+    const cx<T> xc = conj(r.xm);
+    return (r.xk + xc) + mul_i(conj(r.t) * (r.xk - xc));
+  }
+};
+
+// Inverse transforms of the 3*ns field spectra in SP (entries k <= Kd written,
+// entries Kd < k <= P zero: see zero_tails) into IB, one signal per lane group
+// at a time.  A lane group past the last signal repeats its wavefront's first
+// signal (same inputs, same outputs), so no branch surrounds the transforms.
+// The loads of the first pass are unconditional: the signal's offset is
+// passed through an empty asm statement, so that the compiler cannot tie the
+// loads to the zero stores of zero_tails and split them into conditional
+// loads (each with its own wait).
 template <typename T, int NX, int NT>
 __device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, const cx<T>* tw) {
   using G_ = Geo<NX>;
@@ -243,15 +351,10 @@ __device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, con
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nsig = 3 * ns;
   for (int v0 = wave * SPW; v0 < nsig; v0 += NW * SPW) {
-    const int v = v0 + group;
-    const bool active = v < nsig;
-    const cx<T>* X = sp + (active ? v : 0) * (P + 1);
-    auto load = [X, tw](int idx) {
-      const cx<T> xk = X[idx];
-      const cx<T> xc = conj(X[P - idx]);
-      return (xk + xc) + mul_i(conj(tw[idx]) * (xk - xc));
-    };
-    wave_fft<T, P, +1>(ib + (active ? v : 0) * P, tw, lig, active, load);
+    const int v = v0 + group < nsig ? v0 + group : v0;
+    int off = v * (P + 1);
+    asm volatile("" : "+v"(off));
+    wave_fft<T, P, +1>(ib + v * P, tw, lig, ReadHalfSpectrum<T, P>{sp + off, tw});
   }
 }
 
@@ -270,9 +373,26 @@ __device__ __forceinline__ void zero_tails(cx<T>* sp, int ns) {
   }
 }
 
+// First-pass source of a forward transform: the packed product
+// (scale v1.x w.x, scale v1.y w.y) of two inverse outputs.
+template <typename T>
+struct ReadProducts {
+  const cx<T>* V1;
+  const cx<T>* W;
+  T scale;
+  struct Raw {
+    cx<T> v1, w;
+  };
+  __device__ __forceinline__ Raw fetch(int idx) const { return Raw{V1[idx], W[idx]}; }
+  __device__ __forceinline__ cx<T> make(const Raw& r) const {
+    return cx<T>{scale * (r.v1.x * r.w.x), scale * (r.v1.y * r.w.y)};
+  }
+};
+
 // Forward transforms of the packed products of each state's inverse outputs,
 // written into SP (stride P+1): v1^2/2, v1 v2x, h v1.  The first pass reads
-// both factors and scales by 1/2 or 1, with no branch on the product.
+// both factors and scales by 1/2 or 1, with no branch on the product; lane
+// groups past the last signal repeat their wavefront's first one.
 template <typename T, int NX, int NT>
 __device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int ns, const cx<T>* tw) {
   constexpr int P = Geo<NX>::P;
@@ -284,19 +404,12 @@ __device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nsig = 3 * ns;
   for (int v0 = wave * SPW; v0 < nsig; v0 += NW * SPW) {
-    const int v = v0 + group;
-    const bool active = v < nsig;
-    const int vv = active ? v : 0;
+    const int vv = v0 + group < nsig ? v0 + group : v0;
     const int s = vv / 3, f = vv - 3 * s;
     const cx<T>* V1 = ib + (3 * s) * P;
     const cx<T>* W = ib + (3 * s + (f == 2 ? 2 : f)) * P;   // v1 itself for the square
     const T scale = f == 0 ? T(0.5) : T(1);
-    auto load = [V1, W, scale](int idx) {
-      const cx<T> v1 = V1[idx];
-      const cx<T> w = W[idx];
-      return cx<T>{scale * (v1.x * w.x), scale * (v1.y * w.y)};
-    };
-    wave_fft<T, P, -1>(sp + vv * (P + 1), tw, lig, active, load);
+    wave_fft<T, P, -1>(sp + vv * (P + 1), tw, lig, ReadProducts<T>{V1, W, scale});
   }
 }
 
