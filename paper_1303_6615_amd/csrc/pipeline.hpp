@@ -30,25 +30,32 @@ constexpr unsigned long long kStallTicks = 100000000ull;
 // Thread 0 waits for *ctr >= target (relaxed polls, then an acquire fence).
 // On a stall it records (1, job, counter index) in diag[0..2] and returns
 // false; it also returns false once another workgroup has recorded one.
+// Every waiting workgroup polls, so the words all of them share (the stall
+// record and the completed-job count) are read only every kCheckEvery polls:
+// reading them on every poll makes those few addresses the hottest in the
+// device and slows the polls of the counter a workgroup actually waits on.
 constexpr int kStallPolls = 1 << 22;   // polls without progress: a bound independent of the clock
+constexpr int kCheckEvery = 32;
 
 __device__ __forceinline__ bool wait_count(int* ctr, int target, int* diag, int job, int index) {
   unsigned long long t0 = wall_clock64();
   int seen = __hip_atomic_load(diag + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int polls = 0;
   while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    if (__hip_atomic_load(diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    const int now_done = __hip_atomic_load(diag + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (now_done != seen) {
-      seen = now_done;
-      t0 = wall_clock64();
-      polls = 0;
-    } else if (wall_clock64() - t0 > kStallTicks || ++polls > kStallPolls) {
-      if (__hip_atomic_fetch_add(diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        __hip_atomic_store(diag + 1, job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(diag + 2, index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (++polls % kCheckEvery == 0) {
+      if (__hip_atomic_load(diag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+      const int now_done = __hip_atomic_load(diag + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (now_done != seen) {
+        seen = now_done;
+        t0 = wall_clock64();
+        polls = 0;
+      } else if (wall_clock64() - t0 > kStallTicks || polls > kStallPolls) {
+        if (__hip_atomic_fetch_add(diag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          __hip_atomic_store(diag + 1, job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(diag + 2, index, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return false;
       }
-      return false;
     }
     __builtin_amdgcn_s_sleep(2);
   }
