@@ -175,10 +175,18 @@ int aparareal_solve_batch(const ap_batch_item* items, int count, void* stream);
  *   AP_OPT_COARSE coarse solver: 0 (default) the asymptotic step (Alg. 2);
  *                 1 one Strang step of length dT, i.e. standard parareal
  *                 on the full equation (the paper's comparison, Sec. 6.2);
- *                 M_avg and T0 are then unused.                              */
+ *                 M_avg and T0 are then unused.
+ *   AP_OPT_FINE_GROUP  slices one fine job of a pipelined solve steps
+ *                 together (consecutive slices of one iteration; each rounds
+ *                 as it would alone, so values do not change).  0 (default):
+ *                 automatic, 1 while the slices of the solve or batch fit the
+ *                 resident workgroups, else the most the grid size allows
+ *                 (16, 10, 5, 2, 1, 1 for N = 64 .. 2048); n >= 1: at most n.
+ *                 A group starts when its last slice's input is ready, so
+ *                 grouping trades latency for throughput.                    */
 enum {
   AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2, AP_OPT_GRAPH = 3, AP_OPT_SKIP = 4, AP_OPT_SWEEPS = 5,
-  AP_OPT_FINE = 6, AP_OPT_COARSE = 7
+  AP_OPT_FINE = 6, AP_OPT_COARSE = 7, AP_OPT_FINE_GROUP = 8
 };
 int aparareal_set_option(ap_ctx* ctx, int option, int value);
 int aparareal_get_option(ap_ctx* ctx, int option, int* value);
@@ -224,16 +232,30 @@ int aparareal_profile_read(ap_ctx* ctx, int kernel_class, int* launches, double*
 
 /* Order in which the pipelined solve hands out its jobs (host only, no device
  * needed; for inspection and tests), for a problem of grid size N with
- * parameters p, split / group as AP_OPT_SPLIT / AP_OPT_GROUP.  Writes up to
- * max_jobs (type, k, n, g) quadruples to the host array `out` (may be NULL):
- * type 0 = coarse step C(k,n) in one workgroup, k = 0..K; 1 = fine slice
- * F(k,n) = Fine(U_{n-1}^k), k = 0..K-1, n > k; 2 / 3 = first / second
+ * parameters p, split / group as AP_OPT_SPLIT / AP_OPT_GROUP, and fine jobs of
+ * up to fine_group slices (1..64, capped by the grid size's maximum for
+ * p->precision).  Writes up to max_jobs (type, k, n, g) quadruples to the
+ * host array `out` (may be NULL): type 0 = coarse step C(k,n) in one
+ * workgroup, k = 0..K; 1 = fine slices F(k,n .. n+g-1) = Fine(U_{n-1+i}^k),
+ * k = 0..K-1, n > k (g = 1 for a single slice); 2 / 3 = first / second
  * average of a split coarse step C(k,n) for sample group g; 4 = copy of the
  * exact slice n <= k at level k >= 1 (slice skipping).  Jobs are ordered by
  * their estimated ready times, and every job comes after the jobs it depends
  * on.
  * Returns the job count or AP_EINVAL.                                        */
-int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int group, int* out, int max_jobs);
+int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int group, int fine_group, int* out,
+                                int max_jobs);
+
+/* The hand-out order of a batched launch (as aparareal_solve_batch) of
+ * `count` problems of grid sizes N[i] and parameters p[i] (host arrays),
+ * split / group / fine_group as above for every problem.  cost (host, may be
+ * NULL): per problem four job durations in us that replace the analytic
+ * estimates as aparareal_autotune's measurements do: fine step, stage-1 job,
+ * stage-2 job, whole coarse step (0 keeps the estimate).  Writes up to
+ * max_jobs (prob, type, k, n, g) quintuples to `out` (may be NULL).
+ * Returns the job count or AP_EINVAL.                                        */
+int aparareal_pipeline_schedule_batch(int count, const int* N, const ap_solve_params* p, int split, int group,
+                                      int fine_group, const double* cost, int* out, int max_jobs);
 
 /* Stall record of the context's last pipelined solve (waits for it): host
  * info[3] = (stalled, job index, flag index).  A stall means a job waited on

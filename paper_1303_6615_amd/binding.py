@@ -39,7 +39,7 @@ class BatchItem(ctypes.Structure):
 
 
 AP_OPT_SPLIT, AP_OPT_GROUP, AP_OPT_GRID, AP_OPT_GRAPH, AP_OPT_SKIP, AP_OPT_SWEEPS = 0, 1, 2, 3, 4, 5
-AP_OPT_FINE, AP_OPT_COARSE = 6, 7
+AP_OPT_FINE, AP_OPT_COARSE, AP_OPT_FINE_GROUP = 6, 7, 8
 JOB_COARSE, JOB_FINE, JOB_STAGE1, JOB_STAGE2, JOB_COPY = 0, 1, 2, 3, 4
 
 
@@ -61,7 +61,9 @@ _SIGNATURES = {
     "aparareal_set_option": (_i, [_vp, _i, _i]),
     "aparareal_autotune": (_i, [ctypes.POINTER(BatchItem), _i, _vp, ctypes.POINTER(_d)]),
     "aparareal_get_option": (_i, [_vp, _i, ctypes.POINTER(_i)]),
-    "aparareal_pipeline_schedule": (_i, [_i, ctypes.POINTER(SolveParams), _i, _i, ctypes.POINTER(_i), _i]),
+    "aparareal_pipeline_schedule": (_i, [_i, ctypes.POINTER(SolveParams), _i, _i, _i, ctypes.POINTER(_i), _i]),
+    "aparareal_pipeline_schedule_batch": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(SolveParams), _i, _i, _i,
+                                               ctypes.POINTER(_d), ctypes.POINTER(_i), _i]),
     "aparareal_pipeline_status": (_i, [_vp, ctypes.POINTER(_i)]),
     "aparareal_pipeline_trace": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_longlong), _i]),
     "aparareal_profile_read": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_d)]),
@@ -104,13 +106,33 @@ def lib() -> ctypes.CDLL:
 
 
 def pipeline_schedule(N: int, T: float, slices: int, K: int, dt_fine: float, M: int, split: int = -1,
-                      group: int = 0, precision: int = AP_PREC_FP32) -> list[tuple[int, int, int, int]]:
-    """Job order of the pipelined solve as (type, k, n, g) quadruples (host only)."""
+                      group: int = 0, precision: int = AP_PREC_FP32,
+                      fine_group: int = 1) -> list[tuple[int, int, int, int]]:
+    """Job order of the pipelined solve as (type, k, n, g) quadruples (host only);
+    a fine job (type 1) covers slices n .. n + g - 1."""
     p = SolveParams(float(T), int(slices), int(K), float(dt_fine), int(M), 0.0, 0.0, int(precision))
-    cnt = _check(lib().aparareal_pipeline_schedule(N, ctypes.byref(p), split, group, None, 0))
+    cnt = _check(lib().aparareal_pipeline_schedule(N, ctypes.byref(p), split, group, fine_group, None, 0))
     buf = (ctypes.c_int * (4 * max(cnt, 1)))()
-    cnt = _check(lib().aparareal_pipeline_schedule(N, ctypes.byref(p), split, group, buf, cnt))
+    cnt = _check(lib().aparareal_pipeline_schedule(N, ctypes.byref(p), split, group, fine_group, buf, cnt))
     return [tuple(buf[4 * i:4 * i + 4]) for i in range(cnt)]
+
+
+def pipeline_schedule_batch(problems, split: int = -1, group: int = 0, fine_group: int = 1,
+                            precision: int = AP_PREC_FP32, cost=None) -> list[tuple[int, int, int, int, int]]:
+    """Job order of a batched pipelined launch (host only) as (prob, type, k, n, g)
+    quintuples; problems: (N, T, slices, K, dt_fine, M) tuples; cost: optional
+    per-problem (fine step, stage 1, stage 2, whole) durations in us."""
+    cnt_p = len(problems)
+    Ns = (ctypes.c_int * cnt_p)(*[int(q[0]) for q in problems])
+    ps = (SolveParams * cnt_p)(*[SolveParams(float(q[1]), int(q[2]), int(q[3]), float(q[4]), int(q[5]), 0.0, 0.0,
+                                             int(precision)) for q in problems])
+    cs = None
+    if cost is not None:
+        cs = (ctypes.c_double * (4 * cnt_p))(*[float(v) for row in cost for v in row])
+    cnt = _check(lib().aparareal_pipeline_schedule_batch(cnt_p, Ns, ps, split, group, fine_group, cs, None, 0))
+    buf = (ctypes.c_int * (5 * max(cnt, 1)))()
+    cnt = _check(lib().aparareal_pipeline_schedule_batch(cnt_p, Ns, ps, split, group, fine_group, cs, buf, cnt))
+    return [tuple(buf[5 * i:5 * i + 5]) for i in range(cnt)]
 
 
 def _batch_items(problems, precision):

@@ -78,26 +78,71 @@ struct Engine {
   static __device__ __forceinline__ int mode(int j) { return threadIdx.x + j * NT; }
   static __device__ __forceinline__ bool valid(int j) { return mode(j) < KP; }
 
-  // N of owned-mode modal states x -> n, using slot `slot` (callers alternate
-  // slots between consecutive evaluations when S >= 2).
-  __device__ __forceinline__ void neval(int slot, const cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3],
-                                        const Basis<T> (&bs)[MPT]) {
+  // Most slices one job can step together: one retained mode per thread, and
+  // one round of transforms over the wavefronts, and two slots per slice
+  // (alternating evaluations need no extra barrier).
+  static constexpr int jmax() {
+    if (MPT > 1) return 1;
+    const int by_threads = NT / KP;
+    const int by_waves = (NT / 64) * (64 / WavePlan<P>::G) / 3;
+    const int by_slots = S / 2 > 0 ? S / 2 : 1;
+    int j = by_threads < by_waves ? by_threads : by_waves;
+    j = j < by_slots ? j : by_slots;
+    j = j < 16 ? j : 16;
+    return j > 0 ? j : 1;
+  }
+
+  // The (slice, mode) items a thread owns in a job over J slices: for J = 1,
+  // modes threadIdx.x + j NT (j < MPT); for J > 1 (J <= jmax), mode
+  // threadIdx.x mod KP of slice threadIdx.x / KP.  Threads past the last
+  // slice own nothing (their slice index reads as 0, an address in range).
+  struct Own {
+    int s, base;
+    bool in;
+    __device__ __forceinline__ explicit Own(int J) {
+      if (J > 1) {
+        const int q = int(threadIdx.x) / KP;
+        in = q < J;
+        s = in ? q : 0;
+        base = int(threadIdx.x) - q * KP;
+      } else {
+        s = 0;
+        base = threadIdx.x;
+        in = true;
+      }
+    }
+    __device__ __forceinline__ int mode(int j) const { return base + j * NT; }
+    __device__ __forceinline__ bool valid(int j) const { return in && base + j * NT < KP; }
+  };
+
+  // N of the owned items' modal states x -> n for J slices, using slots
+  // slot .. slot + J - 1 (callers alternate between slots 0 and J when
+  // S >= 2 J, so consecutive evaluations need no barrier between them).
+  __device__ __forceinline__ void neval(int slot, int J, const Own& ow, const cx<T> (&x)[MPT][3],
+                                        cx<T> (&n)[MPT][3], const Basis<T> (&bs)[MPT]) {
     cx<T>* sps = sp + slot * SL::sp_elems;
     cx<T>* ibs = ib + slot * SL::ib_elems;
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
-      if (valid(j)) put_fields<T, NX>(sps, 0, mode(j), x[j], bs[j]);
-    zero_tails<T, NX, NT>(sps, 1);
+      if (ow.valid(j)) put_fields<T, NX>(sps, ow.s, ow.mode(j), x[j], bs[j]);
+    zero_tails<T, NX, NT>(sps, J);
     __syncthreads();
-    inverse_fields<T, NX, NT>(sps, ibs, 1, tw);
+    inverse_fields<T, NX, NT>(sps, ibs, J, tw);
     __syncthreads();
-    forward_products<T, NX, NT>(sps, ibs, 1, tw);
+    forward_products<T, NX, NT>(sps, ibs, J, tw);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
-      if (valid(j)) get_N_sp<T, NX>(sps, mode(j), bs[j], tw, n[j]);
-    if constexpr (S == 1) __syncthreads();
+      if (ow.valid(j)) get_N_sp<T, NX>(sps + ow.s * SL::sp_elems, ow.mode(j), bs[j], tw, n[j]);
+    if (S < 2 * J) __syncthreads();
   }
+  // one slice (slot, thread-owned modes as mode(j))
+  __device__ __forceinline__ void neval(int slot, const cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3],
+                                        const Basis<T> (&bs)[MPT]) {
+    neval(slot, 1, Own(1), x, n, bs);
+  }
+  // the slot after `slot` for the next evaluation of a J-slice job
+  static __device__ __forceinline__ int next_slot(int slot, int J) { return S >= 2 * J ? (slot == 0 ? J : 0) : 0; }
 
   // FP64 block maximum of x over the workgroup (NaN wins); result valid in
   // every thread.  The scratch lives in `ib`, so wait for its last readers first.
@@ -150,7 +195,11 @@ __device__ __forceinline__ cx<T> rot_out(cx<T> c, cx<T> e, int alpha_idx) {
 }
 
 // ------------------------------------------------------------ fine ETDRK4 ---
-// One slice: `steps` ETDRK4 steps from src (modal FP64) to dst.
+// J slices (J <= jmax) stepped together: `steps` ETDRK4 steps of slice s from
+// src0 (s = 0) or src1 + (s - 1) 3 KP (modal FP64) to dst + s 3 KP.  The
+// slices share the evaluations' transforms (one round over the wavefronts),
+// and each rounds exactly as it would alone.  JM = 1 compiles the one-slice
+// job (no run-time slice mapping, fewer registers).
 // Coefficient tables [8][3][KP]: E_hi, E_lo, E2_hi, E2_lo, Q, f1, 2*f2, f3.
 // The state and the step accumulator u+ = E u + f1 N(u) + 2f2 (N(a) + N(b))
 // + f3 N(c) stay in FP64 in both precisions (E from the FP64 table): slowly
@@ -158,20 +207,25 @@ __device__ __forceinline__ cx<T> rot_out(cx<T> c, cx<T> e, int alpha_idx) {
 // state would drop those increments coherently step after step.  With
 // T = float the stage states a, b, c, the nonlinear evaluations and the
 // products f*N run in FP32.
-template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, const cx<double>* __restrict__ src,
-                                         cx<double>* __restrict__ dst, int steps,
-                                         const cx<double>* __restrict__ coef64, const cx<T>* __restrict__ coef,
-                                         const Basis<T>* __restrict__ basis) {
+template <typename T, int NX, int NT, int S, int JM = 0>
+__device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, int Jrun, const cx<double>* __restrict__ src0,
+                                         const cx<double>* __restrict__ src1, cx<double>* __restrict__ dst,
+                                         int steps, const cx<double>* __restrict__ coef64,
+                                         const cx<T>* __restrict__ coef, const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, S>;
   constexpr int KP = E_::KP;
   constexpr int MPT = E_::MPT;
+  const int J = JM == 1 ? 1 : Jrun;   // JM = 1: a single slice, known when compiling
+  const typename E_::Own ow(J);
+  // slice s reads src0 (s = 0) or src1 + (s - 1) * 3 KP and writes dst + s * 3 KP
+  const cx<double>* src = ow.s == 0 ? src0 : src1 + size_t(ow.s - 1) * 3 * KP;
+  cx<double>* out = dst + size_t(ow.s) * 3 * KP;
   cx<double> c[MPT][3], cE[MPT][3];
   cx<T> cE2[MPT][3], cQ[MPT][3], cf1[MPT][3], cf2[MPT][3], cf3[MPT][3];
   Basis<T> bs[MPT];
 #pragma unroll
   for (int j = 0; j < MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : KP - 1;
+    const int k = ow.valid(j) ? ow.mode(j) : KP - 1;
     bs[j] = basis[k];
 #pragma unroll
     for (int al = 0; al < 3; ++al) {
@@ -187,8 +241,8 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, const cx<doub
   }
   int slot = 0;
   auto neval = [&](cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3]) {
-    en.neval(slot, x, n, bs);
-    if constexpr (S >= 2) slot ^= 1;
+    en.neval(slot, J, ow, x, n, bs);
+    slot = E_::next_slot(slot, J);
   };
   cx<T> Nx[MPT][3], st[MPT][3], E2c[MPT][3], Nu[MPT][3];
   cx<double> acc[MPT][3];
@@ -232,8 +286,8 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, const cx<doub
   }
 #pragma unroll
   for (int j = 0; j < MPT; ++j)
-    if (E_::valid(j))
-      for (int al = 0; al < 3; ++al) dst[al * KP + E_::mode(j)] = c[j][al];
+    if (ow.valid(j))
+      for (int al = 0; al < 3; ++al) out[al * KP + ow.mode(j)] = c[j][al];
 }
 
 // --------------------------------------------------------- Strang steps ---
@@ -243,10 +297,13 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, const cx<doub
 // v <- v + h N(v + (h/2) N(v)), and the second half step.  The evaluations and
 // the midpoint state run in T; the state and its update stay in FP64.
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void strang_regs(Engine<T, NX, NT, S>& en, cx<double> (&c)[Engine<T, NX, NT, S>::MPT][3],
+__device__ __forceinline__ void strang_regs(Engine<T, NX, NT, S>& en, int J,
+                                            const typename Engine<T, NX, NT, S>::Own& ow,
+                                            cx<double> (&c)[Engine<T, NX, NT, S>::MPT][3],
                                             int steps, const cx<double> (&cE2)[Engine<T, NX, NT, S>::MPT][3],
                                             double h, const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT]) {
-  constexpr int MPT = Engine<T, NX, NT, S>::MPT;
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int MPT = E_::MPT;
   const T hh = T(0.5 * h), hT = T(h);
   int slot = 0;
   cx<T> st[MPT][3], nv[MPT][3];
@@ -259,56 +316,74 @@ __device__ __forceinline__ void strang_regs(Engine<T, NX, NT, S>& en, cx<double>
         v[j][al] = cE2[j][al] * c[j][al];
         st[j][al] = cvt<T>(v[j][al]);
       }
-    en.neval(slot, st, nv, bs);
-    if constexpr (S >= 2) slot ^= 1;
+    en.neval(slot, J, ow, st, nv, bs);
+    slot = E_::next_slot(slot, J);
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
 #pragma unroll
       for (int al = 0; al < 3; ++al) st[j][al] = st[j][al] + hh * nv[j][al];
-    en.neval(slot, st, nv, bs);
-    if constexpr (S >= 2) slot ^= 1;
+    en.neval(slot, J, ow, st, nv, bs);
+    slot = E_::next_slot(slot, J);
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
 #pragma unroll
       for (int al = 0; al < 3; ++al) c[j][al] = cE2[j][al] * (v[j][al] + cvt<double>(hT * nv[j][al]));
   }
 }
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void strang_regs(Engine<T, NX, NT, S>& en, cx<double> (&c)[Engine<T, NX, NT, S>::MPT][3],
+                                            int steps, const cx<double> (&cE2)[Engine<T, NX, NT, S>::MPT][3],
+                                            double h, const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT]) {
+  strang_regs<T, NX, NT, S>(en, 1, typename Engine<T, NX, NT, S>::Own(1), c, steps, cE2, h, bs);
+}
 
-// Owned modes of the FP64 coefficient slot `slot` of a [8][3][KP] table.
+// Owned items of the FP64 coefficient slot `slot` of a [8][3][KP] table.
 template <typename T, int NX, int NT, int S>
 __device__ __forceinline__ void load_coef64(const cx<double>* __restrict__ coef64, int slot,
+                                            const typename Engine<T, NX, NT, S>::Own& ow,
                                             cx<double> (&out)[Engine<T, NX, NT, S>::MPT][3]) {
   using E_ = Engine<T, NX, NT, S>;
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : E_::KP - 1;
+    const int k = ow.valid(j) ? ow.mode(j) : E_::KP - 1;
     for (int al = 0; al < 3; ++al) out[j][al] = coef64[size_t(slot) * 3 * E_::KP + al * E_::KP + k];
   }
 }
-
-// `steps` Strang steps of size h from src to dst (modal FP64; the table's slot
-// 2 holds E2 = e^{(h/2) lambda}).
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void strang_job(Engine<T, NX, NT, S>& en, const cx<double>* __restrict__ src,
-                                           cx<double>* __restrict__ dst, int steps,
-                                           const cx<double>* __restrict__ coef64, double h,
+__device__ __forceinline__ void load_coef64(const cx<double>* __restrict__ coef64, int slot,
+                                            cx<double> (&out)[Engine<T, NX, NT, S>::MPT][3]) {
+  load_coef64<T, NX, NT, S>(coef64, slot, typename Engine<T, NX, NT, S>::Own(1), out);
+}
+
+// `steps` Strang steps of size h for J slices (as fine_job: slice s from src0
+// or src1 + (s - 1) 3 KP to dst + s 3 KP; modal FP64; the table's slot 2
+// holds E2 = e^{(h/2) lambda}).
+template <typename T, int NX, int NT, int S, int JM = 0>
+__device__ __forceinline__ void strang_job(Engine<T, NX, NT, S>& en, int Jrun, const cx<double>* __restrict__ src0,
+                                           const cx<double>* __restrict__ src1, cx<double>* __restrict__ dst,
+                                           int steps, const cx<double>* __restrict__ coef64, double h,
                                            const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, S>;
   constexpr int MPT = E_::MPT;
+  constexpr int KP = E_::KP;
+  const int J = JM == 1 ? 1 : Jrun;   // JM = 1: a single slice, known when compiling
+  const typename E_::Own ow(J);
+  const cx<double>* src = ow.s == 0 ? src0 : src1 + size_t(ow.s - 1) * 3 * KP;
+  cx<double>* out = dst + size_t(ow.s) * 3 * KP;
   cx<double> c[MPT][3], cE2[MPT][3];
   Basis<T> bs[MPT];
 #pragma unroll
   for (int j = 0; j < MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : E_::KP - 1;
+    const int k = ow.valid(j) ? ow.mode(j) : KP - 1;
     bs[j] = basis[k];
-    for (int al = 0; al < 3; ++al) c[j][al] = src[al * E_::KP + k];
+    for (int al = 0; al < 3; ++al) c[j][al] = src[al * KP + k];
   }
-  load_coef64<T, NX, NT, S>(coef64, 2, cE2);
-  strang_regs<T, NX, NT, S>(en, c, steps, cE2, h, bs);
+  load_coef64<T, NX, NT, S>(coef64, 2, ow, cE2);
+  strang_regs<T, NX, NT, S>(en, J, ow, c, steps, cE2, h, bs);
 #pragma unroll
   for (int j = 0; j < MPT; ++j)
-    if (E_::valid(j))
-      for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = c[j][al];
+    if (ow.valid(j))
+      for (int al = 0; al < 3; ++al) out[al * KP + ow.mode(j)] = c[j][al];
 }
 
 // ----------------------------------------------------------- time average ---

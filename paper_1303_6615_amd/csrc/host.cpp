@@ -21,6 +21,7 @@
 #include <complex>
 #include <cstring>
 #include <algorithm>
+#include <limits>
 #include <map>
 #include <memory>
 #include <string>
@@ -171,6 +172,7 @@ struct ap_ctx {
   int opt_sweeps = 0;        // tol > 0: iteration-ordered sweeps with host residual checks
   int opt_fine = 0;          // fine slices: 0 ETDRK4, 1 Strang steps (Alg. 3)
   int opt_coarse = 0;        // coarse step: 0 asymptotic (Alg. 2), 1 one Strang step (standard parareal)
+  int opt_fine_group = 0;    // slices per fine job: 0 automatic, else at most this many
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;   // private stream the graph is captured on
@@ -481,6 +483,7 @@ struct PipeShape {
   bool split = false, fp64 = false;
   bool skip = true;          // slices n <= k of level k copy their exact values
   int fine_kind = 0, coarse_kind = 0;
+  int fg = 1;                // slices per fine job (consecutive slices of one level, stepped together)
   double tol = 0.0;
   CostCal cal;
 };
@@ -527,42 +530,63 @@ struct SchedItem {
 // Jobs of one problem with their earliest start times: a fine slice F(k,n)
 // and the first stage of C(k,n) start when C(k,n-1) is done; the second stage
 // one stage later; C(k,n) is done after both stages and (k >= 1) after F(k-1,n)
-// and C(k-1,n).  Returns the estimated completion of the last coarse step.
+// and C(k-1,n).  A fine job over fg consecutive slices n .. n+fg-1 starts when
+// the last of their inputs, C(k,n+fg-2), is done.  Any stage-2 job may finish
+// its step and then waits for F(k-1,n) and C(k-1,n), so the stage-2 jobs are
+// also placed after the jobs computing those (their times made just larger).
+// Returns the estimated completion of the last coarse step.
 double problem_jobs(int prob, const PipeShape& q, std::vector<SchedItem>& out) {
   const JobCost jc = job_cost(q);
-  const int Ns = q.Ns, K = q.K;
-  std::vector<double> dC(size_t(K + 1) * Ns, 0.0), dF(size_t(std::max(K, 1)) * Ns, 0.0);
+  const int Ns = q.Ns, K = q.K, fg = std::max(1, q.fg);
+  const size_t cells = size_t(K + 1) * Ns;
+  std::vector<double> dC(cells, 0.0), dF(cells, 0.0), dFs(cells, 0.0), dT2(cells, 0.0);
   auto C = [&](int k, int n) -> double& { return dC[size_t(k) * Ns + n - 1]; };
   auto Fd = [&](int k, int n) -> double& { return dF[size_t(k) * Ns + n - 1]; };
+  auto Fs = [&](int k, int n) -> double& { return dFs[size_t(k) * Ns + n - 1]; };   // start of F(k,n)'s job
+  auto T2 = [&](int k, int n) -> double& { return dT2[size_t(k) * Ns + n - 1]; };   // latest time of C(k,n)'s jobs
+  const double inf = std::numeric_limits<double>::infinity();
   const size_t first = out.size();
-  for (int k = 0; k <= K; ++k)
+  for (int k = 0; k <= K; ++k) {
     for (int n = 1; n <= Ns; ++n) {
       if (q.skip && k >= 1 && n <= k) {
         // exact slice: U(k,n) from U(k-1,n) or F(k-1,k); no fine slice F(k,n)
         double ready = C(k - 1, n);
         if (n == k) ready = std::max(ready, Fd(k - 1, n));
         out.push_back({ready, 0.0, 0, {prob, ap::kJobCopy, k, n, 0}});
+        T2(k, n) = ready;
         C(k, n) = ready + 1.0;
         continue;
       }
       const double ready = n > 1 ? C(k, n - 1) : 0.0;
-      if (k < K) {
-        Fd(k, n) = ready + jc.fine;
-        out.push_back({ready, 0.0, 2, {prob, ap::kJobFine, k, n, 0}});
-      }
       double after = 0.0;
       if (k >= 1) after = std::max(Fd(k - 1, n), C(k - 1, n));
       if (q.split) {
+        double t2 = ready + jc.stage1;
+        if (k >= 1) t2 = std::max({t2, std::nextafter(Fs(k - 1, n), inf), std::nextafter(T2(k - 1, n), inf)});
         for (int g = 0; g < q.groups; ++g) out.push_back({ready, 0.0, 0, {prob, ap::kJobStage1, k, n, g}});
-        for (int g = 0; g < q.groups; ++g)
-          out.push_back({ready + jc.stage1, 0.0, 1, {prob, ap::kJobStage2, k, n, g}});
-        C(k, n) = std::max(ready + jc.stage1 + jc.stage2, after) + jc.finish;
+        for (int g = 0; g < q.groups; ++g) out.push_back({t2, 0.0, 1, {prob, ap::kJobStage2, k, n, g}});
+        T2(k, n) = t2;
+        C(k, n) = std::max({ready + jc.stage1 + jc.stage2, after, t2}) + jc.finish;
       } else {
         const double start = std::max(ready, after);
         out.push_back({start, 0.0, 0, {prob, ap::kJobCoarse, k, n, 0}});
+        T2(k, n) = start;
         C(k, n) = start + jc.whole;
       }
     }
+    if (k == K) break;
+    // fine jobs of level k (inputs U(k, n-1) known now)
+    for (int n = q.skip && k >= 1 ? k + 1 : 1; n <= Ns; n += fg) {
+      const int g = std::min(fg, Ns - n + 1);
+      const int last = n + g - 2;
+      const double ready = last >= 1 ? C(k, last) : 0.0;
+      for (int i = 0; i < g; ++i) {
+        Fs(k, n + i) = ready;
+        Fd(k, n + i) = ready + jc.fine;
+      }
+      out.push_back({ready, 0.0, 2, {prob, ap::kJobFine, k, n, g}});
+    }
+  }
   const double span = C(K, Ns);
   for (size_t i = first; i < out.size(); ++i) out[i].crit = span;
   return span;
@@ -588,8 +612,13 @@ bool order_is_valid(const std::vector<ap::PipeJob>& jobs, const std::vector<Pipe
     const size_t at = base[j.prob] + size_t(j.k) * q.Ns + (j.n - 1);
     const long long pos = (long long)i;
     if (j.type == ap::kJobFine) {
-      if (j.k >= q.K || fpos[at] != none) return false;
-      fpos[at] = pos;
+      // slices n .. n + g - 1 (g >= 1, at most the problem's slices per fine job)
+      const int g = std::max(1, j.g);
+      if (j.k >= q.K || g > std::max(1, q.fg) || j.n + g - 1 > q.Ns) return false;
+      for (int i = 0; i < g; ++i) {
+        if (fpos[at + i] != none) return false;
+        fpos[at + i] = pos;
+      }
       continue;
     }
     if (cfirst[at] == none) cfirst[at] = pos;
@@ -783,6 +812,22 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     nx_max = std::max(nx_max, q.nx);
   }
   if (ncnt > (1LL << 30)) return fail(AP_EINVAL, "batch too large");
+  // resident workgroups of the launch
+  int grid = ap::pipeline_max_grid(nx_common, nx_max, f64);
+  if (grid <= 0) return fail(AP_EDEVICE, "pipeline kernel does not fit the device");
+  if (owner->opt_grid > 0) grid = std::min(grid, owner->opt_grid);
+  // Slices per fine job: stepping several slices in one workgroup costs a job
+  // about what one slice costs, but a group starts only when its last input
+  // is ready.  Automatic: one slice while the batch's slices fit the resident
+  // workgroups (the solve is latency-bound), else the most per grid size.
+  long long slices_total = 0;
+  for (auto& it : items) slices_total += it.q.Ns;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const int jm = ap::pipeline_fine_slices(items[i].q.nx, f64);
+    const int want = items[i].c->opt_fine_group;
+    items[i].q.fg = want > 0 ? std::min(want, jm) : (slices_total > grid ? jm : 1);
+    shapes[i].fg = items[i].q.fg;
+  }
   // counters, then ticket, stall record [4] (stalled, job, counter, jobs
   // completed), per-workgroup progress [2][1024]
   const long long nflags = ncnt + 5 + 2 * 1024;
@@ -797,7 +842,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     key += std::to_string(q.nx) + ":" + std::to_string(q.Ns) + ":" + std::to_string(q.K) + ":" +
            std::to_string(q.steps) + ":" + std::to_string(q.M) + ":" + std::to_string(q.gs) + ":" +
            std::to_string(int(q.split)) + ":" + std::to_string(int(q.fp64)) + ":" + std::to_string(int(q.skip)) + ":" +
-           std::to_string(q.fine_kind) + std::to_string(q.coarse_kind) + ":" +
+           std::to_string(q.fine_kind) + std::to_string(q.coarse_kind) + ":" + std::to_string(q.fg) + ":" +
            (q.cal.valid ? std::to_string(q.cal.fine_step) + "," + std::to_string(q.cal.stage1) + "," +
                               std::to_string(q.cal.stage2) + "," + std::to_string(q.cal.whole)
                         : std::string("-")) + ";";
@@ -837,9 +882,6 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     return hip_fail(e, "problem descriptor upload");
   if ((e = upload_if_changed(owner, owner->pp_rows, owner->pp_rows_host, as_bytes(rows))) != hipSuccess)
     return hip_fail(e, "residual table upload");
-  int grid = ap::pipeline_max_grid(nx_common, nx_max, f64);
-  if (grid <= 0) return fail(AP_EDEVICE, "pipeline kernel does not fit the device");
-  if (owner->opt_grid > 0) grid = std::min(grid, owner->opt_grid);
   grid = std::max(1, std::min({grid, owner->pp_njobs, 1024}));   // progress record holds 1024 workgroups
   unsigned long long* trace = nullptr;
   if (owner->trace_on) {
@@ -1311,6 +1353,10 @@ int aparareal_set_option(ap_ctx* c, int option, int value) {
       if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_FINE takes 0 (ETDRK4) or 1 (Strang)");
       c->opt_fine = value;
       return AP_OK;
+    case AP_OPT_FINE_GROUP:
+      if (value < 0 || value > 64) return fail(AP_EINVAL, "AP_OPT_FINE_GROUP takes 0..64");
+      c->opt_fine_group = value;
+      return AP_OK;
     case AP_OPT_COARSE:
       if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_COARSE takes 0 (asymptotic) or 1 (Strang)");
       c->opt_coarse = value;
@@ -1333,6 +1379,7 @@ int aparareal_get_option(ap_ctx* c, int option, int* value) {
     case AP_OPT_SWEEPS: *value = c->opt_sweeps; return AP_OK;
     case AP_OPT_FINE: *value = c->opt_fine; return AP_OK;
     case AP_OPT_COARSE: *value = c->opt_coarse; return AP_OK;
+    case AP_OPT_FINE_GROUP: *value = c->opt_fine_group; return AP_OK;
     default: return fail(AP_EINVAL, "unknown option");
   }
 }
@@ -1349,25 +1396,47 @@ int aparareal_pipeline_status(ap_ctx* c, int* info) {
   return AP_OK;
 }
 
-int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int group, int* out, int max_jobs) {
+namespace {
+// Shape of a problem of a schedule query (no context needed).
+int query_shape(int N, const ap_solve_params* p, int split, int group, int fine_group, const double* cost,
+                PipeShape* q) {
   if (!p || !is_pow2(N) || N < 64 || N > 2048 || p->slices < 1 || p->K < 0 || p->M_avg < 2 || group < 0 ||
-      split < -1 || split > 1 || !(p->T > 0.0) || !(p->dt_fine > 0.0) || max_jobs < 0)
+      split < -1 || split > 1 || fine_group < 1 || fine_group > 64 || !(p->T > 0.0) || !(p->dt_fine > 0.0))
     return fail(AP_EINVAL, "bad schedule query");
   if (size_t(2 * p->K + 1) * size_t(p->slices) > (size_t(1) << 24)) return fail(AP_EINVAL, "problem too large");
   const double dT = p->T / p->slices;
   const double ratio = dT / p->dt_fine;
   if (ratio > 1e7) return fail(AP_EINVAL, "dT/dt_fine too large");
+  q->nx = N;
+  q->Ns = p->slices;
+  q->K = p->K;
+  q->steps = std::max(1, int(std::ceil(ratio - 1e-9)));
+  q->M = p->M_avg;
+  q->gs = group > 0 ? group : default_group_size(N);
+  q->groups = ap::avg_groups(q->M, q->gs);
+  q->fp64 = p->precision == AP_PREC_FP64;
+  q->split = split < 0 ? q->groups >= 2 : split != 0;
+  q->skip = true;
+  q->fg = std::min(fine_group, ap::pipeline_fine_slices(N, q->fp64));
+  if (cost) {
+    for (int i = 0; i < 4; ++i)
+      if (!(cost[i] >= 0.0) || !(cost[i] < 1e9)) return fail(AP_EINVAL, "bad job duration");
+    q->cal.valid = true;
+    q->cal.fine_step = cost[0];
+    q->cal.stage1 = cost[1];
+    q->cal.stage2 = cost[2];
+    q->cal.whole = cost[3];
+  }
+  return AP_OK;
+}
+}  // namespace
+
+int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int group, int fine_group, int* out,
+                                int max_jobs) {
+  if (max_jobs < 0) return fail(AP_EINVAL, "bad schedule query");
   PipeShape q;
-  q.nx = N;
-  q.Ns = p->slices;
-  q.K = p->K;
-  q.steps = std::max(1, int(std::ceil(ratio - 1e-9)));
-  q.M = p->M_avg;
-  q.gs = group > 0 ? group : default_group_size(N);
-  q.groups = ap::avg_groups(q.M, q.gs);
-  q.fp64 = p->precision == AP_PREC_FP64;
-  q.split = split < 0 ? q.groups >= 2 : split != 0;
-  q.skip = true;
+  const int rc = query_shape(N, p, split, group, fine_group, nullptr, &q);
+  if (rc) return rc;
   const std::vector<PipeShape> shapes{q};
   const std::vector<ap::PipeJob> jobs = schedule_jobs(shapes);
   if (!order_is_valid(jobs, shapes)) return fail(AP_EINVAL, "internal: job order is not topological");
@@ -1377,6 +1446,30 @@ int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int 
       out[4 * i + 1] = jobs[i].k;
       out[4 * i + 2] = jobs[i].n;
       out[4 * i + 3] = jobs[i].g;
+    }
+  return int(jobs.size());
+}
+
+int aparareal_pipeline_schedule_batch(int count, const int* N, const ap_solve_params* p, int split, int group,
+                                      int fine_group, const double* cost, int* out, int max_jobs) {
+  if (count < 1 || count > 4096 || !N || !p || max_jobs < 0) return fail(AP_EINVAL, "bad schedule query");
+  std::vector<PipeShape> shapes(static_cast<size_t>(count));
+  size_t cells = 0;
+  for (int i = 0; i < count; ++i) {
+    const int rc = query_shape(N[i], &p[i], split, group, fine_group, cost ? cost + 4 * i : nullptr, &shapes[i]);
+    if (rc) return rc;
+    cells += size_t(2 * p[i].K + 1) * size_t(p[i].slices);
+    if (cells > (size_t(1) << 24)) return fail(AP_EINVAL, "batch too large");
+  }
+  const std::vector<ap::PipeJob> jobs = schedule_jobs(shapes);
+  if (!order_is_valid(jobs, shapes)) return fail(AP_EINVAL, "internal: job order is not topological");
+  if (out)
+    for (size_t i = 0; i < jobs.size() && i < size_t(max_jobs); ++i) {
+      out[5 * i] = jobs[i].prob;
+      out[5 * i + 1] = jobs[i].type;
+      out[5 * i + 2] = jobs[i].k;
+      out[5 * i + 3] = jobs[i].n;
+      out[5 * i + 4] = jobs[i].g;
     }
   return int(jobs.size());
 }

@@ -24,14 +24,22 @@
 
 namespace ap {
 
+// Fine batches: for N <= 256 a 512-thread workgroup steps several slices
+// together (Engine::jmax: 16, 10, 5 for N = 64, 128, 256), with two slots per
+// slice; larger grids run one slice per workgroup of just enough threads to
+// own one mode each, with two slots.
 template <int NX>
 constexpr int fine_threads() {
-  return NX <= 512 ? 192 : NX == 1024 ? 384 : 704;
+  return NX <= 256 ? 512 : NX == 512 ? 192 : NX == 1024 ? 384 : 704;
 }
-// two slots (alternating evaluations) when they fit
 template <typename T, int NX, int NT>
 constexpr int fine_slots() {
+  if constexpr (NX <= 256) return max_slots<T, NX, NT>();
   return max_slots<T, NX, NT>() >= 2 ? 2 : 1;
+}
+template <typename T, int NX>
+constexpr int fine_slices() {
+  return Engine<T, NX, fine_threads<NX>(), fine_slots<T, NX, fine_threads<NX>()>()>::jmax();
 }
 // ------------------------------------------------- boundary transforms -----
 // physical [B][3][N] float64 -> modal [B][3][KP] complex float64 (projected)
@@ -140,29 +148,36 @@ __global__ void __launch_bounds__(NT) k_nonlinear(const cx<double>* __restrict__
 }
 
 // ------------------------------------------------------------ fine batch ---
+// Workgroup b steps slices b J .. min(b J + J, batch) - 1 (J = fine_slices).
 template <typename T, int NX, int NT>
 __global__ void __launch_bounds__(NT) k_fine(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
-                                             int steps, const cx<double>* __restrict__ coef64,
+                                             int batch, int steps, const cx<double>* __restrict__ coef64,
                                              const cx<T>* __restrict__ coef, const cx<T>* __restrict__ tw,
                                              const Basis<T>* __restrict__ basis) {
-  using E_ = Engine<T, NX, NT, fine_slots<T, NX, NT>()>;
+  constexpr int S = fine_slots<T, NX, NT>();
+  using E_ = Engine<T, NX, NT, S>;
   extern __shared__ unsigned char smem_raw[];
   E_ en(smem_raw, tw);
   const size_t st = size_t(3) * E_::KP;
-  fine_job<T, NX, NT, fine_slots<T, NX, NT>()>(en, Uin + blockIdx.x * st, Uout + blockIdx.x * st, steps, coef64,
-                                                 coef, basis);
+  const int first = blockIdx.x * E_::jmax();
+  const int J = min(E_::jmax(), batch - first);
+  fine_job<T, NX, NT, S>(en, J, Uin + first * st, Uin + (first + 1) * st, Uout + first * st, steps, coef64, coef,
+                         basis);
 }
 
 template <typename T, int NX, int NT>
 __global__ void __launch_bounds__(NT) k_strang(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
-                                               int steps, double h, const cx<double>* __restrict__ coef64,
+                                               int batch, int steps, double h, const cx<double>* __restrict__ coef64,
                                                const cx<T>* __restrict__ tw, const Basis<T>* __restrict__ basis) {
-  using E_ = Engine<T, NX, NT, fine_slots<T, NX, NT>()>;
+  constexpr int S = fine_slots<T, NX, NT>();
+  using E_ = Engine<T, NX, NT, S>;
   extern __shared__ unsigned char smem_raw[];
   E_ en(smem_raw, tw);
   const size_t st = size_t(3) * E_::KP;
-  strang_job<T, NX, NT, fine_slots<T, NX, NT>()>(en, Uin + blockIdx.x * st, Uout + blockIdx.x * st, steps, coef64, h,
-                                                   basis);
+  const int first = blockIdx.x * E_::jmax();
+  const int J = min(E_::jmax(), batch - first);
+  strang_job<T, NX, NT, S>(en, J, Uin + first * st, Uin + (first + 1) * st, Uout + first * st, steps, coef64, h,
+                           basis);
 }
 
 // ---------------------------------------------------- average and coarse ---
@@ -315,9 +330,10 @@ static hipError_t fine_nx(const cx<double>* in, cx<double>* out, int batch, int 
                           const cx<T>* coef, const DevTables& t, hipStream_t s) {
   constexpr int NT = fine_threads<NX>();
   const size_t lds = Engine<T, NX, NT, fine_slots<T, NX, NT>()>::lds_bytes();
+  const int J = fine_slices<T, NX>();
   prep_lds(k_fine<T, NX, NT>, lds);
-  hipLaunchKernelGGL((k_fine<T, NX, NT>), dim3(batch), dim3(NT), lds, s, in, out, steps, coef64, coef, t.tw<T>(),
-                     t.basis<T>());
+  hipLaunchKernelGGL((k_fine<T, NX, NT>), dim3((batch + J - 1) / J), dim3(NT), lds, s, in, out, batch, steps, coef64,
+                     coef, t.tw<T>(), t.basis<T>());
   return hipGetLastError();
 }
 
@@ -326,9 +342,10 @@ static hipError_t strang_nx(const cx<double>* in, cx<double>* out, int batch, in
                             const cx<double>* coef64, const DevTables& t, hipStream_t s) {
   constexpr int NT = fine_threads<NX>();
   const size_t lds = Engine<T, NX, NT, fine_slots<T, NX, NT>()>::lds_bytes();
+  const int J = fine_slices<T, NX>();
   prep_lds(k_strang<T, NX, NT>, lds);
-  hipLaunchKernelGGL((k_strang<T, NX, NT>), dim3(batch), dim3(NT), lds, s, in, out, steps, h, coef64, t.tw<T>(),
-                     t.basis<T>());
+  hipLaunchKernelGGL((k_strang<T, NX, NT>), dim3((batch + J - 1) / J), dim3(NT), lds, s, in, out, batch, steps, h,
+                     coef64, t.tw<T>(), t.basis<T>());
   return hipGetLastError();
 }
 
@@ -430,6 +447,22 @@ static bool pipe_kernel(int nx, int nx_max, bool fp64, PipeLaunchFn* fn, PipeOcc
     *occ = pipe_occupancy_mix2048_f32;
   }
   return true;
+}
+
+template <typename T>
+static int pipeline_fine_slices_t(int nx) {
+  constexpr int NT = kPipeThreads;
+  switch (nx) {
+    case 64: return Engine<T, 64, NT, pipe_slots<T, 64>()>::jmax();
+    case 128: return Engine<T, 128, NT, pipe_slots<T, 128>()>::jmax();
+    case 256: return Engine<T, 256, NT, pipe_slots<T, 256>()>::jmax();
+    case 512: return Engine<T, 512, NT, pipe_slots<T, 512>()>::jmax();
+    case 1024: return Engine<T, 1024, NT, pipe_slots<T, 1024>()>::jmax();
+    default: return Engine<T, 2048, NT, pipe_slots<T, 2048>()>::jmax();
+  }
+}
+int pipeline_fine_slices(int nx, bool fp64) {
+  return fp64 ? pipeline_fine_slices_t<double>(nx) : pipeline_fine_slices_t<float>(nx);
 }
 
 int pipeline_max_grid(int nx, int nx_max, bool fp64) {

@@ -93,7 +93,10 @@ __device__ __forceinline__ bool wait_deps(const PipeJob& jb, const PipeProb<T>& 
     if (n == k && !wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n))) return false;
     return wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n));
   }
-  if (n > 1 && !wait_count(&p.cnt[ix.coarse(k, n - 1)], 1, diag, jt, ix.coarse(k, n - 1))) return false;
+  // a fine job over slices n .. n + g - 1 (g >= 2) needs their inputs U(k, n - 1 .. n + g - 2): the
+  // coarse chain publishes in order, so the last one suffices
+  const int last = jb.type == kJobFine && jb.g > 1 ? n + jb.g - 2 : n - 1;
+  if (last >= 1 && !wait_count(&p.cnt[ix.coarse(k, last)], 1, diag, jt, ix.coarse(k, last))) return false;
   if (jb.type == kJobCoarse && k >= 1) {
     if (!wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n))) return false;
     if (!wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n))) return false;
@@ -118,13 +121,16 @@ constexpr size_t pipe_lds() {
 // `staged` tracks the twiddle table held in LDS across jobs.
 template <typename T, int NX>
 __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
-                                       const void*& staged, int* diag, int jt, int* s_flag, bool skip) {
+                                       const void*& staged, int* diag, int jt, int* s_flag, bool skip, int& npub) {
   constexpr int NT = kPipeThreads;
   constexpr int S = pipe_slots<T, NX>();
   using E_ = Engine<T, NX, NT, S>;
   constexpr int MPT = E_::MPT;
   const PipeIdx ix{p.Ns, p.K};
   const int Ns = p.Ns, k = jb.k, n = jb.n;
+  // a fine job steps J consecutive slices together and publishes their J counters
+  const int J = jb.type == kJobFine && jb.g > 1 ? min(jb.g, E_::jmax()) : 1;
+  npub = J;
   if (skip) {
     // past the stopped level: publish only (stage-2 jobs still count in so
     // that the last one publishes the step)
@@ -159,10 +165,20 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
     return ix.coarse(k, n);
   };
   if (jb.type == kJobFine) {
-    if (p.fine_kind == 1)
-      strang_job<T, NX, NT, S>(en, uprev, state(p.F, k, n), p.steps, p.coef64, p.hf, p.basis);
-    else
-      fine_job<T, NX, NT, S>(en, uprev, state(p.F, k, n), p.steps, p.coef64, p.coef, p.basis);
+    // slice n reads uprev, slices n + s (s >= 1) read U(k, n + s - 1), stored in order from U(k, n)
+    const cx<double>* src1 = state(p.U, k, n);
+    cx<double>* dst = state(p.F, k, n);
+    if (p.fine_kind == 1) {
+      if (J == 1)
+        strang_job<T, NX, NT, S, 1>(en, 1, uprev, src1, dst, p.steps, p.coef64, p.hf, p.basis);
+      else
+        strang_job<T, NX, NT, S>(en, J, uprev, src1, dst, p.steps, p.coef64, p.hf, p.basis);
+    } else {
+      if (J == 1)
+        fine_job<T, NX, NT, S, 1>(en, 1, uprev, src1, dst, p.steps, p.coef64, p.coef, p.basis);
+      else
+        fine_job<T, NX, NT, S>(en, J, uprev, src1, dst, p.steps, p.coef64, p.coef, p.basis);
+    }
     return ix.fine(k, n);
   }
   if (jb.type == kJobCopy) {
@@ -233,10 +249,11 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
 
 template <typename T, int NX, int... REST>
 __device__ __forceinline__ int dispatch_job(int nx, unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
-                                            const void*& staged, int* diag, int jt, int* s_flag, bool skip) {
-  if (nx == NX) return run_job<T, NX>(smem, jb, p, staged, diag, jt, s_flag, skip);
+                                            const void*& staged, int* diag, int jt, int* s_flag, bool skip,
+                                            int& npub) {
+  if (nx == NX) return run_job<T, NX>(smem, jb, p, staged, diag, jt, s_flag, skip, npub);
   if constexpr (sizeof...(REST) > 0)
-    return dispatch_job<T, REST...>(nx, smem, jb, p, staged, diag, jt, s_flag, skip);
+    return dispatch_job<T, REST...>(nx, smem, jb, p, staged, diag, jt, s_flag, skip, npub);
   else
     return -1;
 }
@@ -256,14 +273,16 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
   // both sides of the back-edge would form a single divergent region across
   // it, which the compiler may turn into a loop the other lanes never leave.
   // The values read back from LDS are made uniform with readfirstlane.
-  int pub = -1;                 // counter index of the job finished last
+  int pub = -1;                 // first counter index of the job finished last
+  int npub = 1;                 // consecutive counters it publishes
   int* pub_cnt = nullptr;
   const void* staged = nullptr;
   for (;;) {
     if (threadIdx.x == 0) {
       if (pub >= 0) {
         __threadfence();
-        __hip_atomic_fetch_add(&pub_cnt[pub], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        for (int i = 0; i < npub; ++i)
+          __hip_atomic_fetch_add(&pub_cnt[pub + i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(abort + 3, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (progress) {
           progress[2 * blockIdx.x] += 1;
@@ -293,8 +312,10 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
     const PipeProb<T>& p = probs[jb.prob];
     const int nx = __builtin_amdgcn_readfirstlane(p.nx);
     const bool skip = __builtin_amdgcn_readfirstlane(s_skip) != 0;
+    int np = 1;
     pub = __builtin_amdgcn_readfirstlane(
-        dispatch_job<T, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip));
+        dispatch_job<T, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip, np));
+    npub = __builtin_amdgcn_readfirstlane(np);
     pub_cnt = p.cnt;
     __syncthreads();
     if (trace && threadIdx.x == 0) trace[3 * j + 1] = wall_clock64();

@@ -51,8 +51,9 @@ def test_solve_params_layout_matches_header():
     assert ctypes.sizeof(binding.SolveParams) == 56
 
 
-def _deps(job, K, groups, split):
-    """Jobs that must precede `job` = (type, k, n, g) in the hand-out order."""
+def _deps(job, K, groups, split, fine_of):
+    """Jobs that must precede `job` = (type, k, n, g) in the hand-out order;
+    fine_of[(k, n)] is the fine job that steps slice F(k, n)."""
     t, k, n, g = job
 
     def step(kk, nn):            # the jobs that complete C(kk, nn)
@@ -60,28 +61,42 @@ def _deps(job, K, groups, split):
             return [(4, kk, nn, 0)]
         return [(3, kk, nn, x) for x in range(groups)] if split else [(0, kk, nn, 0)]
     if t == 4:                   # exact slice: after C(k-1, n) and, for n = k, F(k-1, k)
-        return step(k - 1, n) + ([(1, k - 1, n, 0)] if n == k else [])
+        return step(k - 1, n) + ([fine_of[(k - 1, n)]] if n == k else [])
+    if t == 1:                   # fine slices n .. n + g - 1: after their inputs U(k, n - 1 .. n + g - 2)
+        return [d for m in range(n, n + g) if m > 1 for d in step(k, m - 1)]
     prev = step(k, n - 1) if n > 1 else []
-    if t in (1, 2):
+    if t == 2:
         return prev
-    before = [(1, k - 1, n, 0)] + step(k - 1, n) if k >= 1 else []
+    before = [fine_of[(k - 1, n)]] + step(k - 1, n) if k >= 1 else []
     if t == 0:
         return prev + before
     return [(2, k, n, x) for x in range(groups)] + before     # stage 2 (any may finish the step)
 
 
-@pytest.mark.parametrize("N,T,Ns,K,dt,M,split,group", [
-    (64, 1.0, 16, 5, 0.0005, 16, -1, 0), (256, 2.0, 64, 8, 0.0005, 32, -1, 0),
-    (256, 2.0, 64, 8, 0.0005, 32, 0, 0), (128, 0.7, 7, 3, 0.1, 2, 1, 0), (512, 1.0, 5, 0, 0.01, 8, -1, 3),
-    (1024, 1.0, 256, 10, 0.0001, 64, -1, 0), (2048, 1.0, 3, 9, 1e-4, 32, 1, 7), (64, 1.0, 4, 2, 0.05, 9, 1, 1)])
-def test_pipeline_schedule_is_topological_and_drains(L, N, T, Ns, K, dt, M, split, group):
-    jobs = binding.pipeline_schedule(N, T, Ns, K, dt, M, split=split, group=group)
+# most slices per fine job by grid size (FP32 pipeline workgroups of 512 threads)
+_FINE_MAX = {64: 16, 128: 10, 256: 5, 512: 2, 1024: 1, 2048: 1}
+
+
+@pytest.mark.parametrize("N,T,Ns,K,dt,M,split,group,fg", [
+    (64, 1.0, 16, 5, 0.0005, 16, -1, 0, 1), (256, 2.0, 64, 8, 0.0005, 32, -1, 0, 1),
+    (256, 2.0, 64, 8, 0.0005, 32, 0, 0, 1), (128, 0.7, 7, 3, 0.1, 2, 1, 0, 1), (512, 1.0, 5, 0, 0.01, 8, -1, 3, 1),
+    (1024, 1.0, 256, 10, 0.0001, 64, -1, 0, 1), (2048, 1.0, 3, 9, 1e-4, 32, 1, 7, 1), (64, 1.0, 4, 2, 0.05, 9, 1, 1, 1),
+    (256, 2.0, 64, 8, 0.0005, 32, -1, 0, 64), (256, 2.0, 23, 4, 0.0005, 32, 0, 0, 3),
+    (64, 1.0, 40, 6, 0.0005, 16, 1, 0, 64), (128, 0.7, 7, 3, 0.1, 2, 1, 0, 4), (512, 1.0, 9, 5, 0.01, 8, -1, 0, 64),
+    (1024, 1.0, 12, 3, 0.0001, 64, -1, 0, 8)])
+def test_pipeline_schedule_is_topological_and_drains(L, N, T, Ns, K, dt, M, split, group, fg):
+    jobs = binding.pipeline_schedule(N, T, Ns, K, dt, M, split=split, group=group, fine_group=fg)
     gs = group if group > 0 else max(1, 8 * (64 // (8 if N <= 64 else 16 if N <= 128 else 32 if N <= 256 else 64)) // 3)
     groups = (M - 1 + gs - 1) // gs
     is_split = (groups >= 2) if split < 0 else bool(split)
     steps = max(1, math.ceil(T / Ns / dt - 1e-9))
-    # fine slices F(k, n) for n > k; slices n <= k of level k >= 1 are copies
-    want = {(1, k, n, 0) for k in range(K) for n in range(k + 1, Ns + 1)}
+    J = min(fg, _FINE_MAX[N])
+    # fine slices F(k, n) for n > k, in jobs of J consecutive slices from n = k + 1
+    # (the last of a level may be shorter); slices n <= k of level k >= 1 are copies
+    want = set()
+    for k in range(K):
+        for n in range(k + 1, Ns + 1, J):
+            want.add((1, k, n, min(J, Ns - n + 1)))
     want |= {(4, k, n, 0) for k in range(1, K + 1) for n in range(1, min(k, Ns) + 1)}
     real = [(k, n) for k in range(K + 1) for n in range(1, Ns + 1) if not (k >= 1 and n <= k)]
     if is_split:
@@ -89,9 +104,10 @@ def test_pipeline_schedule_is_topological_and_drains(L, N, T, Ns, K, dt, M, spli
     else:
         want |= {(0, k, n, 0) for (k, n) in real}
     assert len(jobs) == len(want) and set(jobs) == want
+    fine_of = {(j[1], j[2] + i): j for j in jobs if j[0] == 1 for i in range(j[3])}
     pos = {j: i for i, j in enumerate(jobs)}
     for j in jobs:
-        for d in _deps(j, K, groups, is_split):
+        for d in _deps(j, K, groups, is_split, fine_of):
             assert pos[d] < pos[j], (j, d)
     # ticket scheduling with W workers: each takes the next job and waits for
     # its dependencies (durations in nonlinear evaluations)
@@ -101,10 +117,68 @@ def test_pipeline_schedule_is_topological_and_drains(L, N, T, Ns, K, dt, M, spli
         end = {}
         for j in jobs:
             w = min(range(W), key=lambda i: free[i])
-            start = max([free[w]] + [end[d] for d in _deps(j, K, groups, is_split)])
+            start = max([free[w]] + [end[d] for d in _deps(j, K, groups, is_split, fine_of)])
             end[j] = start + dur[j[0]]
             free[w] = end[j]
         assert max(end.values()) <= sum(dur[j[0]] for j in jobs) + 1e-9
+
+
+@pytest.mark.parametrize("seed,split,fg,calibrated", [(0, 1, 64, False), (1, 1, 64, True), (2, 0, 64, True),
+                                                      (3, 1, 1, True), (4, -1, 3, False)])
+def test_batch_schedule_is_topological_and_drains(L, seed, split, fg, calibrated):
+    # several problems of uneven shape in one launch, with grouped fine jobs and
+    # (as after autotuning) measured job durations: every job after the jobs it
+    # depends on, and the ticket order drains with 1, 7 or 256 workgroups
+    import random
+    rng = random.Random(seed)
+    probs, cost = [], []
+    for _ in range(rng.randint(2, 24)):
+        N = rng.choice([64, 128, 256, 512, 1024])
+        Ns, K = rng.randint(1, 60), rng.randint(0, 8)
+        probs.append((N, rng.uniform(0.05, 2.0), Ns, K, rng.uniform(1e-4, 1e-2), rng.randint(2, 64)))
+        cost.append((rng.uniform(1, 10), rng.uniform(3, 15), rng.uniform(3, 15), rng.uniform(10, 100)))
+    jobs = binding.pipeline_schedule_batch(probs, split=split, fine_group=fg, cost=cost if calibrated else None)
+    meta = []
+    for (N, T, Ns, K, dt, M) in probs:
+        gs = max(1, 8 * (64 // (8 if N <= 64 else 16 if N <= 128 else 32 if N <= 256 else 64)) // 3)
+        groups = (M - 1 + gs - 1) // gs
+        meta.append((K, groups, (groups >= 2) if split < 0 else bool(split), min(fg, _FINE_MAX[N]), Ns))
+    for i, (K, groups, is_split, J, Ns) in enumerate(meta):
+        mine = [j[1:] for j in jobs if j[0] == i]
+        fine = {(k, n + x) for (t, k, n, g) in mine if t == 1 for x in range(g)}
+        assert fine == {(k, n) for k in range(K) for n in range(k + 1, Ns + 1)}
+        assert all(g <= J for (t, k, n, g) in mine if t == 1)
+    fine_of = [{} for _ in probs]
+    for j in jobs:
+        if j[1] == 1:
+            for x in range(j[4]):
+                fine_of[j[0]][(j[2], j[3] + x)] = j[1:]
+    pos = {j: i for i, j in enumerate(jobs)}
+    dep = {}
+    for j in jobs:
+        K, groups, is_split, _, _ = meta[j[0]]
+        dep[j] = [(j[0],) + d for d in _deps(j[1:], K, groups, is_split, fine_of[j[0]])]
+        for d in dep[j]:
+            assert pos[d] < pos[j], (j, d)
+
+    def deps(j):
+        return dep[j]
+    dur = {0: 20, 1: 40, 2: 5, 3: 5, 4: 0.1}
+    for W in (1, 7, 256):
+        free = [0.0] * W
+        end = {}
+        for j in jobs:
+            w = min(range(W), key=lambda i: free[i])
+            start = max([free[w]] + [end[d] for d in deps(j)])
+            end[j] = start + dur[j[1]]
+            free[w] = end[j]
+        assert max(end.values()) <= sum(dur[j[1]] for j in jobs) + 1e-9
+
+
+def test_pipeline_schedule_rejects_bad_fine_group(L):
+    p = binding.SolveParams(1.0, 4, 2, 0.01, 8, 0.0, 0.0, 0)
+    for fg in (0, -1, 65):
+        assert L.aparareal_pipeline_schedule(256, ctypes.byref(p), -1, 0, fg, None, 0) == -1
 
 
 def test_batch_and_options_reject_bad_arguments(L):
@@ -140,8 +214,8 @@ def test_serving_rejects_bad_arguments(L):
 def test_counted_work_matches_the_jobs_run(L, Ns, K):
     # the benchmark counts fine slices and coarse steps actually computed
     from paper_1303_6615_amd import metrics
-    jobs = binding.pipeline_schedule(256, 1.0, Ns, K, 0.001, 32, split=0)
-    fine = sum(1 for j in jobs if j[0] == 1)
+    jobs = binding.pipeline_schedule(256, 1.0, Ns, K, 0.001, 32, split=0, fine_group=4)
+    fine = sum(j[3] for j in jobs if j[0] == 1)
     coarse = sum(1 for j in jobs if j[0] == 0)
     gp, flops = metrics.pipelined_work(256, Ns, K, 7, 32)
     assert gp == fine * 7 * 256

@@ -89,6 +89,39 @@ def test_fine_batch(torch_cuda, n, eps, dT, steps, prec, tol):
     assert _rel(got, ref) < tol
 
 
+@pytest.mark.parametrize("n,prec,strang", [(64, FP64, False), (128, FP32, False), (256, FP32, False),
+                                            (256, FP32, True), (512, FP64, False)])
+def test_fine_batch_slices_stepped_together_equal_alone(torch_cuda, n, prec, strang):
+    # a workgroup steps several slices at once (16, 10, 5, 2 for N = 64 .. 512);
+    # each rounds exactly as alone, whatever the batch and its ragged last group
+    torch = torch_cuda
+    nu = NU_BY_NX[n]
+    u = torch.tensor(_states(n, 13, 11 * n), device="cuda")
+    with _ctx(n, 0.01, nu) as ctx:
+        run = (lambda x: ctx.strang_batch(x, 0.01, 3, precision=prec)) if strang else \
+              (lambda x: ctx.fine_batch(x, 0.01, 3, precision=prec))
+        together = run(u)
+        alone = torch.cat([run(u[i:i + 1]) for i in range(u.shape[0])])
+    assert torch.equal(together, alone)
+
+
+@pytest.mark.parametrize("cfg,prec,fine_kind", [(C1, FP64, 0), (C2, FP32, 0), (C2, FP32, 1)])
+def test_grouped_fine_jobs_change_no_value(torch_cuda, cfg, prec, fine_kind):
+    # fine jobs of the pipelined solve over up to 16 / 5 consecutive slices
+    # (AP_OPT_FINE_GROUP) give the single-slice results bitwise
+    from paper_1303_6615_amd.binding import AP_OPT_FINE, AP_OPT_FINE_GROUP
+    torch = torch_cuda
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        ctx.set_option(AP_OPT_FINE, fine_kind)
+        ctx.set_option(AP_OPT_FINE_GROUP, 1)
+        U1, r1 = _solve(ctx, torch, cfg, prec)
+        U1, r1 = U1.clone(), r1.clone()
+        for fg in (3, 64):
+            ctx.set_option(AP_OPT_FINE_GROUP, fg)
+            Ug, rg = _solve(ctx, torch, cfg, prec)
+            assert torch.equal(U1, Ug) and torch.equal(r1, rg), fg
+
+
 @pytest.mark.parametrize("n,T0,M,prec,tol", [
     (64, 6.25, 16, FP64, 1e-12),
     (256, 3.125, 32, FP64, 1e-12),
