@@ -46,10 +46,53 @@ def parse():
                          "whole replay, boundary kernels included)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the schedule autotuner (analytic job durations, default mapping)")
+    ap.add_argument("--fine-batch", type=int, default=5120,
+                    help="slices of the fine-batch throughput measurement (0 skips it)")
+    ap.add_argument("--fine-batch-only", action="store_true",
+                    help="only run the fine-batch throughput measurement and print its object")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def fine_batch_measure(slices):
+    """Throughput form of the fine propagator: one aparareal_fine_batch launch
+    over `slices` independent N = 256 FP32 slices of the C2 shape (63 ETDRK4
+    steps each), timed on the fine kernel alone with HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_1303_6615_amd import metrics
+    from paper_1303_6615_amd.binding import Context
+    from paper_1303_6615_amd.inputs import C2, seeded_state
+
+    cfg = C2
+    dT = cfg.T / cfg.slices
+    u = np.stack([seeded_state(cfg.nx, cfg.k_ic, 1000 + i) for i in range(min(slices, 64))])
+    u = torch.tensor(np.resize(u, (slices, 3, cfg.nx)), device="cuda")
+    out = torch.empty_like(u)
+    with Context(cfg.nx, cfg.eps, cfg.F, cfg.nu) as ctx:
+        ctx.fine_batch(u, dT, cfg.fine_steps, precision=0, out=out)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(3):
+            ctx.fine_batch(u, dT, cfg.fine_steps, precision=0, out=out)
+        torch.cuda.synchronize()
+        n, ms = ctx.profile_read()["fine"]
+        ctx.profile(False)
+    if not torch.isfinite(out).all():
+        raise SystemExit("non-finite fine batch")
+    avg_s = ms / n * 1e-3
+    gp = slices * cfg.fine_steps * cfg.nx
+    flops = metrics.fine_flops(cfg.nx, slices, cfg.fine_steps)
+    return {"workload": f"rsw-n256-eps1e-2 fine batch, {slices} slices x {cfg.fine_steps} ETDRK4 steps, fp32",
+            "kernel": "k_fine<float,256>", "avg_launch_ms": round(avg_s * 1e3, 4),
+            "value": round(gp / avg_s, 1), "unit": "fine grid-point-steps/s",
+            "roofline": {"bound": "alu", "achieved": round(flops / avg_s / 1e12, 4),
+                         "peak": metrics.PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(flops / avg_s / 1e12 / metrics.PEAK_FP32_TFLOPS, 4),
+                         "frac_of_unpacked_fp32": round(flops / avg_s / 1e12 / metrics.PEAK_FP32_NOPACK_TFLOPS, 4)}}
 
 
 def cpu_baseline(cfg):
@@ -117,6 +160,9 @@ def main():
     if args.copy_mib:
         copy_probe(args.copy_mib)
         return
+    if args.fine_batch_only:
+        print(json.dumps({"fine_batch": fine_batch_measure(args.fine_batch or 5120)}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the parallel-in-time "
               "dimension is the batch dimension of the single-GPU kernels.", file=sys.stderr)
@@ -183,6 +229,8 @@ def main():
         "final_residual": W["final_residual"](),
         "autotune": W["autotune"],
     }
+    if args.fine_batch > 0:
+        line["fine_batch"] = fine_batch_measure(args.fine_batch)
     if args.serve_requests > 0:
         from paper_1303_6615_amd import serving
         line["serving"] = serving.run(n_requests=args.serve_requests, warmup=8)
