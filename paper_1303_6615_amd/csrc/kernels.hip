@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(NT) k_to_modal(const double* __restrict__ phys
   using G = Geo<NX>;
   using T = double;
   constexpr int P = G::P;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* a = tw + NX;
   cx<T>* b = a + 3 * P;
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(NT) k_to_physical(const cx<double>* __restrict
   using G = Geo<NX>;
   using T = double;
   constexpr int P = G::P;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   // spec [3][P+1] shares the second FFT buffer: it is dead once the
   // pre-processed spectra are in `a`.
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -128,7 +128,7 @@ template <typename T, int NX, int NT>
 __global__ void __launch_bounds__(NT) k_nonlinear(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Nout,
                                                   const cx<T>* __restrict__ tw, const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, 1>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   E_ en(smem_raw, tw);
   const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * E_::KP;
   cx<double>* dst = Nout + size_t(blockIdx.x) * 3 * E_::KP;
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(NT) k_fine(const cx<double>* __restrict__ Uin,
                                              const Basis<T>* __restrict__ basis) {
   constexpr int S = fine_slots<T, NX, NT>();
   using E_ = Engine<T, NX, NT, S>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   E_ en(smem_raw, tw);
   const size_t st = size_t(3) * E_::KP;
   const int first = blockIdx.x * E_::jmax();
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(NT) k_strang(const cx<double>* __restrict__ Ui
                                                const cx<T>* __restrict__ tw, const Basis<T>* __restrict__ basis) {
   constexpr int S = fine_slots<T, NX, NT>();
   using E_ = Engine<T, NX, NT, S>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   E_ en(smem_raw, tw);
   const size_t st = size_t(3) * E_::KP;
   const int first = blockIdx.x * E_::jmax();
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(NT) k_average(const cx<double>* __restrict__ U
                                                 AvgTab<T> av, const cx<T>* __restrict__ tw,
                                                 const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, S>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   E_ en(smem_raw, tw);
   const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * E_::KP;
   cx<double>* dst = Nout + size_t(blockIdx.x) * 3 * E_::KP;
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(NT) k_coarse(const cx<double>* __restrict__ Ui
                                                CoarseTab<T> ct, const cx<T>* __restrict__ tw,
                                                const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, S>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   E_ en(smem_raw, tw);
   const size_t st = size_t(3) * E_::KP;
   cx<double>* o = Uout + blockIdx.x * st;
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(NT) k_sweep(cx<double>* __restrict__ U, const 
                                               int initial, CoarseTab<T> ct, const cx<T>* __restrict__ tw,
                                               const Basis<T>* __restrict__ basis) {
   using E_ = Engine<T, NX, NT, S>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   E_ en(smem_raw, tw);
   const size_t st = size_t(3) * E_::KP;
   for (int n = 1; n <= Ns; ++n) {

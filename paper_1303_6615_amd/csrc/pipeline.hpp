@@ -264,7 +264,7 @@ template <typename T, int... NXS>
 __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __restrict__ jobs, int njobs,
                                                            const PipeProb<T>* __restrict__ probs, int* ticket,
                                                            int* abort, int* progress, unsigned long long* trace) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_job, s_ok, s_flag, s_skip;
   // Thread 0's scheduling work (publish the previous job's counter, take a
   // ticket, wait on the new job's dependencies) is one region at the top of

@@ -20,8 +20,12 @@
 
 namespace ap {
 
+// Complex value aligned to its size, so that LDS and global accesses are
+// single 64-bit (float) or 128-bit (double) operations.  Two 32-bit LDS
+// accesses to consecutive complex floats would map lanes i and i + 32 to one
+// bank; a 64-bit access serves 32 lanes per cycle across all 64 banks.
 template <typename T>
-struct cx {
+struct alignas(2 * sizeof(T)) cx {
   T x, y;
 };
 
