@@ -24,22 +24,31 @@
 
 namespace ap {
 
-// Fine batches: for N <= 256 a 512-thread workgroup steps several slices
-// together (Engine::jmax: 16, 10, 5 for N = 64, 128, 256), with two slots per
-// slice; larger grids run one slice per workgroup of just enough threads to
-// own one mode each, with two slots.
-template <int NX>
+// Fine batches: workgroups small enough that several share a CU (VGPRs and
+// LDS permitting), each stepping as many slices as its threads own modes
+// and its wavefronts transform in one round (Engine::jmax), with two slots
+// per slice.  Threads per workgroup by precision and grid size, measured on
+// MI355X over 5120-slice batches (FP32: 128 / 192 / 192 / 256 / 384 / 704
+// for N = 64 .. 2048; FP64: 256 / 256 / 512 / 384 / 384 / 704).
+template <typename T, int NX>
 constexpr int fine_threads() {
-  return NX <= 256 ? 512 : NX == 512 ? 192 : NX == 1024 ? 384 : 704;
+  if constexpr (sizeof(T) == 4) return NX == 64 ? 128 : NX <= 256 ? 192 : NX == 512 ? 256 : NX == 1024 ? 384 : 704;
+  else return NX <= 128 ? 256 : NX == 256 ? 512 : NX <= 1024 ? 384 : 704;
 }
 template <typename T, int NX, int NT>
 constexpr int fine_slots() {
-  if constexpr (NX <= 256) return max_slots<T, NX, NT>();
-  return max_slots<T, NX, NT>() >= 2 ? 2 : 1;
+  constexpr int KP = Geo<NX>::KP;
+  constexpr int MPT = (KP + NT - 1) / NT;
+  int j = MPT > 1 ? 1 : NT / KP;
+  const int by_waves = (NT / 64) * (64 / WavePlan<NX / 2>::G) / 3;
+  j = j < by_waves ? j : by_waves;
+  j = j < 16 ? (j > 0 ? j : 1) : 16;
+  const int s = max_slots<T, NX, NT>();
+  return 2 * j < s ? 2 * j : s;
 }
 template <typename T, int NX>
 constexpr int fine_slices() {
-  return Engine<T, NX, fine_threads<NX>(), fine_slots<T, NX, fine_threads<NX>()>()>::jmax();
+  return Engine<T, NX, fine_threads<T, NX>(), fine_slots<T, NX, fine_threads<T, NX>()>()>::jmax();
 }
 // ------------------------------------------------- boundary transforms -----
 // physical [B][3][N] float64 -> modal [B][3][KP] complex float64 (projected)
@@ -318,7 +327,7 @@ static hipError_t to_physical_nx(const cx<double>* modal, double* phys, int batc
 
 template <typename T, int NX>
 static hipError_t nonlinear_nx(const cx<double>* in, cx<double>* out, int batch, const DevTables& t, hipStream_t s) {
-  constexpr int NT = fine_threads<NX>();
+  constexpr int NT = fine_threads<T, NX>();
   const size_t lds = Engine<T, NX, NT, 1>::lds_bytes();
   prep_lds(k_nonlinear<T, NX, NT>, lds);
   hipLaunchKernelGGL((k_nonlinear<T, NX, NT>), dim3(batch), dim3(NT), lds, s, in, out, t.tw<T>(), t.basis<T>());
@@ -328,7 +337,7 @@ static hipError_t nonlinear_nx(const cx<double>* in, cx<double>* out, int batch,
 template <typename T, int NX>
 static hipError_t fine_nx(const cx<double>* in, cx<double>* out, int batch, int steps, const cx<double>* coef64,
                           const cx<T>* coef, const DevTables& t, hipStream_t s) {
-  constexpr int NT = fine_threads<NX>();
+  constexpr int NT = fine_threads<T, NX>();
   const size_t lds = Engine<T, NX, NT, fine_slots<T, NX, NT>()>::lds_bytes();
   const int J = fine_slices<T, NX>();
   prep_lds(k_fine<T, NX, NT>, lds);
@@ -340,7 +349,7 @@ static hipError_t fine_nx(const cx<double>* in, cx<double>* out, int batch, int 
 template <typename T, int NX>
 static hipError_t strang_nx(const cx<double>* in, cx<double>* out, int batch, int steps, double h,
                             const cx<double>* coef64, const DevTables& t, hipStream_t s) {
-  constexpr int NT = fine_threads<NX>();
+  constexpr int NT = fine_threads<T, NX>();
   const size_t lds = Engine<T, NX, NT, fine_slots<T, NX, NT>()>::lds_bytes();
   const int J = fine_slices<T, NX>();
   prep_lds(k_strang<T, NX, NT>, lds);
