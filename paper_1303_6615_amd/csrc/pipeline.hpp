@@ -27,7 +27,8 @@ namespace ap {
 // long before their inputs exist).
 constexpr unsigned long long kStallTicks = 100000000ull;
 
-// Thread 0 waits for *ctr >= target (relaxed polls, then an acquire fence).
+// Thread 0 waits for *ctr >= target (relaxed polls, then an agent-scope
+// acquire fence: the producers are on this device).
 // On a stall it records (1, job, counter index) in diag[0..2] and returns
 // false; it also returns false once another workgroup has recorded one.
 // Every waiting workgroup polls, so the words all of them share (the stall
@@ -59,9 +60,14 @@ __device__ __forceinline__ bool wait_count(int* ctr, int target, int* diag, int 
     }
     __builtin_amdgcn_s_sleep(2);
   }
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
+
+// This wavefront's global stores have completed at the L2 (vector memory
+// counter at zero); the memory clobber keeps the compiler from moving stores
+// past it.
+__device__ __forceinline__ void wait_global_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Counter indices of one problem.
 struct PipeIdx {
@@ -216,15 +222,18 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
     return ix.stage1(k, n);
   }
   stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 2, jb.g, p.P1 + lvl, p.groups, p.P2 + lvl + jb.g * st, w, cr);
-  // Count this group in; the last group to arrive finishes the step.
+  // Count this group in; the last group to arrive finishes the step.  Every
+  // wavefront first waits for its stores of the group sum to reach the L2
+  // (a workgroup barrier waits only for LDS); thread 0's release then writes
+  // them back for the other XCDs.
+  wait_global_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
     const int before = __hip_atomic_fetch_add(&p.cnt[ix.stage2(k, n)], 1, __ATOMIC_ACQ_REL,
                                               __HIP_MEMORY_SCOPE_AGENT);
     int flag = 0;
     if (before == p.groups - 1) {
-      __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       bool ok = true;
       if (k >= 1) {
         ok = wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n));
@@ -280,7 +289,7 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
   for (;;) {
     if (threadIdx.x == 0) {
       if (pub >= 0) {
-        __threadfence();
+        // the job's stores were released by every wavefront before the barrier
         for (int i = 0; i < npub; ++i)
           __hip_atomic_fetch_add(&pub_cnt[pub + i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(abort + 3, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -317,6 +326,11 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
         dispatch_job<T, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip, np));
     npub = __builtin_amdgcn_readfirstlane(np);
     pub_cnt = p.cnt;
+    // Every wavefront waits for its stores of the job's results to reach the
+    // L2 before the barrier after which thread 0 publishes the job's counters
+    // (the barrier alone waits only for LDS); thread 0's release atomic then
+    // writes them back to the memory the other XCDs read.
+    wait_global_stores();
     __syncthreads();
     if (trace && threadIdx.x == 0) trace[3 * j + 1] = wall_clock64();
   }
