@@ -122,6 +122,25 @@ constexpr size_t pipe_lds() {
   return Engine<T, NX, kPipeThreads, pipe_slots<T, NX>()>::lds_bytes();
 }
 
+// The fine slices of a job, called rather than inlined: one call per job (a
+// job steps for hundreds of microseconds, so the call costs nothing
+// measurable), and the stepping loop gets a register allocation of its own
+// instead of sharing one with every other job type (and, in a kernel for
+// several grid sizes, with every other size).  The caller has staged the
+// twiddles.
+template <typename T, int NX, int JM>
+__device__ __attribute__((noinline)) void fine_slices_job(unsigned char* smem, const cx<T>* tw, int kind, int J,
+                                                          const cx<double>* src0, const cx<double>* src1,
+                                                          cx<double>* dst, int steps, const cx<double>* coef64,
+                                                          const cx<T>* coef, double hf, const Basis<T>* basis) {
+  using E_ = Engine<T, NX, kPipeThreads, pipe_slots<T, NX>()>;
+  E_ en(smem, tw, false);
+  if (kind == 1)
+    strang_job<T, NX, kPipeThreads, pipe_slots<T, NX>(), JM>(en, J, src0, src1, dst, steps, coef64, hf, basis);
+  else
+    fine_job<T, NX, kPipeThreads, pipe_slots<T, NX>(), JM>(en, J, src0, src1, dst, steps, coef64, coef, basis);
+}
+
 // Runs job jb of problem p (grid size NX) in this workgroup.  Returns the
 // counter index to publish when the job's results are complete, or -1.
 // `staged` tracks the twiddle table held in LDS across jobs.
@@ -174,17 +193,12 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
     // slice n reads uprev, slices n + s (s >= 1) read U(k, n + s - 1), stored in order from U(k, n)
     const cx<double>* src1 = state(p.U, k, n);
     cx<double>* dst = state(p.F, k, n);
-    if (p.fine_kind == 1) {
-      if (J == 1)
-        strang_job<T, NX, NT, S, 1>(en, 1, uprev, src1, dst, p.steps, p.coef64, p.hf, p.basis);
-      else
-        strang_job<T, NX, NT, S>(en, J, uprev, src1, dst, p.steps, p.coef64, p.hf, p.basis);
-    } else {
-      if (J == 1)
-        fine_job<T, NX, NT, S, 1>(en, 1, uprev, src1, dst, p.steps, p.coef64, p.coef, p.basis);
-      else
-        fine_job<T, NX, NT, S>(en, J, uprev, src1, dst, p.steps, p.coef64, p.coef, p.basis);
-    }
+    if (J == 1)
+      fine_slices_job<T, NX, 1>(smem, p.tw, p.fine_kind, 1, uprev, src1, dst, p.steps, p.coef64, p.coef, p.hf,
+                                p.basis);
+    else
+      fine_slices_job<T, NX, 0>(smem, p.tw, p.fine_kind, J, uprev, src1, dst, p.steps, p.coef64, p.coef, p.hf,
+                                p.basis);
     return ix.fine(k, n);
   }
   if (jb.type == kJobCopy) {
