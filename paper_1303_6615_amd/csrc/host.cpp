@@ -874,7 +874,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
       const auto* b = reinterpret_cast<const unsigned char*>(&pr);
       probs.insert(probs.end(), b, b + sizeof(pr));
     }
-    const int* stop = it.q.tol > 0.0 ? cnt + (ap::pipe_counters(it.q.Ns, it.q.K) - 1) : nullptr;
+    const int* stop = it.q.tol > 0.0 ? cnt + ap::pipe_stop_index(it.q.Ns, it.q.K) : nullptr;
     for (int k = 0; k < it.q.K; ++k)
       rows.push_back({it.c->pp_part.as<double2>() + size_t(k) * it.q.Ns, it.resid + k, stop, it.q.Ns, k + 1});
   }
@@ -924,9 +924,10 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     long long foff = 0;
     for (auto& it : items) {
       ap_ctx* c = it.c;
+      const int* stop = flags + foff + ap::pipe_stop_index(it.q.Ns, it.q.K);
       foff += ap::pipe_counters(it.q.Ns, it.q.K);
       if (it.q.tol > 0.0 && it.q.K > 1 &&
-          (err = ap::launch_select_level(c->pp_U.as<cx<double>>(), it.q.Ns, it.q.K, c->KP, flags + foff - 1, st)) !=
+          (err = ap::launch_select_level(c->pp_U.as<cx<double>>(), it.q.Ns, it.q.K, c->KP, stop, st)) !=
               hipSuccess)
         return hip_fail(err, "level selection");
       const cx<double>* UK = c->pp_U.as<cx<double>>() + size_t(it.q.K) * (it.q.Ns + 1) * 3 * c->KP;

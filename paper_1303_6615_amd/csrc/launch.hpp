@@ -57,13 +57,17 @@ struct PipeJob {
   int prob, type, k, n, g;
 };
 
-// Counter layout of one problem (int32, zeroed before the launch):
+// Counter layout of one problem (int32, zeroed before the launch), in units
+// of kCounterStride ints: every counter has a 128-byte line of its own, so
+// that workgroups polling different counters do not queue on one line.
 //   C(k,n) done     at             k Ns + n-1   (k = 0..K)
 //   F(k,n) done     at (K+1) Ns +  k Ns + n-1   (k = 0..K-1)
 //   stage-1 count   at (2K+1) Ns + k Ns + n-1   (k = 0..K)
 //   stage-2 count   at (3K+2) Ns + k Ns + n-1   (k = 0..K)
 //   stopped level   at (4K+3) Ns                (0: running; k: residual r^k <= tol)
-inline long long pipe_counters(int Ns, int K) { return (4LL * K + 3) * Ns + 1; }
+constexpr int kCounterStride = 32;
+inline long long pipe_counters(int Ns, int K) { return ((4LL * K + 3) * Ns + 1) * kCounterStride; }
+inline long long pipe_stop_index(int Ns, int K) { return (4LL * K + 3) * Ns * kCounterStride; }
 
 // Per-problem device descriptor of the pipelined solve.
 template <typename T>

@@ -69,14 +69,15 @@ __device__ __forceinline__ bool wait_count(int* ctr, int target, int* diag, int 
 // past it.
 __device__ __forceinline__ void wait_global_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Counter indices of one problem.
+// Counter indices of one problem (layout in launch.hpp; consecutive slices'
+// counters are kCounterStride apart).
 struct PipeIdx {
   int Ns, K;
-  __device__ int coarse(int k, int n) const { return k * Ns + n - 1; }
-  __device__ int fine(int k, int n) const { return (K + 1) * Ns + k * Ns + n - 1; }
-  __device__ int stage1(int k, int n) const { return (2 * K + 1) * Ns + k * Ns + n - 1; }
-  __device__ int stage2(int k, int n) const { return (3 * K + 2) * Ns + k * Ns + n - 1; }
-  __device__ int stopped() const { return (4 * K + 3) * Ns; }
+  __device__ int coarse(int k, int n) const { return (k * Ns + n - 1) * kCounterStride; }
+  __device__ int fine(int k, int n) const { return ((K + 1) * Ns + k * Ns + n - 1) * kCounterStride; }
+  __device__ int stage1(int k, int n) const { return ((2 * K + 1) * Ns + k * Ns + n - 1) * kCounterStride; }
+  __device__ int stage2(int k, int n) const { return ((3 * K + 2) * Ns + k * Ns + n - 1) * kCounterStride; }
+  __device__ int stopped() const { return (4 * K + 3) * Ns * kCounterStride; }
 };
 
 // The job's level lies past the level at which its problem stopped (the
@@ -297,7 +298,7 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
   // it, which the compiler may turn into a loop the other lanes never leave.
   // The values read back from LDS are made uniform with readfirstlane.
   int pub = -1;                 // first counter index of the job finished last
-  int npub = 1;                 // consecutive counters it publishes
+  int npub = 1;                 // counters it publishes (consecutive slices, kCounterStride apart)
   int* pub_cnt = nullptr;
   const void* staged = nullptr;
   for (;;) {
@@ -305,7 +306,7 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
       if (pub >= 0) {
         // the job's stores were released by every wavefront before the barrier
         for (int i = 0; i < npub; ++i)
-          __hip_atomic_fetch_add(&pub_cnt[pub + i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(&pub_cnt[pub + i * kCounterStride], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(abort + 3, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (progress) {
           progress[2 * blockIdx.x] += 1;

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/aparareal.h"
+#include "launch.hpp"
 
 namespace aplib {
 void set_last_error(const std::string& msg);   // host.cpp: the message of aparareal_last_error
@@ -46,7 +47,7 @@ size_t footprint(int N, const ap_solve_params& p) {
   const size_t gs_bytes = p.precision == AP_PREC_FP64 ? 16 : 8;
   size_t b = st * (Ns + 1) * (2 * (K + 1) + std::max<size_t>(K, 1));
   b += 2 * (K + 1) * size_t(p.M_avg) * 3 * KP * gs_bytes;       // group sums (groups <= M)
-  b += (4 * K + 3) * Ns * 4 + K * Ns * 16;                       // counters, residual parts
+  b += size_t(ap::pipe_counters(int(Ns), int(K))) * 4 + K * Ns * 16;   // counters, residual parts
   b += 2 * 8 * 3 * KP * 16 + size_t(p.M_avg) * KP * 24 + KP * 64; // tables
   b += 3 * size_t(N) * 8 * (Ns + 2) + K * 8;                     // u0, U_out, resid
   b += ((2 * K + 1) * Ns * size_t(2 * p.M_avg + 1)) * 20;       // job list
