@@ -27,8 +27,17 @@ namespace ap {
 // long before their inputs exist).
 constexpr unsigned long long kStallTicks = 100000000ull;
 
+// Agent-scope acquire by thread 0 on behalf of its workgroup: the cache
+// invalidation it issues must complete before the barrier after which the
+// other wavefronts read the producers' data (the fence alone orders only this
+// wavefront's later loads).
+__device__ __forceinline__ void acquire_for_workgroup() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // Thread 0 waits for *ctr >= target (relaxed polls, then an agent-scope
-// acquire fence: the producers are on this device).
+// acquire for the workgroup: the producers are on this device).
 // On a stall it records (1, job, counter index) in diag[0..2] and returns
 // false; it also returns false once another workgroup has recorded one.
 // Every waiting workgroup polls, so the words all of them share (the stall
@@ -60,7 +69,7 @@ __device__ __forceinline__ bool wait_count(int* ctr, int target, int* diag, int 
     }
     __builtin_amdgcn_s_sleep(2);
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  acquire_for_workgroup();
   return true;
 }
 
@@ -248,7 +257,7 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
                                               __HIP_MEMORY_SCOPE_AGENT);
     int flag = 0;
     if (before == p.groups - 1) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      acquire_for_workgroup();
       bool ok = true;
       if (k >= 1) {
         ok = wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n));
