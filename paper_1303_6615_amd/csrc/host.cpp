@@ -1037,7 +1037,7 @@ ap_ctx* aparareal_create(int N, double eps, double F, double nu) {
   };
   for (int t = 0; t < N; ++t) push(2.0 * M_PI * double(t) / double(N));
   {
-    int r[3], npass = 0;
+    int r[4], npass = 0;
     ap::wave_plan_radices(N / 2, r, &npass);
     int NS = r[0];
     for (int j = 1; j < npass; ++j) {

@@ -85,38 +85,48 @@ __device__ __forceinline__ void dft_reg(cx<T> (&x)[R]) {
 }
 
 // Plan per transform length: G lanes per signal (64/G signals share a
-// wavefront) and radices R0, R1[, R2] with product P, chosen so that every
-// pass has about G butterflies.
+// wavefront) and n passes of radices r0 .. r3 with product P.  Every pass has
+// at least G butterflies where the length allows it (P >= 128): a pass with
+// fewer leaves lanes repeating butterflies, so radix-4 passes (and one radix-2
+// pass) beat fewer passes of radix 8.
 template <int P> struct WavePlan;
-template <> struct WavePlan<32>   { static constexpr int G = 8,  n = 2, r0 = 4,  r1 = 8, r2 = 1; };
-template <> struct WavePlan<64>   { static constexpr int G = 16, n = 3, r0 = 4,  r1 = 4, r2 = 4; };
-template <> struct WavePlan<128>  { static constexpr int G = 32, n = 3, r0 = 4,  r1 = 4, r2 = 8; };
-template <> struct WavePlan<256>  { static constexpr int G = 64, n = 3, r0 = 4,  r1 = 8, r2 = 8; };
-template <> struct WavePlan<512>  { static constexpr int G = 64, n = 3, r0 = 8,  r1 = 8, r2 = 8; };
-template <> struct WavePlan<1024> { static constexpr int G = 64, n = 3, r0 = 16, r1 = 8, r2 = 8; };
+template <> struct WavePlan<32>   { static constexpr int G = 8,  n = 2, r0 = 4,  r1 = 8, r2 = 1, r3 = 1; };
+template <> struct WavePlan<64>   { static constexpr int G = 16, n = 3, r0 = 4,  r1 = 4, r2 = 4, r3 = 1; };
+template <> struct WavePlan<128>  { static constexpr int G = 32, n = 4, r0 = 4,  r1 = 4, r2 = 4, r3 = 2; };
+template <> struct WavePlan<256>  { static constexpr int G = 64, n = 4, r0 = 4,  r1 = 4, r2 = 4, r3 = 4; };
+template <> struct WavePlan<512>  { static constexpr int G = 64, n = 3, r0 = 8,  r1 = 8, r2 = 8, r3 = 1; };
+template <> struct WavePlan<1024> { static constexpr int G = 64, n = 3, r0 = 16, r1 = 8, r2 = 8, r3 = 1; };
 
 // Twiddle table of a grid size N = 2P: entries t < N hold exp(-2 pi i t/N)
-// (real-signal pre/post-processing); then, for the passes after the first,
-// exp(-2 pi i q k / (NS R)) at [(q-1) NS + k] (q = 1..R-1, k < NS; NS points
-// combined before the pass, radix R), contiguous in k so that the lanes of a
-// pass read consecutive entries.
+// (real-signal pre/post-processing); then, for each pass j after the first,
+// exp(-2 pi i q k / (NS R)) at [offset_j + (q-1) NS + k] (q = 1..R-1, k < NS;
+// NS points combined before the pass, radix R), contiguous in k so that the
+// lanes of a pass read consecutive entries.
 template <int P>
 constexpr int pass1_tw_offset() { return 2 * P; }
 template <int P>
 constexpr int pass2_tw_offset() { return 2 * P + (WavePlan<P>::r1 - 1) * WavePlan<P>::r0; }
 template <int P>
+constexpr int pass3_tw_offset() {
+  using PL = WavePlan<P>;
+  return pass2_tw_offset<P>() + (PL::r2 - 1) * PL::r0 * PL::r1;
+}
+template <int P>
 constexpr int tw_elems() {
   using PL = WavePlan<P>;
-  return PL::n == 3 ? pass2_tw_offset<P>() + (PL::r2 - 1) * PL::r0 * PL::r1 : pass2_tw_offset<P>();
+  return PL::n == 4   ? pass3_tw_offset<P>() + (PL::r3 - 1) * PL::r0 * PL::r1 * PL::r2
+         : PL::n == 3 ? pass3_tw_offset<P>()
+                      : pass2_tw_offset<P>();
 }
 
 // The radices of the plan for transform length P (host side, for the tables).
-inline void wave_plan_radices(int P, int r[3], int* n) {
+inline void wave_plan_radices(int P, int r[4], int* n) {
+  r[3] = 1;
   switch (P) {
     case 32: r[0] = 4; r[1] = 8; r[2] = 1; *n = 2; return;
     case 64: r[0] = 4; r[1] = 4; r[2] = 4; *n = 3; return;
-    case 128: r[0] = 4; r[1] = 4; r[2] = 8; *n = 3; return;
-    case 256: r[0] = 4; r[1] = 8; r[2] = 8; *n = 3; return;
+    case 128: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 2; *n = 4; return;
+    case 256: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 4; *n = 4; return;
     case 512: r[0] = 8; r[1] = 8; r[2] = 8; *n = 3; return;
     default: r[0] = 16; r[1] = 8; r[2] = 8; *n = 3; return;
   }
@@ -153,9 +163,12 @@ template <typename T, int P>
 constexpr int swz_pass0() { return kSwzR; }
 template <typename T, int P>
 constexpr int swz_pass1() {
-  if constexpr (sizeof(T) == 4) return P <= 128 ? kSwzR5 : P == 256 ? kSwzR9 : kSwzRx2;
+  if constexpr (sizeof(T) == 4) return P <= 256 ? kSwzR5 : kSwzRx2;
   else return P <= 256 ? kSwzR5 : P == 512 ? kSwzRx1 : kSwzId;
 }
+// layout written by pass 2 of a four-pass plan (radix 4 after 16 points)
+template <typename T, int P>
+constexpr int swz_pass2() { return sizeof(T) == 4 ? kSwzR9 : kSwzR; }
 
 // Sources of a pass's inputs.  fetch(i) issues the LDS loads of input i
 // (returning raw values), make(raw) forms the input from them; a pass issues
@@ -288,11 +301,19 @@ __device__ __forceinline__ void wave_fft(cx<T>* buf, const cx<T>* tw, int lig, c
   using PL = WavePlan<P>;
   constexpr bool PRE = tw_in_registers<T, P>();
   constexpr int S0 = swz_pass0<T, P>();
-  constexpr int S1 = PL::n == 3 ? swz_pass1<T, P>() : kSwzId;
+  constexpr int S1 = PL::n >= 3 ? swz_pass1<T, P>() : kSwzId;
   NoTw<T> none;
   PassTw<T, P, PL::r1, PL::r0, PL::G, pass1_tw_offset<P>(), PRE> w1;
   wave_pass<T, P, PL::r0, 1, DIR, PL::G, S0, PRE>(buf, tw, none, w1, lig, src);
-  if constexpr (PL::n == 3) {
+  if constexpr (PL::n == 4) {
+    constexpr int S2 = swz_pass2<T, P>();
+    constexpr int NS2 = PL::r0 * PL::r1, NS3 = NS2 * PL::r2;
+    PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P>(), PRE> w2;
+    PassTw<T, P, PL::r3, NS3, PL::G, pass3_tw_offset<P>(), PRE> w3;
+    wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
+    wave_pass<T, P, PL::r2, NS2, DIR, PL::G, S2, PRE>(buf, tw, w2, w3, lig, ReadLayout<T, S1>{buf});
+    wave_pass<T, P, PL::r3, NS3, DIR, PL::G, kSwzId, PRE>(buf, tw, w3, none, lig, ReadLayout<T, S2>{buf});
+  } else if constexpr (PL::n == 3) {
     PassTw<T, P, PL::r2, PL::r0 * PL::r1, PL::G, pass2_tw_offset<P>(), PRE> w2;
     wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
     wave_pass<T, P, PL::r2, PL::r0 * PL::r1, DIR, PL::G, kSwzId, PRE>(buf, tw, w2, none, lig, ReadLayout<T, S1>{buf});
