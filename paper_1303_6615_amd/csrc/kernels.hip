@@ -28,12 +28,12 @@ namespace ap {
 // LDS permitting), each stepping as many slices as its threads own modes
 // and its wavefronts transform in one round (Engine::jmax), with two slots
 // per slice.  Threads per workgroup by precision and grid size, measured on
-// MI355X over 5120-slice batches (FP32: 128 / 192 / 192 / 256 / 384 / 704
-// for N = 64 .. 2048; FP64: 256 / 256 / 512 / 384 / 384 / 704).
+// MI355X over 5120-slice batches (FP32: 128 / 192 / 192 / 192 / 384 / 704
+// for N = 64 .. 2048; FP64: 256 / 256 / 512 / 256 / 384 / 704).
 template <typename T, int NX>
 constexpr int fine_threads() {
-  if constexpr (sizeof(T) == 4) return NX == 64 ? 128 : NX <= 256 ? 192 : NX == 512 ? 256 : NX == 1024 ? 384 : 704;
-  else return NX <= 128 ? 256 : NX == 256 ? 512 : NX <= 1024 ? 384 : 704;
+  if constexpr (sizeof(T) == 4) return NX == 64 ? 128 : NX <= 512 ? 192 : NX == 1024 ? 384 : 704;
+  else return NX <= 128 ? 256 : NX == 256 ? 512 : NX == 512 ? 256 : NX == 1024 ? 384 : 704;
 }
 template <typename T, int NX, int NT>
 constexpr int fine_slots() {
