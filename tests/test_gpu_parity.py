@@ -378,9 +378,10 @@ def _serve_all(srv, reqs, precision=FP32):
 
 
 @pytest.mark.xfail(strict=False, reason=(
-    "open defect: a split-step N=512 solve occasionally reads a state from before its producer's write "
-    "(seen with workspaces poisoned by NaN bytes, about 1 solve in 80, always N=512 with split coarse steps); "
-    "the request's residuals at early levels then differ from its served solve"))
+    "open defect: with split coarse steps and only 1-2 fine steps per slice, a solve occasionally reads a "
+    "state from before its producer's write (workspaces poisoned with NaN bytes show it in 10 of 30 solves "
+    "at N=512, eps=0.1; never with whole coarse steps or 12+ fine steps per slice); the request's residuals "
+    "at early levels then differ from its served solve"))
 def test_serving_results_equal_alone_solves(torch_cuda):
     # requests of uneven N, eps, T and slices through the serving loop: each
     # result equals the same solve run alone (continuous batching changes only
