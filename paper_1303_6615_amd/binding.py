@@ -107,10 +107,10 @@ def lib() -> ctypes.CDLL:
 
 def pipeline_schedule(N: int, T: float, slices: int, K: int, dt_fine: float, M: int, split: int = -1,
                       group: int = 0, precision: int = AP_PREC_FP32,
-                      fine_group: int = 1) -> list[tuple[int, int, int, int]]:
+                      fine_group: int = 1, tol: float = 0.0) -> list[tuple[int, int, int, int]]:
     """Job order of the pipelined solve as (type, k, n, g) quadruples (host only);
     a fine job (type 1) covers slices n .. n + g - 1."""
-    p = SolveParams(float(T), int(slices), int(K), float(dt_fine), int(M), 0.0, 0.0, int(precision))
+    p = SolveParams(float(T), int(slices), int(K), float(dt_fine), int(M), 0.0, float(tol), int(precision))
     cnt = _check(lib().aparareal_pipeline_schedule(N, ctypes.byref(p), split, group, fine_group, None, 0))
     buf = (ctypes.c_int * (4 * max(cnt, 1)))()
     cnt = _check(lib().aparareal_pipeline_schedule(N, ctypes.byref(p), split, group, fine_group, buf, cnt))
@@ -120,12 +120,13 @@ def pipeline_schedule(N: int, T: float, slices: int, K: int, dt_fine: float, M: 
 def pipeline_schedule_batch(problems, split: int = -1, group: int = 0, fine_group: int = 1,
                             precision: int = AP_PREC_FP32, cost=None) -> list[tuple[int, int, int, int, int]]:
     """Job order of a batched pipelined launch (host only) as (prob, type, k, n, g)
-    quintuples; problems: (N, T, slices, K, dt_fine, M) tuples; cost: optional
+    quintuples; problems: (N, T, slices, K, dt_fine, M[, tol]) tuples; cost: optional
     per-problem (fine step, stage 1, stage 2, whole) durations in us."""
     cnt_p = len(problems)
     Ns = (ctypes.c_int * cnt_p)(*[int(q[0]) for q in problems])
-    ps = (SolveParams * cnt_p)(*[SolveParams(float(q[1]), int(q[2]), int(q[3]), float(q[4]), int(q[5]), 0.0, 0.0,
-                                             int(precision)) for q in problems])
+    ps = (SolveParams * cnt_p)(*[SolveParams(float(q[1]), int(q[2]), int(q[3]), float(q[4]), int(q[5]), 0.0,
+                                             float(q[6]) if len(q) > 6 else 0.0, int(precision))
+                                 for q in problems])
     cs = None
     if cost is not None:
         cs = (ctypes.c_double * (4 * cnt_p))(*[float(v) for row in cost for v in row])

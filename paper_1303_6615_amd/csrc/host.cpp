@@ -546,12 +546,20 @@ double problem_jobs(int prob, const PipeShape& q, std::vector<SchedItem>& out) {
   auto T2 = [&](int k, int n) -> double& { return dT2[size_t(k) * Ns + n - 1]; };   // latest time of C(k,n)'s jobs
   const double inf = std::numeric_limits<double>::infinity();
   const size_t first = out.size();
+  // With a tolerance the job completing C(k, Ns) also waits for the copy jobs
+  // of level k (it reads their residual parts): it is placed after them.
+  auto after_copies = [&](int k, int n, double t) {
+    if (!(q.tol > 0.0) || !q.skip || k < 1 || n != Ns) return t;
+    for (int m = 1; m <= std::min(k, Ns - 1); ++m) t = std::max(t, std::nextafter(T2(k, m), inf));
+    return t;
+  };
   for (int k = 0; k <= K; ++k) {
     for (int n = 1; n <= Ns; ++n) {
       if (q.skip && k >= 1 && n <= k) {
         // exact slice: U(k,n) from U(k-1,n) or F(k-1,k); no fine slice F(k,n)
         double ready = C(k - 1, n);
         if (n == k) ready = std::max(ready, Fd(k - 1, n));
+        ready = after_copies(k, n, ready);
         out.push_back({ready, 0.0, 0, {prob, ap::kJobCopy, k, n, 0}});
         T2(k, n) = ready;
         C(k, n) = ready + 1.0;
@@ -563,12 +571,13 @@ double problem_jobs(int prob, const PipeShape& q, std::vector<SchedItem>& out) {
       if (q.split) {
         double t2 = ready + jc.stage1;
         if (k >= 1) t2 = std::max({t2, std::nextafter(Fs(k - 1, n), inf), std::nextafter(T2(k - 1, n), inf)});
+        t2 = after_copies(k, n, t2);
         for (int g = 0; g < q.groups; ++g) out.push_back({ready, 0.0, 0, {prob, ap::kJobStage1, k, n, g}});
         for (int g = 0; g < q.groups; ++g) out.push_back({t2, 0.0, 1, {prob, ap::kJobStage2, k, n, g}});
         T2(k, n) = t2;
         C(k, n) = std::max({ready + jc.stage1 + jc.stage2, after, t2}) + jc.finish;
       } else {
-        const double start = std::max(ready, after);
+        const double start = after_copies(k, n, std::max(ready, after));
         out.push_back({start, 0.0, 0, {prob, ap::kJobCoarse, k, n, 0}});
         T2(k, n) = start;
         C(k, n) = start + jc.whole;
@@ -634,10 +643,18 @@ bool order_is_valid(const std::vector<ap::PipeJob>& jobs, const std::vector<Pipe
       for (int n = 1; n <= q.Ns; ++n) {
         const size_t at = idx(k, n);
         if (cfirst[at] == none) return false;
+        // with a tolerance, C(k, Ns) (its completion point) comes after the copy jobs of level k
+        auto copies_before = [&](long long from) {
+          if (!(q.tol > 0.0) || !q.skip || k < 1 || n != q.Ns) return true;
+          for (int m = 1; m <= std::min(k, q.Ns - 1); ++m)
+            if (clast[idx(k, m)] >= from) return false;
+          return true;
+        };
         if (q.skip && k >= 1 && n <= k) {
           // copy job: after C(k-1,n) and, for n = k, after F(k-1,k); no fine slice
           if (fpos[at] != none || clast[idx(k - 1, n)] >= cfirst[at]) return false;
           if (n == k && (fpos[idx(k - 1, n)] == none || fpos[idx(k - 1, n)] >= cfirst[at])) return false;
+          if (!copies_before(cfirst[at])) return false;
           continue;
         }
         if (k < q.K && fpos[at] == none) return false;
@@ -648,6 +665,7 @@ bool order_is_valid(const std::vector<ap::PipeJob>& jobs, const std::vector<Pipe
         const long long finish_from = q.split ? s2first[at] : cfirst[at];
         if (q.split && (s1last[at] == none || s2first[at] == none || s1last[at] >= s2first[at])) return false;
         if (k >= 1 && (fpos[idx(k - 1, n)] >= finish_from || clast[idx(k - 1, n)] >= finish_from)) return false;
+        if (!copies_before(finish_from)) return false;
       }
   }
   return true;
@@ -1418,6 +1436,7 @@ int query_shape(int N, const ap_solve_params* p, int split, int group, int fine_
   q->fp64 = p->precision == AP_PREC_FP64;
   q->split = split < 0 ? q->groups >= 2 : split != 0;
   q->skip = true;
+  q->tol = p->tol > 0.0 ? p->tol : 0.0;
   q->fg = std::min(fine_group, ap::pipeline_fine_slices(N, q->fp64));
   if (cost) {
     for (int i = 0; i < 4; ++i)

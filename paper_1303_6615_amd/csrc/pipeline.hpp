@@ -36,6 +36,20 @@ __device__ __forceinline__ void acquire_for_workgroup() {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Agent-scope release by thread 0 on behalf of its workgroup, before the
+// relaxed atomic that publishes: every wavefront has waited for its own
+// stores to reach the L2 before the barrier that precedes this.  The fence
+// writes this XCD's L2 back (buffer_wbl2); the explicit wait then holds the
+// publishing atomic until that write-back has completed.  The compiler's own
+// wait after the write-back is a soft one that its wait-count pass deletes
+// when it sees no loads or stores in flight (it does not count the
+// write-back): the atomic then reaches the other XCDs before the data, and a
+// consumer that is already polling reads the state from before the write.
+__device__ __forceinline__ void release_for_workgroup() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
 // Thread 0 waits for *ctr >= target (relaxed polls, then an agent-scope
 // acquire for the workgroup: the producers are on this device).
 // On a stall it records (1, job, counter index) in diag[0..2] and returns
@@ -99,6 +113,20 @@ __device__ __forceinline__ bool past_stop(const PipeJob& jb, const PipeProb<T>& 
   return st > 0 && jb.k > st;
 }
 
+// With a tolerance, the job that completes C(k, Ns) reads every residual part
+// of level k (level_residual).  The copy jobs of the exact slices m <= k are
+// not on the coarse chain that leads to C(k, Ns), so that job also waits for
+// their counters (thread 0).
+template <typename T>
+__device__ __forceinline__ bool wait_level_copies(const PipeProb<T>& p, const PipeIdx& ix, int k, int* diag,
+                                                  int jt) {
+  if (!(p.tol > 0.0) || k < 1) return true;
+  const int last = min(k, p.Ns - 1);
+  for (int m = 1; m <= last; ++m)
+    if (!wait_count(&p.cnt[ix.coarse(k, m)], 1, diag, jt, ix.coarse(k, m))) return false;
+  return true;
+}
+
 // Dependencies a job waits for before it starts (thread 0).
 template <typename T>
 __device__ __forceinline__ bool wait_deps(const PipeJob& jb, const PipeProb<T>& p, int* diag, int jt) {
@@ -107,7 +135,8 @@ __device__ __forceinline__ bool wait_deps(const PipeJob& jb, const PipeProb<T>& 
   if (jb.type == kJobStage2) return wait_count(&p.cnt[ix.stage1(k, n)], p.groups, diag, jt, ix.stage1(k, n));
   if (jb.type == kJobCopy) {
     if (n == k && !wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n))) return false;
-    return wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n));
+    if (!wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n))) return false;
+    return n == p.Ns ? wait_level_copies(p, ix, k, diag, jt) : true;
   }
   // a fine job over slices n .. n + g - 1 (g >= 2) needs their inputs U(k, n - 1 .. n + g - 2): the
   // coarse chain publishes in order, so the last one suffices
@@ -116,6 +145,7 @@ __device__ __forceinline__ bool wait_deps(const PipeJob& jb, const PipeProb<T>& 
   if (jb.type == kJobCoarse && k >= 1) {
     if (!wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n))) return false;
     if (!wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n))) return false;
+    if (n == p.Ns && !wait_level_copies(p, ix, k, diag, jt)) return false;
   }
   return true;
 }
@@ -253,7 +283,8 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
   wait_global_stores();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int before = __hip_atomic_fetch_add(&p.cnt[ix.stage2(k, n)], 1, __ATOMIC_ACQ_REL,
+    release_for_workgroup();
+    const int before = __hip_atomic_fetch_add(&p.cnt[ix.stage2(k, n)], 1, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
     int flag = 0;
     if (before == p.groups - 1) {
@@ -263,6 +294,7 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
         ok = wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n));
         if (ok) ok = wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n));
       }
+      if (ok && n == Ns) ok = wait_level_copies(p, ix, k, diag, jt);
       flag = ok ? 1 : 0;
     }
     *s_flag = flag;
@@ -313,9 +345,10 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
   for (;;) {
     if (threadIdx.x == 0) {
       if (pub >= 0) {
-        // the job's stores were released by every wavefront before the barrier
+        // every wavefront's stores of the job reached the L2 before the barrier
+        release_for_workgroup();
         for (int i = 0; i < npub; ++i)
-          __hip_atomic_fetch_add(&pub_cnt[pub + i * kCounterStride], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_add(&pub_cnt[pub + i * kCounterStride], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(abort + 3, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (progress) {
           progress[2 * blockIdx.x] += 1;

@@ -260,6 +260,53 @@ def test_split_coarse_steps_equal_single_workgroup_steps_bitwise(torch_cuda, cfg
             assert torch.equal(Us, Uq) and torch.equal(rs, rq), group
 
 
+@pytest.mark.parametrize("fg", [1, 2])
+def test_split_steps_with_short_fine_jobs(torch_cuda, fg):
+    # eps = 0.1 with 16 slices of T = 0.1: two fine steps per slice, so fine
+    # jobs end long before the coarse step they feed, and consumers are
+    # already polling when a split step's finisher publishes.  Split and whole
+    # coarse steps give the same bits, run after run, and the oracle's values.
+    from paper_1303_6615_amd.binding import AP_OPT_FINE_GROUP, AP_OPT_SPLIT
+    from paper_1303_6615_amd.inputs import SolveConfig
+    torch = torch_cuda
+    cfg = SolveConfig("short-fine-n512", nx=512, eps=0.1, nu=NU_BY_NX[512], T=0.1, slices=16, K=8, dt=0.1 / 20,
+                      Mbar=32, k_ic=64, seed=21)
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        ctx.set_option(AP_OPT_FINE_GROUP, fg)
+        ctx.set_option(AP_OPT_SPLIT, 0)
+        Uw, rw = _solve(ctx, torch, cfg, FP32)
+        ctx.set_option(AP_OPT_SPLIT, 1)
+        for rep in range(3):
+            Us, rs = _solve(ctx, torch, cfg, FP32)
+            assert torch.equal(Us, Uw) and torch.equal(rs, rw), rep
+    Uref, rref = _oracle_solve(cfg)
+    assert _rel(Uw.cpu().numpy(), Uref) < 2e-5
+    assert np.all(np.abs(rw.cpu().numpy() - rref) <= 1e-3 * rref + 1e-6)
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_tolerance_stop_matches_the_oracle(torch_cuda, split):
+    # Alg. 4's while loop: the device-side stop after the first iteration
+    # with r^k <= tol gives the oracle's tolerance-stopped iterate and
+    # residuals (FP64; tol placed between two of the oracle's residuals)
+    from paper_1303_6615_amd.binding import AP_OPT_SPLIT
+    torch = torch_cuda
+    cfg = C1
+    _, rfull = _oracle_solve(cfg)
+    stop = 3
+    tol = float(np.sqrt(rfull[stop - 1] * rfull[stop - 2]))
+    Uref, rref, _ = O.parareal_solve(cfg.initial_state(), cfg.nx, cfg.eps, cfg.F, cfg.nu, cfg.T, cfg.slices,
+                                     cfg.K, cfg.fine_steps, cfg.Mbar, cfg.window, tol=tol)
+    assert len(rref) == stop
+    with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
+        ctx.set_option(AP_OPT_SPLIT, split)
+        U, r = _solve(ctx, torch, cfg, FP64, tol=tol)
+    r = r.cpu().numpy()
+    assert np.all(r[stop:] == -1.0) and np.all(r[:stop] >= 0)
+    assert np.all(np.abs(r[:stop] - np.array(rref)) <= 1e-6 * np.array(rref) + 1e-12)
+    assert _rel(U.cpu().numpy(), Uref) < 1e-11
+
+
 def test_group_size_changes_rounding_only(torch_cuda):
     from paper_1303_6615_amd.binding import AP_OPT_GROUP
     torch = torch_cuda
@@ -377,11 +424,6 @@ def _serve_all(srv, reqs, precision=FP32):
     return [out[t] for t in tickets]
 
 
-@pytest.mark.xfail(strict=False, reason=(
-    "open defect: with split coarse steps and only 1-2 fine steps per slice, a solve occasionally reads a "
-    "state from before its producer's write (workspaces poisoned with NaN bytes show it in 10 of 30 solves "
-    "at N=512, eps=0.1; never with whole coarse steps or 12+ fine steps per slice); the request's residuals "
-    "at early levels then differ from its served solve"))
 def test_serving_results_equal_alone_solves(torch_cuda):
     # requests of uneven N, eps, T and slices through the serving loop: each
     # result equals the same solve run alone (continuous batching changes only
