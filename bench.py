@@ -2,25 +2,37 @@
 """Benchmark: asymptotic parareal solves of the 1D rotating shallow water system
 on one MI355X.
 
-One step = one complete parareal solve (coarse initial sweep, then K iterations
-of [fine batch over every slice, serial coarse sweep with the FP64
-correction, residual], run as one pipelined persistent launch) of the default
-workload
-    N = 256, eps = 0.01, nu = 1e-5, F = 1, T = 2, 64 slices, K = 8,
-    fine ETDRK4 dt = eps/20 (63 steps per slice), M = 32 averaging samples,
-    T0 = dT/eps, FP32 propagators with FP64 correction,
-    seeded k^-2 initial spectrum up to k = 32, max|h| = 0.1.
-Inputs are resident on the device before timing starts.
+One step = one persistent launch that runs 64 independent parareal solves of
+uneven size to completion (the mixed-batch workload, the largest single-GPU
+configuration):
+    64 problems drawn by default_rng(4): N ~ U{128, 256, 512, 1024},
+    eps ~ U{0.1, 0.01, 0.001}, slices ~ U{16..256}; T = 1, K = 8,
+    fine ETDRK4 dt = eps/20, M = 32 averaging samples, T0 = dT/eps,
+    nu by grid size (3e-5, 1e-5, 1e-6, 1e-7), seeded k^-2 initial spectra up
+    to k = N/8 with max|h| = 0.1; FP32 propagators with FP64 correction.
+Each solve is the coarse initial sweep plus K iterations of [fine ETDRK4 over
+every slice, serial coarse sweep with the FP64 correction, residual]; all of
+them run as one dependency graph in one launch.  Inputs are resident on the
+device before timing starts.
 
-Metric: fine grid-point-steps per second of whole-solve wall time, counting
+Metric: fine grid-point-steps per second of whole-step wall time, counting
 the fine slices actually computed (K x slices x fine steps x N per solve,
 less the K(K-1)/2 slices that earlier iterations made exact and that are
-copied instead of recomputed).  The JSON line also carries the
-roofline of the dominant kernel (algorithmic flops per launch over its
-event-timed average duration) and the FP64 CPU oracle timed on one full
-solve of the same workload.
+copied instead of recomputed).  The JSON line also carries:
+  roofline      the persistent kernel's algorithmic flops per launch over its
+                event-timed average duration, against the FP32 vector peak;
+  c3            the N = 1024, 256-slice single solve (FP32 propagators with
+                FP64 correction), measured the same way;
+  fine_batch    the fine propagator alone in its throughput form;
+  serving       the request loop (continuous batching) against the plain
+                per-request FP64 path, closed and open loop, with sampled
+                requests re-run alone and compared with their served results;
+  cpu_baseline  the FP64 oracle on the host's cores (a process per problem)
+                over a bounded sample of the same workload, timed before the
+                GPU is touched.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload c4|c1|c2|c3]
+                    [--no-cpu-baseline] [--no-c3] [--serve-requests R]
 """
 import argparse
 import json
@@ -31,16 +43,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+MIXED_NAME = "rsw-mixed64-n128-1024-fp32c64"
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48,
-                    help="requests of the serving measurement (0 skips it)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the C3 measurement beside the headline")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests of the open-loop serving measurement (0 skips serving)")
     ap.add_argument("--graph", action="store_true",
                     help="replay each step from a captured hipGraph (the pipeline timing then covers the "
                          "whole replay, boundary kernels included)")
@@ -54,6 +69,16 @@ def parse():
                     help="only run a plain device copy of this many MiB three times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def host_workers() -> int:
+    """Worker processes for the CPU baseline: the cores this process may run
+    on, at most 16 (one GPU's share of a host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def fine_batch_measure(slices):
@@ -95,19 +120,57 @@ def fine_batch_measure(slices):
                          "frac_of_unpacked_fp32": round(flops / avg_s / 1e12 / metrics.PEAK_FP32_NOPACK_TFLOPS, 4)}}
 
 
-def cpu_baseline(cfg):
-    """The FP64 oracle on one full solve of the workload, BLAS limited to one thread."""
+def _oracle_solve(cfg):
+    """One oracle solve in a worker process (BLAS and FFT single-threaded);
+    returns its wall time."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle as O
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        U, res, _ = O.parareal_solve(cfg.initial_state(), cfg.nx, cfg.eps, cfg.F, cfg.nu, cfg.T,
-                                     cfg.slices, cfg.K, cfg.fine_steps, cfg.Mbar, cfg.window)
+        U, _, _ = O.parareal_solve(cfg.initial_state(), cfg.nx, cfg.eps, cfg.F, cfg.nu, cfg.T,
+                                   cfg.slices, cfg.K, cfg.fine_steps, cfg.Mbar, cfg.window)
         dt = time.perf_counter() - t0
     assert np.all(np.isfinite(U))
-    return {"value": cfg.fine_gp_steps() / dt, "unit": "fine grid-point-steps/s", "cores": 1,
+    return dt
+
+
+def cpu_baseline_mixed(slices=16):
+    """The FP64 oracle on every problem of the mixed batch, each cut to its
+    first `slices` slices (same dT, fine steps, K and M, so the same per-slice
+    work and fine/coarse mix), one process per problem on the host's cores.
+    Counted like the GPU: fine grid-point-steps of the slices that are not
+    exact copies, over the wall time of the whole pool."""
+    import dataclasses
+    import multiprocessing as mp
+
+    from paper_1303_6615_amd import metrics
+    from paper_1303_6615_amd.inputs import mixed_batch
+
+    probs = []
+    for c in mixed_batch(64):
+        ns = min(c.slices, slices)
+        probs.append(dataclasses.replace(c, slices=ns, T=c.dT * ns))
+    workers = host_workers()
+    gp = sum(metrics.pipelined_work(c.nx, c.slices, c.K, c.fine_steps, c.Mbar)[0] for c in probs)
+    order = sorted(probs, key=lambda c: -c.slices * c.fine_steps * c.nx)     # longest first
+    ctx = mp.get_context("fork")           # before any GPU use: plain forks of this process
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        per = pool.map(_oracle_solve, order, chunksize=1)
+    wall = time.perf_counter() - t0
+    return {"value": round(gp / wall, 1), "unit": "fine grid-point-steps/s", "cores": workers,
+            "kind": "oracle", "seconds": round(wall, 3), "cpu_seconds": round(sum(per), 3),
+            "sample": f"all 64 problems of {MIXED_NAME}, each cut to its first {slices} slices "
+                      f"(same dT, fine steps, K = 8, M = 32); numpy FP64, one single-threaded "
+                      f"process per problem, {workers} at a time"}
+
+
+def cpu_baseline(cfg):
+    """The FP64 oracle on one full solve of the workload, BLAS limited to one thread."""
+    dt = _oracle_solve(cfg)
+    return {"value": round(cfg.fine_gp_steps() / dt, 1), "unit": "fine grid-point-steps/s", "cores": 1,
             "kind": "oracle", "seconds": round(dt, 3),
             "sample": f"one full parareal solve of {cfg.name} (numpy FP64, single thread)"}
 
@@ -155,6 +218,49 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_kib_per_dispatch": mib * 1024, "dispatches": 3}), flush=True)
 
 
+def measure(W, steps, warmup):
+    """Times `steps` steps of workload W after `warmup` untimed ones: wall
+    time between two device synchronisations, and the persistent kernel's
+    launches from HIP events on the stream it runs on."""
+    import torch
+
+    from paper_1303_6615_amd import metrics
+
+    for _ in range(warmup):
+        W["step"]()
+    torch.cuda.synchronize()
+    owner = W["owner"]
+    owner.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        W["step"]()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = owner.profile_read()
+    owner.profile(False)
+    W["check"]()
+    kern = {}
+    tot_ms = sum(ms for (_, ms) in prof.values())
+    for name, (n, ms) in prof.items():
+        if n == 0:
+            continue
+        d = {"launches": n, "avg_ms": round(ms / n, 5), "share": round(ms / tot_ms, 4)}
+        if name == "pipeline":
+            d["tflops"] = round(W["pipeline_flops"] / (ms / n * 1e-3) / 1e12, 4)
+        kern[name] = d
+    n_launch, ms_total = prof["pipeline"]
+    avg_s = ms_total / n_launch * 1e-3
+    achieved = W["pipeline_flops"] / avg_s / 1e12
+    fp32 = W["precision"] == 0
+    peak = metrics.PEAK_FP32_TFLOPS if fp32 else metrics.PEAK_FP64_TFLOPS
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 6), "traffic": measured_traffic(W["name"]),
+                "kernel": W["kernel"], "flops_per_launch": W["pipeline_flops"],
+                "avg_launch_ms": round(avg_s * 1e3, 5)}
+    return {"value": W["gp_steps"] * steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
+            "roofline": roofline, "kernels": kern, "dtype": "f32" if fp32 else "f64"}
+
+
 def main():
     args = parse()
     if args.copy_mib:
@@ -165,83 +271,66 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the parallel-in-time "
-              "dimension is the batch dimension of the single-GPU kernels.", file=sys.stderr)
+              "dimension is the batch dimension of the single-GPU kernels, and this build "
+              "uses no second GPU.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+
+    # the oracle first: its worker processes are forked before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        if args.workload == "c4":
+            cpu = cpu_baseline_mixed()
+        else:
+            from paper_1303_6615_amd.inputs import C1, C2, C3
+            cpu = cpu_baseline({"c1": C1, "c2": C2, "c3": C3}[args.workload])
+        print(f"# cpu baseline done in {cpu['seconds']} s", file=sys.stderr, flush=True)
+
     import torch
-
-    from paper_1303_6615_amd import metrics
-
     torch.cuda.set_device(0)
-    W = single_workload(args) if args.workload != "c4" else batch_workload(args)
-
-    for _ in range(args.warmup):
-        W["step"]()
-    torch.cuda.synchronize()
-
-    owner = W["owner"]
-    owner.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        W["step"]()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = owner.profile_read()
-    owner.profile(False)
-    W["check"]()
-
-    value = W["gp_steps"] * args.steps / elapsed
-    flops = {"pipeline": W["pipeline_flops"]}
-    kern = {}
-    tot_ms = sum(ms for (_, ms) in prof.values())
-    for name, (n, ms) in prof.items():
-        if n == 0:
-            continue
-        d = {"launches": n, "avg_ms": round(ms / n, 5), "share": round(ms / tot_ms, 4)}
-        if name in flops:
-            d["tflops"] = round(flops[name] / (ms / n * 1e-3) / 1e12, 4)
-        kern[name] = d
-    n_launch, ms_total = prof["pipeline"]
-    avg_s = ms_total / n_launch * 1e-3
-    achieved = flops["pipeline"] / avg_s / 1e12
-    fp32 = W["precision"] == 0
-    peak = metrics.PEAK_FP32_TFLOPS if fp32 else metrics.PEAK_FP64_TFLOPS
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 6), "traffic": measured_traffic(W["name"]),
-                "kernel": W["kernel"], "flops_per_launch": flops["pipeline"],
-                "avg_launch_ms": round(avg_s * 1e3, 5)}
+    W = single_workload(args, args.workload) if args.workload != "c4" else batch_workload(args)
+    m = measure(W, args.steps, args.warmup)
     line = {
         "metric": "fine grid-point-steps/s at 1 GPU",
-        "value": round(value, 1),
+        "value": round(m["value"], 1),
         "unit": "fine grid-point-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "ms_per_step": round(m["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f32" if fp32 else "f64",
+        "dtype": m["dtype"],
         "data": "synthetic",
         "config": W["config"],
-        "roofline": roofline,
-        "kernels": kern,
+        "roofline": m["roofline"],
+        "kernels": m["kernels"],
         "final_residual": W["final_residual"](),
         "autotune": W["autotune"],
     }
+    W["close"]()
+    print("# headline done", file=sys.stderr, flush=True)
+    if args.workload == "c4" and not args.no_c3:
+        W3 = single_workload(args, "c3")
+        m3 = measure(W3, 5, 1)
+        line["c3"] = {"workload": W3["name"], "value": round(m3["value"], 1), "unit": "fine grid-point-steps/s",
+                      "ms_per_solve": round(m3["ms_per_step"], 4), "roofline": m3["roofline"],
+                      "final_residual": W3["final_residual"](), "autotune": W3["autotune"]}
+        W3["close"]()
+        print("# c3 done", file=sys.stderr, flush=True)
     if args.fine_batch > 0:
         line["fine_batch"] = fine_batch_measure(args.fine_batch)
+        print("# fine batch done", file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         from paper_1303_6615_amd import serving
         line["serving"] = serving.run(n_requests=args.serve_requests, warmup=8)
-        line["serving"]["unit"] = "solves/s, latency s"
-    if not args.no_cpu_baseline and args.workload != "c4":
-        line["cpu_baseline"] = cpu_baseline(W["cfg"])
+        print("# serving done", file=sys.stderr, flush=True)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
-    W["close"]()
 
 
-def single_workload(args):
+def single_workload(args, which):
     """One parareal solve per step (workloads c1-c3)."""
     import numpy as np
     import torch
@@ -250,7 +339,7 @@ def single_workload(args):
     from paper_1303_6615_amd.binding import Context, autotune
     from paper_1303_6615_amd.inputs import C1, C2, C3
 
-    cfg = {"c1": C1, "c2": C2, "c3": C3}[args.workload]
+    cfg = {"c1": C1, "c2": C2, "c3": C3}[which]
     ctx = Context(cfg.nx, cfg.eps, cfg.F, cfg.nu)
     u0 = torch.tensor(cfg.initial_state(), device="cuda")
     out = torch.empty((cfg.slices + 1, 3, cfg.nx), dtype=torch.float64, device="cuda")
@@ -294,8 +383,6 @@ def single_workload(args):
 def batch_workload(args):
     """64 uneven problems (N 128-1024, eps 0.1-0.001, 16-256 slices, K = 8) in
     one persistent launch per step."""
-    import ctypes
-
     import numpy as np
     import torch
 
@@ -332,10 +419,10 @@ def batch_workload(args):
             x.close()
 
     return {
-        "name": "rsw-mixed64-n128-1024-fp32c64", "cfg": None, "owner": ctxs[0], "step": step, "check": check,
+        "name": MIXED_NAME, "cfg": None, "owner": ctxs[0], "step": step, "check": check,
         "precision": 0, "gp_steps": sum(w[0] for w in work), "pipeline_flops": flops,
         "kernel": "k_pipeline<float,64,128,256,512,1024>",
-        "config": {"workload": "rsw-mixed64-n128-1024-fp32c64", "problems": len(probs),
+        "config": {"workload": MIXED_NAME, "problems": len(probs),
                    "N": sorted({c.nx for c in probs}), "eps": sorted({c.eps for c in probs}),
                    "slices": [min(c.slices for c in probs), max(c.slices for c in probs)], "K": 8, "T": 1.0,
                    "M_avg": 32, "precision": "fp32 propagators, fp64 correction",
