@@ -7,6 +7,7 @@ Tolerances (relative L2 over all 3*N grid values, worst state):
     H^-1 norm (mode-k errors divided by 1 + k): N differentiates quadratic
     products once, and FP32 rounding of the products is white in k, so its
     image under i*k grows with k; H^-1 measures the products' rounding itself.
+    In the plain relative L2 norm single N is held to 1e-7 x Kd.
 """
 import numpy as np
 import pytest
@@ -62,6 +63,12 @@ def test_nonlinear(torch_cuda, n, prec, tol):
         got = ctx.nonlinear(torch.tensor(u, device="cuda"), precision=prec).cpu().numpy()
     err = _rel(got, ref) if prec == FP64 else _rel_hm1(got, ref, n)
     assert err < tol
+    if prec == FP32:
+        # plain relative L2: the FP32 rounding of the products is white over
+        # the retained band and N differentiates it once, so the error of mode
+        # k grows with k while N's energy sits at low k; the relative error
+        # grows with Kd = N/3, measured 4-5.4e-8 x Kd for N = 64..2048
+        assert _rel(got, ref) < 1e-7 * (n // 3)
 
 
 def test_empty_batch_is_noop(torch_cuda):
@@ -77,6 +84,10 @@ def test_empty_batch_is_noop(torch_cuda):
     (256, 0.01, 0.03125, 63, FP32, 2e-5),
     (256, 0.01, 0.03125, 63, FP64, 1e-11),
     (1024, 0.001, 1.0 / 256, 40, FP32, 2e-5),
+    (512, 0.01, 1.0 / 64, 32, FP32, 2e-5),
+    (512, 0.1, 0.05, 10, FP64, 1e-11),
+    (2048, 0.01, 0.01, 20, FP32, 2e-5),
+    (2048, 0.001, 0.002, 20, FP64, 1e-11),
 ])
 def test_fine_batch(torch_cuda, n, eps, dT, steps, prec, tol):
     torch = torch_cuda
@@ -143,6 +154,10 @@ def test_average(torch_cuda, n, T0, M, prec, tol):
     (64, 0.01, 1.0 / 16, 16, FP64, 1e-12),
     (256, 0.01, 0.03125, 32, FP32, 2e-5),
     (256, 0.1, 0.1, 9, FP64, 1e-12),
+    (512, 0.01, 1.0 / 64, 32, FP32, 2e-5),
+    (512, 0.001, 1.0 / 128, 32, FP64, 1e-12),
+    (2048, 0.01, 1.0 / 32, 32, FP32, 2e-5),
+    (2048, 0.1, 0.125, 16, FP64, 1e-12),
 ])
 def test_coarse(torch_cuda, n, eps, dT, M, prec, tol):
     torch = torch_cuda
