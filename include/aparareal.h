@@ -74,6 +74,24 @@ int aparareal_nonlinear(ap_ctx* ctx, const double* U_in, double* N_out, int batc
 int aparareal_fine_batch(ap_ctx* ctx, const double* U_in, double* U_out, int batch,
                          double dT, int steps, int precision, void* stream);
 
+/* aparareal_fine_batch for callers that cannot allocate memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results (bitwise) as aparareal_fine_batch, but
+ * every scratch byte (the coefficient tables of dT/steps and the modal input
+ * and output states) lives in one 64 MiB array per device that the library
+ * holds until the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call, on the device or the host.  The tables are copied from a
+ * pageable host buffer of the context with hipMemcpyAsync, so the call is not
+ * capturable as it stands.  Limit: 2 * batch * 3 * (N/3 + 1) * 16 bytes plus
+ * the tables (576 * (N/3 + 1) bytes, rounded to 256) within 64 MiB, e.g.
+ * 8122 states at N = 256 or 1017 at N = 2048; a larger batch returns AP_EINVAL
+ * before anything is enqueued.  The context's device must be current.  Every
+ * call on one device shares that device's array: calls on one stream run in
+ * order, calls that overlap on one GPU (other streams, other contexts or
+ * threads) race on it.                                                        */
+int aparareal_fine_batch_noalloc(ap_ctx* ctx, const double* U_in, double* U_out, int batch,
+                                 double dT, int steps, int precision, void* stream);
+
 /* Strang-splitting propagator (Alg. 3): `steps` steps of length h = dT/steps,
  * each a half step of the exact linear flow exp((h/2)(-L/eps + D)), a
  * midpoint step of the nonlinear flow v <- v + h N(v + (h/2) N(v)), and a

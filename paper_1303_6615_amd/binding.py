@@ -52,6 +52,7 @@ _SIGNATURES = {
     "aparareal_destroy": (_i, [_vp]),
     "aparareal_nonlinear": (_i, [_vp, _dp, _dp, _i, _i, _vp]),
     "aparareal_fine_batch": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
+    "aparareal_fine_batch_noalloc": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
     "aparareal_strang_batch": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
     "aparareal_average": (_i, [_vp, _dp, _dp, _i, _d, _i, _i, _vp]),
     "aparareal_coarse": (_i, [_vp, _dp, _dp, _i, _d, _i, _d, _i, _vp]),
@@ -239,6 +240,11 @@ class Context:
 
     def fine_batch(self, U, dT: float, steps: int, precision: int = AP_PREC_FP32, out=None):
         return self._batched(lib().aparareal_fine_batch, U, float(dT), int(steps), precision, out=out)
+
+    def fine_batch_noalloc(self, U, dT: float, steps: int, precision: int = AP_PREC_FP32, out=None):
+        """fine_batch through the entry point that allocates nothing (its
+        scratch is the library's per-device array); `out` may be passed in."""
+        return self._batched(lib().aparareal_fine_batch_noalloc, U, float(dT), int(steps), precision, out=out)
 
     def strang_batch(self, U, dT: float, steps: int, precision: int = AP_PREC_FP32, out=None):
         return self._batched(lib().aparareal_strang_batch, U, float(dT), int(steps), precision, out=out)

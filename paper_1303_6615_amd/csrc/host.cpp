@@ -30,6 +30,7 @@
 
 #include "../../include/aparareal.h"
 #include "launch.hpp"
+#include "noalloc.hpp"
 #include "wavefft.hpp"
 
 namespace {
@@ -154,6 +155,10 @@ struct ap_ctx {
   std::map<uint64_t, std::unique_ptr<FineTables>> fine_cache;
   std::map<std::tuple<uint64_t, uint64_t, int, int>, std::unique_ptr<AvgTables>> avg_cache;
   DevBuf ws_in, ws_out, ws_U, ws_F, ws_G, ws_part;
+  // host staging of the fine coefficient tables for the allocation-free
+  // fine batch ([8][3][KP] each), sized when the context is created
+  std::vector<cx<double>> na_t64;
+  std::vector<cx<float>> na_t32;
   // pipelined solve: per-level states, flags, job list and descriptor
   DevBuf pp_U, pp_F, pp_G, pp_part, pp_P1, pp_P2;     // this context's problem
   DevBuf pp_flags, pp_jobs, pp_prob, pp_rows;          // launches this context owns
@@ -255,16 +260,13 @@ hipError_t ensure(ap_ctx* c, DevBuf& b, size_t bytes) {
   return b.alloc(bytes);
 }
 
-int fine_tables(ap_ctx* c, double h, FineTables** out) {
-  auto it = c->fine_cache.find(bits(h));
-  if (it != c->fine_cache.end()) {
-    *out = it->second.get();
-    return AP_OK;
-  }
-  auto ft = std::make_unique<FineTables>();
+// ETDRK4 coefficients of step h for every retained mode and eigen-branch
+// (Sec. 6.2, the Cox-Matthews scheme with the exact linear part
+// lambda = -nu k^4 - i alpha omega_k / eps): [8][3][KP] tables
+//   FP64: E, 0, E2, 0, Q, f1, 2 f2, f3
+//   FP32: E and E2 each as hi + lo, then Q, f1, 2 f2, f3.
+void fine_coefs(const ap_ctx* c, double h, cx<double>* t64, cx<float>* t32) {
   const int KP = c->KP;
-  std::vector<cx<double>> t64(size_t(8) * 3 * KP);
-  std::vector<cx<float>> t32(size_t(8) * 3 * KP);
   for (int k = 0; k < KP; ++k) {
     const double kk = double(k);
     for (int al = 0; al < 3; ++al) {
@@ -280,13 +282,11 @@ int fine_tables(ap_ctx* c, double h, FineTables** out) {
                           h * (-p2 + 4.0 * p3)};
       const size_t o = size_t(al) * KP + k;
       auto at = [&](int slot) { return size_t(slot) * 3 * KP + o; };
-      // FP64: E, 0, E2, 0, Q, f1, 2f2, f3
       t64[at(0)] = to_cx<double>(vals[0]);
       t64[at(1)] = cx<double>{0, 0};
       t64[at(2)] = to_cx<double>(vals[1]);
       t64[at(3)] = cx<double>{0, 0};
       for (int q = 2; q < 6; ++q) t64[at(q + 2)] = to_cx<double>(vals[q]);
-      // FP32: E and E2 as hi + lo
       for (int q = 0; q < 2; ++q) {
         const cx<float> hi = to_cx<float>(vals[q]);
         const cd rest = vals[q] - cd(double(hi.x), double(hi.y));
@@ -296,6 +296,18 @@ int fine_tables(ap_ctx* c, double h, FineTables** out) {
       for (int q = 2; q < 6; ++q) t32[at(q + 2)] = to_cx<float>(vals[q]);
     }
   }
+}
+
+int fine_tables(ap_ctx* c, double h, FineTables** out) {
+  auto it = c->fine_cache.find(bits(h));
+  if (it != c->fine_cache.end()) {
+    *out = it->second.get();
+    return AP_OK;
+  }
+  auto ft = std::make_unique<FineTables>();
+  std::vector<cx<double>> t64(size_t(8) * 3 * c->KP);
+  std::vector<cx<float>> t32(size_t(8) * 3 * c->KP);
+  fine_coefs(c, h, t64.data(), t32.data());
   hipError_t e = ft->coef64.upload(t64);
   if (e == hipSuccess) e = ft->coef32.upload(t32);
   if (e != hipSuccess) return hip_fail(e, "fine coefficient upload");
@@ -1035,6 +1047,8 @@ ap_ctx* aparareal_create(int N, double eps, double F, double nu) {
   }
   c->omega.resize(c->KP);
   c->akw.resize(c->KP);
+  c->na_t64.resize(size_t(8) * 3 * c->KP);
+  c->na_t32.resize(size_t(8) * 3 * c->KP);
   std::vector<ap::Basis<double>> b64(c->KP);
   std::vector<ap::Basis<float>> b32(c->KP);
   for (int k = 0; k < c->KP; ++k) {
@@ -1114,6 +1128,56 @@ int aparareal_fine_batch(ap_ctx* c, const double* U_in, double* U_out, int batch
   });
   if (e != hipSuccess) return hip_fail(e, "fine launch");
   return batch_epilogue(c, U_out, batch, s);
+}
+
+// The fine batch with every scratch byte in the library's per-device scratch
+// array: the coefficient tables of the step size, then the modal input and
+// output states.  Nothing is allocated, on the device or on the host.
+int aparareal_fine_batch_noalloc(ap_ctx* c, const double* U_in, double* U_out, int batch, double dT, int steps,
+                                 int precision, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_prec(precision))) return rc;
+  if (!(dT > 0.0 && std::isfinite(dT))) return fail(AP_EINVAL, "dT must be > 0");
+  if (steps < 1) return fail(AP_EINVAL, "steps must be >= 1");
+  if (batch < 0) return fail(AP_EINVAL, "batch must be >= 0");
+  if (batch > 0 && (!U_in || !U_out)) return fail(AP_EINVAL, "null array");
+  if (U_in && U_in == U_out) return fail(AP_EINVAL, "U_out may not alias U_in");
+  auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b64 = c->na_t64.size() * sizeof(cx<double>), b32 = c->na_t32.size() * sizeof(cx<float>);
+  const size_t fixed = up256(b64) + up256(b32);
+  const size_t per_state = 2 * state_bytes(c);
+  const size_t max_batch = (ap::kNoAllocScratchBytes - fixed - 512) / per_state;
+  if (size_t(batch) > max_batch)
+    return fail(AP_EINVAL, "batch of " + std::to_string(batch) + " states exceeds the scratch: at most " +
+                               std::to_string(max_batch) + " states of N = " + std::to_string(c->N));
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != c->device) return fail(AP_EINVAL, "the context's device must be the current device");
+  void* base = nullptr;
+  if ((e = ap::noalloc_scratch(c->device, &base)) != hipSuccess) return hip_fail(e, "scratch address");
+  if ((e = order_stream(c, s)) != hipSuccess) return hip_fail(e, "stream ordering");
+  if (batch == 0) return AP_OK;
+  unsigned char* p = static_cast<unsigned char*>(base);
+  auto* coef64 = reinterpret_cast<cx<double>*>(p);
+  auto* coef32 = reinterpret_cast<cx<float>*>(p + up256(b64));
+  auto* in = reinterpret_cast<cx<double>*>(p + fixed);
+  auto* out = reinterpret_cast<cx<double>*>(p + fixed + up256(size_t(batch) * state_bytes(c)));
+  // pageable host source: the copy has taken the bytes when the call returns
+  fine_coefs(c, dT / steps, c->na_t64.data(), c->na_t32.data());
+  if ((e = hipMemcpyAsync(coef64, c->na_t64.data(), b64, hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(coef32, c->na_t32.data(), b32, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "coefficient copy");
+  if ((e = ap::launch_to_modal(c->N, U_in, in, batch, c->tabs, s)) != hipSuccess)
+    return hip_fail(e, "to_modal launch");
+  if ((e = ap::launch_fine(c->N, precision == AP_PREC_FP64, in, out, batch, steps, coef64, coef32, c->tabs, s)) !=
+      hipSuccess)
+    return hip_fail(e, "fine launch");
+  if ((e = ap::launch_to_physical(c->N, out, U_out, batch, c->tabs, s)) != hipSuccess)
+    return hip_fail(e, "to_physical launch");
+  return AP_OK;
 }
 
 int aparareal_strang_batch(ap_ctx* c, const double* U_in, double* U_out, int batch, double dT, int steps,

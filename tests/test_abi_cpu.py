@@ -39,6 +39,7 @@ def test_create_rejects_bad_parameters(L, args):
 
 def test_calls_reject_null_context(L):
     assert L.aparareal_fine_batch(None, None, None, 1, 0.1, 1, 0, None) == -1
+    assert L.aparareal_fine_batch_noalloc(None, None, None, 1, 0.1, 1, 0, None) == -1
     assert L.aparareal_solve(None, None, None, None, None, None) == -1
     assert L.aparareal_destroy(None) == -1
     assert b"null context" in L.aparareal_last_error()
