@@ -24,6 +24,7 @@
 #include <limits>
 #include <map>
 #include <memory>
+#include <queue>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -532,87 +533,6 @@ JobCost job_cost(const PipeShape& q) {
   return c;
 }
 
-struct SchedItem {
-  double t;       // estimated ready time with unlimited workgroups (us)
-  double crit;    // the problem's estimated critical path: longer problems first on ties
-  int rank;       // stage 1 / whole coarse 0, stage 2 1, fine 2
-  ap::PipeJob j;
-};
-
-// Jobs of one problem with their earliest start times: a fine slice F(k,n)
-// and the first stage of C(k,n) start when C(k,n-1) is done; the second stage
-// one stage later; C(k,n) is done after both stages and (k >= 1) after F(k-1,n)
-// and C(k-1,n).  A fine job over fg consecutive slices n .. n+fg-1 starts when
-// the last of their inputs, C(k,n+fg-2), is done.  Any stage-2 job may finish
-// its step and then waits for F(k-1,n) and C(k-1,n), so the stage-2 jobs are
-// also placed after the jobs computing those (their times made just larger).
-// Returns the estimated completion of the last coarse step.
-double problem_jobs(int prob, const PipeShape& q, std::vector<SchedItem>& out) {
-  const JobCost jc = job_cost(q);
-  const int Ns = q.Ns, K = q.K, fg = std::max(1, q.fg);
-  const size_t cells = size_t(K + 1) * Ns;
-  std::vector<double> dC(cells, 0.0), dF(cells, 0.0), dFs(cells, 0.0), dT2(cells, 0.0);
-  auto C = [&](int k, int n) -> double& { return dC[size_t(k) * Ns + n - 1]; };
-  auto Fd = [&](int k, int n) -> double& { return dF[size_t(k) * Ns + n - 1]; };
-  auto Fs = [&](int k, int n) -> double& { return dFs[size_t(k) * Ns + n - 1]; };   // start of F(k,n)'s job
-  auto T2 = [&](int k, int n) -> double& { return dT2[size_t(k) * Ns + n - 1]; };   // latest time of C(k,n)'s jobs
-  const double inf = std::numeric_limits<double>::infinity();
-  const size_t first = out.size();
-  // With a tolerance the job completing C(k, Ns) also waits for the copy jobs
-  // of level k (it reads their residual parts): it is placed after them.
-  auto after_copies = [&](int k, int n, double t) {
-    if (!(q.tol > 0.0) || !q.skip || k < 1 || n != Ns) return t;
-    for (int m = 1; m <= std::min(k, Ns - 1); ++m) t = std::max(t, std::nextafter(T2(k, m), inf));
-    return t;
-  };
-  for (int k = 0; k <= K; ++k) {
-    for (int n = 1; n <= Ns; ++n) {
-      if (q.skip && k >= 1 && n <= k) {
-        // exact slice: U(k,n) from U(k-1,n) or F(k-1,k); no fine slice F(k,n)
-        double ready = C(k - 1, n);
-        if (n == k) ready = std::max(ready, Fd(k - 1, n));
-        ready = after_copies(k, n, ready);
-        out.push_back({ready, 0.0, 0, {prob, ap::kJobCopy, k, n, 0}});
-        T2(k, n) = ready;
-        C(k, n) = ready + 1.0;
-        continue;
-      }
-      const double ready = n > 1 ? C(k, n - 1) : 0.0;
-      double after = 0.0;
-      if (k >= 1) after = std::max(Fd(k - 1, n), C(k - 1, n));
-      if (q.split) {
-        double t2 = ready + jc.stage1;
-        if (k >= 1) t2 = std::max({t2, std::nextafter(Fs(k - 1, n), inf), std::nextafter(T2(k - 1, n), inf)});
-        t2 = after_copies(k, n, t2);
-        for (int g = 0; g < q.groups; ++g) out.push_back({ready, 0.0, 0, {prob, ap::kJobStage1, k, n, g}});
-        for (int g = 0; g < q.groups; ++g) out.push_back({t2, 0.0, 1, {prob, ap::kJobStage2, k, n, g}});
-        T2(k, n) = t2;
-        C(k, n) = std::max({ready + jc.stage1 + jc.stage2, after, t2}) + jc.finish;
-      } else {
-        const double start = after_copies(k, n, std::max(ready, after));
-        out.push_back({start, 0.0, 0, {prob, ap::kJobCoarse, k, n, 0}});
-        T2(k, n) = start;
-        C(k, n) = start + jc.whole;
-      }
-    }
-    if (k == K) break;
-    // fine jobs of level k (inputs U(k, n-1) known now)
-    for (int n = q.skip && k >= 1 ? k + 1 : 1; n <= Ns; n += fg) {
-      const int g = std::min(fg, Ns - n + 1);
-      const int last = n + g - 2;
-      const double ready = last >= 1 ? C(k, last) : 0.0;
-      for (int i = 0; i < g; ++i) {
-        Fs(k, n + i) = ready;
-        Fd(k, n + i) = ready + jc.fine;
-      }
-      out.push_back({ready, 0.0, 2, {prob, ap::kJobFine, k, n, g}});
-    }
-  }
-  const double span = C(K, Ns);
-  for (size_t i = first; i < out.size(); ++i) out[i].crit = span;
-  return span;
-}
-
 // Every job's dependencies must come earlier in the hand-out order (for a
 // split step: every stage-2 job after all stage-1 jobs of the step and after
 // every job the finishing one waits for).  Then the earliest unfinished job
@@ -683,25 +603,165 @@ bool order_is_valid(const std::vector<ap::PipeJob>& jobs, const std::vector<Pipe
   return true;
 }
 
-// Hand-out order of the jobs of several problems: by estimated ready time,
-// then longer problems first, then stage 1 before stage 2 before fine slices.
-std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes) {
-  std::vector<SchedItem> it;
-  for (size_t p = 0; p < shapes.size(); ++p) problem_jobs(int(p), shapes[p], it);
-  std::stable_sort(it.begin(), it.end(), [](const SchedItem& a, const SchedItem& b) {
-    if (a.t != b.t) return a.t < b.t;
-    if (a.crit != b.crit) return a.crit > b.crit;
-    if (a.rank != b.rank) return a.rank < b.rank;
-    if (a.j.prob != b.j.prob) return a.j.prob < b.j.prob;
-    if (a.j.k != b.j.k) return a.j.k < b.j.k;
-    if (a.j.n != b.j.n) return a.j.n < b.j.n;
-    return a.j.g < b.j.g;
-  });
+// Dependency graph of the jobs of several problems, as the device waits for
+// them: per job its duration estimate (us) and the jobs it waits for.
+struct JobDag {
+  std::vector<ap::PipeJob> job;
+  std::vector<double> dur;
+  std::vector<int> pred_begin;   // CSR: preds of job i at pred[pred_begin[i] .. pred_begin[i+1])
+  std::vector<int> pred;
+};
+
+// Appends the jobs of one problem in a topological order (level by level:
+// its coarse steps and copies, then its fine jobs) with their dependencies.
+//   copy C(k,n), n <= k:  C(k-1,n); for n = k also F(k-1,k)
+//   whole C(k,n):         C(k,n-1); for k >= 1 also F(k-1,n), C(k-1,n)
+//   stage 1 of C(k,n):    C(k,n-1)
+//   stage 2 of C(k,n):    every stage-1 job of the step, and (any stage-2 job
+//                         may finish the step) for k >= 1 F(k-1,n), C(k-1,n)
+//   fine F(k,n..n+g-1):   C(k,n+g-2) (its last input; the chain orders the rest)
+// C(k,n) is complete when its whole or copy job, or every stage-2 job, is.
+// With a tolerance, the jobs completing C(k,Ns) also wait for the copies of
+// level k (they read their residual parts).
+void problem_dag(int prob, const PipeShape& q, JobDag& d) {
+  const JobCost jc = job_cost(q);
+  const int Ns = q.Ns, K = q.K, fg = std::max(1, q.fg);
+  const size_t cells = size_t(K + 1) * Ns;
+  std::vector<int> cfirst(cells, -1), clast(cells, -1), fjob(cells, -1);
+  auto at = [&](int k, int n) { return size_t(k) * Ns + n - 1; };
+  std::vector<int> deps;
+  auto comp = [&](int k, int n) {   // the jobs completing C(k,n)
+    const int a = cfirst[at(k, n)], b = clast[at(k, n)];
+    const bool split = d.job[a].type == ap::kJobStage1;
+    for (int i = split ? a : b; i <= b; ++i)
+      if (d.job[i].type != ap::kJobStage1) deps.push_back(i);
+  };
+  auto copies = [&](int k, int n) {
+    if (!(q.tol > 0.0) || !q.skip || k < 1 || n != Ns) return;
+    for (int m = 1; m <= std::min(k, Ns - 1); ++m) comp(k, m);
+  };
+  auto add = [&](ap::PipeJob j, double dur) {
+    d.job.push_back(j);
+    d.dur.push_back(dur);
+    d.pred.insert(d.pred.end(), deps.begin(), deps.end());
+    d.pred_begin.push_back(int(d.pred.size()));
+    deps.clear();
+    return int(d.job.size()) - 1;
+  };
+  for (int k = 0; k <= K; ++k) {
+    for (int n = 1; n <= Ns; ++n) {
+      if (q.skip && k >= 1 && n <= k) {
+        comp(k - 1, n);
+        if (n == k) deps.push_back(fjob[at(k - 1, n)]);
+        copies(k, n);
+        cfirst[at(k, n)] = clast[at(k, n)] = add({prob, ap::kJobCopy, k, n, 0}, 1.0);
+        continue;
+      }
+      if (q.split) {
+        int first = -1;
+        for (int g = 0; g < q.groups; ++g) {
+          if (n > 1) comp(k, n - 1);
+          const int i = add({prob, ap::kJobStage1, k, n, g}, jc.stage1);
+          if (g == 0) first = i;
+        }
+        int last = -1;
+        for (int g = 0; g < q.groups; ++g) {
+          for (int x = 0; x < q.groups; ++x) deps.push_back(first + x);
+          if (k >= 1) {
+            deps.push_back(fjob[at(k - 1, n)]);
+            comp(k - 1, n);
+          }
+          copies(k, n);
+          last = add({prob, ap::kJobStage2, k, n, g}, jc.stage2 + jc.finish);
+        }
+        cfirst[at(k, n)] = first;
+        clast[at(k, n)] = last;
+      } else {
+        if (n > 1) comp(k, n - 1);
+        if (k >= 1) {
+          deps.push_back(fjob[at(k - 1, n)]);
+          comp(k - 1, n);
+        }
+        copies(k, n);
+        cfirst[at(k, n)] = clast[at(k, n)] = add({prob, ap::kJobCoarse, k, n, 0}, jc.whole);
+      }
+    }
+    if (k == K) break;
+    for (int n = q.skip && k >= 1 ? k + 1 : 1; n <= Ns; n += fg) {
+      const int g = std::min(fg, Ns - n + 1);
+      if (n + g - 2 >= 1) comp(k, n + g - 2);
+      const int i = add({prob, ap::kJobFine, k, n, g}, jc.fine);
+      for (int x = 0; x < g; ++x) fjob[at(k, n + x)] = i;
+    }
+  }
+}
+
+// Hand-out order of the jobs of several problems on `workers` resident
+// workgroups: a list schedule simulated with the jobs' duration estimates.
+// Whenever a workgroup is free it takes, among the jobs whose dependencies
+// have completed, the one with the longest remaining path to the end of its
+// problem (its own duration plus the longest chain of jobs that wait on it,
+// the "bottom level"); the jobs are handed out in the order the simulation
+// starts them.  Long chains (long fine steps or many slices) thus start
+// first and are not stretched by the jobs of short problems, while every
+// workgroup is kept busy.  The order is topological by construction.
+std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes, int workers) {
+  JobDag d;
+  d.pred_begin.push_back(0);
+  for (size_t p = 0; p < shapes.size(); ++p) problem_dag(int(p), shapes[p], d);
+  const int nj = int(d.job.size());
+  // successors (CSR) and bottom levels (jobs were appended in a topological order)
+  std::vector<int> nsucc(size_t(nj) + 1, 0), npred(nj, 0);
+  for (int i = 0; i < nj; ++i) {
+    npred[i] = d.pred_begin[i + 1] - d.pred_begin[i];
+    for (int x = d.pred_begin[i]; x < d.pred_begin[i + 1]; ++x) ++nsucc[d.pred[x] + 1];
+  }
+  for (int i = 0; i < nj; ++i) nsucc[i + 1] += nsucc[i];
+  std::vector<int> succ(d.pred.size()), fill(nsucc.begin(), nsucc.end() - 1);
+  for (int i = 0; i < nj; ++i)
+    for (int x = d.pred_begin[i]; x < d.pred_begin[i + 1]; ++x) succ[fill[d.pred[x]]++] = i;
+  std::vector<double> bl(nj, 0.0);
+  for (int i = nj - 1; i >= 0; --i) {
+    double m = 0.0;
+    for (int x = nsucc[i]; x < nsucc[i + 1]; ++x) m = std::max(m, bl[succ[x]]);
+    bl[i] = d.dur[i] + m;
+  }
+  // event simulation: ready jobs by bottom level (ties: earlier in the list),
+  // running jobs by end time
+  auto later = [&](int a, int b) { return bl[a] != bl[b] ? bl[a] < bl[b] : a > b; };
+  std::priority_queue<int, std::vector<int>, decltype(later)> ready(later);
+  using Ev = std::pair<double, int>;
+  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> running;
+  for (int i = 0; i < nj; ++i)
+    if (npred[i] == 0) ready.push(i);
   std::vector<ap::PipeJob> out;
-  out.reserve(it.size());
-  for (auto& x : it) out.push_back(x.j);
+  out.reserve(nj);
+  const int W = std::max(1, workers);
+  int busy = 0;
+  double now = 0.0;
+  while (int(out.size()) < nj) {
+    while (busy < W && !ready.empty()) {
+      const int i = ready.top();
+      ready.pop();
+      out.push_back(d.job[i]);
+      running.push({now + d.dur[i], i});
+      ++busy;
+    }
+    if (running.empty()) return {};   // a cycle: cannot happen; the caller rejects an empty order
+    now = running.top().first;
+    while (!running.empty() && running.top().first <= now) {
+      const int i = running.top().second;
+      running.pop();
+      --busy;
+      for (int x = nsucc[i]; x < nsucc[i + 1]; ++x)
+        if (--npred[succ[x]] == 0) ready.push(succ[x]);
+    }
+  }
   return out;
 }
+
+// Workgroups assumed by the host-only schedule queries (one per CU of an MI355X).
+constexpr int kQueryWorkers = 256;
 
 // ---------------------------------------------------------- pipelined solve -
 // One problem of a pipelined launch: its context (tables, per-problem device
@@ -867,7 +927,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
   int* ticket = flags + ncnt;
   int* abort = ticket + 1;
   // job list, cached by the problems' shapes
-  std::string key;
+  std::string key = std::to_string(grid) + "|";
   for (auto& q : shapes)
     key += std::to_string(q.nx) + ":" + std::to_string(q.Ns) + ":" + std::to_string(q.K) + ":" +
            std::to_string(q.steps) + ":" + std::to_string(q.M) + ":" + std::to_string(q.gs) + ":" +
@@ -877,7 +937,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
                               std::to_string(q.cal.stage2) + "," + std::to_string(q.cal.whole)
                         : std::string("-")) + ";";
   if (key != owner->pp_jobs_key) {
-    std::vector<ap::PipeJob> jobs = schedule_jobs(shapes);
+    std::vector<ap::PipeJob> jobs = schedule_jobs(shapes, grid);
     if (!order_is_valid(jobs, shapes)) return fail(AP_EINVAL, "internal: job order is not topological");
     if (jobs.size() > size_t(1) << 30) return fail(AP_EINVAL, "batch too large");
     owner->pp_jobs_key.clear();
@@ -1522,7 +1582,7 @@ int aparareal_pipeline_schedule(int N, const ap_solve_params* p, int split, int 
   const int rc = query_shape(N, p, split, group, fine_group, nullptr, &q);
   if (rc) return rc;
   const std::vector<PipeShape> shapes{q};
-  const std::vector<ap::PipeJob> jobs = schedule_jobs(shapes);
+  const std::vector<ap::PipeJob> jobs = schedule_jobs(shapes, kQueryWorkers);
   if (!order_is_valid(jobs, shapes)) return fail(AP_EINVAL, "internal: job order is not topological");
   if (out)
     for (size_t i = 0; i < jobs.size() && i < size_t(max_jobs); ++i) {
@@ -1545,7 +1605,7 @@ int aparareal_pipeline_schedule_batch(int count, const int* N, const ap_solve_pa
     cells += size_t(2 * p[i].K + 1) * size_t(p[i].slices);
     if (cells > (size_t(1) << 24)) return fail(AP_EINVAL, "batch too large");
   }
-  const std::vector<ap::PipeJob> jobs = schedule_jobs(shapes);
+  const std::vector<ap::PipeJob> jobs = schedule_jobs(shapes, kQueryWorkers);
   if (!order_is_valid(jobs, shapes)) return fail(AP_EINVAL, "internal: job order is not topological");
   if (out)
     for (size_t i = 0; i < jobs.size() && i < size_t(max_jobs); ++i) {

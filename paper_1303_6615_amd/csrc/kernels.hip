@@ -158,8 +158,11 @@ __global__ void __launch_bounds__(NT) k_nonlinear(const cx<double>* __restrict__
 
 // ------------------------------------------------------------ fine batch ---
 // Workgroup b steps slices b J .. min(b J + J, batch) - 1 (J = fine_slices).
+#ifndef AP_FINE_WAVES_PER_EU
+#define AP_FINE_WAVES_PER_EU 1
+#endif
 template <typename T, int NX, int NT>
-__global__ void __launch_bounds__(NT) k_fine(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(AP_FINE_WAVES_PER_EU))) k_fine(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
                                              int batch, int steps, const cx<double>* __restrict__ coef64,
                                              const cx<T>* __restrict__ coef, const cx<T>* __restrict__ tw,
                                              const Basis<T>* __restrict__ basis) {

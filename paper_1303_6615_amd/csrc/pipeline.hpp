@@ -312,13 +312,45 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
   return level_done();
 }
 
-template <typename T, int NX, int... REST>
+// What a job hands back to the kernel's scheduling loop.
+struct JobOut {
+  int pub;                 // first counter index to publish, or -1
+  int npub;                // counters it publishes
+  const void* staged;      // twiddle table left in LDS
+};
+
+// A job of grid size NX as an out-of-line call, for kernels that serve
+// several grid sizes: each size's job code gets a register allocation of its
+// own instead of one shared by every size (shared, the coarse steps of the
+// larger sizes spilled).  One call per job; a job runs for microseconds to
+// milliseconds.
+template <typename T, int NX>
+__device__ __attribute__((noinline)) JobOut run_job_call(unsigned char* smem, PipeJob jb, const PipeProb<T>* p,
+                                                         const void* staged, int* diag, int jt, int* s_flag,
+                                                         bool skip) {
+  JobOut o;
+  o.staged = staged;
+  o.npub = 1;
+  o.pub = run_job<T, NX>(smem, jb, *p, o.staged, diag, jt, s_flag, skip, o.npub);
+  return o;
+}
+
+template <typename T, bool CALL, int NX, int... REST>
 __device__ __forceinline__ int dispatch_job(int nx, unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
                                             const void*& staged, int* diag, int jt, int* s_flag, bool skip,
                                             int& npub) {
-  if (nx == NX) return run_job<T, NX>(smem, jb, p, staged, diag, jt, s_flag, skip, npub);
+  if (nx == NX) {
+    if constexpr (CALL) {
+      const JobOut o = run_job_call<T, NX>(smem, jb, &p, staged, diag, jt, s_flag, skip);
+      staged = o.staged;
+      npub = o.npub;
+      return o.pub;
+    } else {
+      return run_job<T, NX>(smem, jb, p, staged, diag, jt, s_flag, skip, npub);
+    }
+  }
   if constexpr (sizeof...(REST) > 0)
-    return dispatch_job<T, REST...>(nx, smem, jb, p, staged, diag, jt, s_flag, skip, npub);
+    return dispatch_job<T, CALL, REST...>(nx, smem, jb, p, staged, diag, jt, s_flag, skip, npub);
   else
     return -1;
 }
@@ -380,7 +412,7 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
     const bool skip = __builtin_amdgcn_readfirstlane(s_skip) != 0;
     int np = 1;
     pub = __builtin_amdgcn_readfirstlane(
-        dispatch_job<T, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip, np));
+        dispatch_job<T, (sizeof...(NXS) > 1), NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip, np));
     npub = __builtin_amdgcn_readfirstlane(np);
     pub_cnt = p.cnt;
     // Every wavefront waits for its stores of the job's results to reach the
