@@ -201,10 +201,17 @@ int aparareal_solve_batch(const ap_batch_item* items, int count, void* stream);
  *                 resident workgroups, else the most the grid size allows
  *                 (16, 10, 5, 2, 1, 1 for N = 64 .. 2048); n >= 1: at most n.
  *                 A group starts when its last slice's input is ready, so
- *                 grouping trades latency for throughput.                    */
+ *                 grouping trades latency for throughput.
+ *   AP_OPT_FINE_SHAPE  workgroup shape of aparareal_fine_batch (threads and
+ *                 slices per workgroup; three are compiled per precision and
+ *                 grid size, see aparareal_fine_shape): -1 (default) the
+ *                 shape aparareal_autotune_fine chose for this device, grid
+ *                 size and precision (in this context or, earlier, in the
+ *                 tuning cache), else shape 0; 0..2 that shape.  A slice
+ *                 rounds the same way in every shape: results are unchanged. */
 enum {
   AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2, AP_OPT_GRAPH = 3, AP_OPT_SKIP = 4, AP_OPT_SWEEPS = 5,
-  AP_OPT_FINE = 6, AP_OPT_COARSE = 7, AP_OPT_FINE_GROUP = 8
+  AP_OPT_FINE = 6, AP_OPT_COARSE = 7, AP_OPT_FINE_GROUP = 8, AP_OPT_FINE_SHAPE = 9
 };
 int aparareal_set_option(ap_ctx* ctx, int option, int value);
 int aparareal_get_option(ap_ctx* ctx, int option, int* value);
@@ -225,6 +232,26 @@ int aparareal_get_option(ap_ctx* ctx, int option, int* value);
  * summation order of the average (rounding only), and later solves equal
  * solves with AP_OPT_SPLIT and AP_OPT_GROUP set to the values read back.    */
 int aparareal_autotune(const ap_batch_item* items, int count, void* stream, double* best_ms);
+
+/* Autotuner of the fine batch (the parareal fine sweep over independent
+ * states, spec batching pattern): times aparareal_fine_batch's three
+ * compiled workgroup shapes for this grid size and precision on the caller's
+ * states (one warm-up and three timed launches each, HIP events on `stream`;
+ * the call synchronises), keeps the fastest in the context, and records it in
+ * the tuning cache, a text file read by every later context of this device
+ * kind, grid size and precision: $APARAREAL_TUNE_CACHE, else
+ * $XDG_CACHE_HOME/aparareal/tune.txt, else $HOME/.cache/aparareal/tune.txt
+ * (a write that fails is ignored).  U_in physical [batch][3][N], unchanged.
+ * shape_ms (host, 3 doubles, may be NULL) receives the mean launch time of
+ * each shape, *best (may be NULL) the chosen shape.  Results do not depend on
+ * the shape.                                                                  */
+int aparareal_autotune_fine(ap_ctx* ctx, const double* U_in, int batch, double dT, int steps, int precision,
+                            void* stream, double* shape_ms, int* best);
+
+/* The workgroup shape the context's fine batches use in this precision: its
+ * index (0..2), threads per workgroup and slices per workgroup (outputs may
+ * be NULL).                                                                    */
+int aparareal_fine_shape(ap_ctx* ctx, int precision, int* shape, int* threads, int* slices);
 
 /* Kernel timing (diagnostics, no effect on results).  While enabled, the
  * library brackets each of its own kernel launches with a pair of HIP events

@@ -39,7 +39,7 @@ class BatchItem(ctypes.Structure):
 
 
 AP_OPT_SPLIT, AP_OPT_GROUP, AP_OPT_GRID, AP_OPT_GRAPH, AP_OPT_SKIP, AP_OPT_SWEEPS = 0, 1, 2, 3, 4, 5
-AP_OPT_FINE, AP_OPT_COARSE, AP_OPT_FINE_GROUP = 6, 7, 8
+AP_OPT_FINE, AP_OPT_COARSE, AP_OPT_FINE_GROUP, AP_OPT_FINE_SHAPE = 6, 7, 8, 9
 JOB_COARSE, JOB_FINE, JOB_STAGE1, JOB_STAGE2, JOB_COPY = 0, 1, 2, 3, 4
 
 
@@ -61,6 +61,8 @@ _SIGNATURES = {
     "aparareal_solve_batch": (_i, [ctypes.POINTER(BatchItem), _i, _vp]),
     "aparareal_set_option": (_i, [_vp, _i, _i]),
     "aparareal_autotune": (_i, [ctypes.POINTER(BatchItem), _i, _vp, ctypes.POINTER(_d)]),
+    "aparareal_autotune_fine": (_i, [_vp, _dp, _i, _d, _i, _i, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i)]),
+    "aparareal_fine_shape": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "aparareal_get_option": (_i, [_vp, _i, ctypes.POINTER(_i)]),
     "aparareal_pipeline_schedule": (_i, [_i, ctypes.POINTER(SolveParams), _i, _i, _i, ctypes.POINTER(_i), _i]),
     "aparareal_pipeline_schedule_batch": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(SolveParams), _i, _i, _i,
@@ -245,6 +247,25 @@ class Context:
         """fine_batch through the entry point that allocates nothing (its
         scratch is the library's per-device array); `out` may be passed in."""
         return self._batched(lib().aparareal_fine_batch_noalloc, U, float(dT), int(steps), precision, out=out)
+
+    def autotune_fine(self, U, dT: float, steps: int, precision: int = AP_PREC_FP32):
+        """Time the fine batch's workgroup shapes on U, keep and cache the
+        fastest; returns (best shape, [mean ms per shape])."""
+        import torch
+        U = _states(U, self.N, "U")
+        ms = (ctypes.c_double * 3)()
+        best = ctypes.c_int(0)
+        _check(lib().aparareal_autotune_fine(self._h, ctypes.c_void_p(U.data_ptr()), U.numel() // (3 * self.N),
+                                             float(dT), int(steps), int(precision), _stream(torch), ms,
+                                             ctypes.byref(best)))
+        return best.value, list(ms)
+
+    def fine_shape(self, precision: int = AP_PREC_FP32) -> tuple[int, int, int]:
+        """(shape, threads per workgroup, slices per workgroup) of fine batches."""
+        sh, nt, j = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(lib().aparareal_fine_shape(self._h, int(precision), ctypes.byref(sh), ctypes.byref(nt),
+                                          ctypes.byref(j)))
+        return sh.value, nt.value, j.value
 
     def strang_batch(self, U, dT: float, steps: int, precision: int = AP_PREC_FP32, out=None):
         return self._batched(lib().aparareal_strang_batch, U, float(dT), int(steps), precision, out=out)

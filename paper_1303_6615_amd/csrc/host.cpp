@@ -16,14 +16,19 @@
 //     power for this kernel); rot[m][k] = exp(-i omega_k s_m);
 //   * coarse step (Alg. 2): hd[k] = exp(-nu k^4 dT/2), rotT[k] = exp(-i omega_k dT/eps).
 #include <hip/hip_runtime.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <queue>
 #include <string>
 #include <tuple>
@@ -179,6 +184,9 @@ struct ap_ctx {
   int opt_fine = 0;          // fine slices: 0 ETDRK4, 1 Strang steps (Alg. 3)
   int opt_coarse = 0;        // coarse step: 0 asymptotic (Alg. 2), 1 one Strang step (standard parareal)
   int opt_fine_group = 0;    // slices per fine job: 0 automatic, else at most this many
+  int opt_fine_shape = -1;   // workgroup shape of the fine batch: -1 tuned (or default), else 0..2
+  int tuned_shape[2] = {-1, -1};   // per precision: from aparareal_autotune_fine or the tuning cache
+  std::string device_key;          // device kind, the tuning cache's key
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;   // private stream the graph is captured on
@@ -315,6 +323,92 @@ int fine_tables(ap_ctx* c, double h, FineTables** out) {
   *out = ft.get();
   c->fine_cache[bits(h)] = std::move(ft);
   return AP_OK;
+}
+
+// ------------------------------------------------------------ tuning cache -
+// Persisted choices of aparareal_autotune_fine, one line per device, grid size
+// and precision:  "fine <device> <N> <precision> <shape>".  The file is
+// $APARAREAL_TUNE_CACHE, else $XDG_CACHE_HOME/aparareal/tune.txt, else
+// $HOME/.cache/aparareal/tune.txt; the last line for a key wins.  A missing or
+// unreadable file means no entries, and a failed write is ignored: a shape
+// only changes speed, never results.
+std::mutex g_tune_mu;
+
+std::string tune_cache_path() {
+  if (const char* p = std::getenv("APARAREAL_TUNE_CACHE")) return p;
+  if (const char* x = std::getenv("XDG_CACHE_HOME")) return std::string(x) + "/aparareal/tune.txt";
+  if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/aparareal/tune.txt";
+  return std::string();
+}
+
+// Identifies the device kind: architecture name and compute-unit count.
+std::string device_key(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string k = prop.gcnArchName;
+  for (char& ch : k)
+    if (ch == ' ') ch = '_';
+  return k + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+}
+
+std::vector<std::string> read_lines(const std::string& path) {
+  std::vector<std::string> out;
+  if (path.empty()) return out;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return out;
+  char buf[512];
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string ln(buf);
+    while (!ln.empty() && (ln.back() == '\n' || ln.back() == '\r')) ln.pop_back();
+    if (!ln.empty()) out.push_back(ln);
+  }
+  std::fclose(f);
+  return out;
+}
+
+// The cached shape for (device, N, precision), or -1.
+int tune_lookup(const std::string& dev, int N, int precision) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const std::string key = "fine " + dev + " " + std::to_string(N) + " " + std::to_string(precision) + " ";
+  int shape = -1;
+  for (const std::string& ln : read_lines(tune_cache_path()))
+    if (ln.compare(0, key.size(), key) == 0) {
+      const int v = std::atoi(ln.c_str() + key.size());
+      if (v >= 0 && v < ap::kFineShapeCount) shape = v;
+    }
+  return shape;
+}
+
+void tune_store(const std::string& dev, int N, int precision, int shape) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  const std::string key = "fine " + dev + " " + std::to_string(N) + " " + std::to_string(precision) + " ";
+  std::vector<std::string> keep;
+  for (const std::string& ln : read_lines(path))
+    if (ln.compare(0, key.size(), key) != 0) keep.push_back(ln);
+  keep.push_back(key + std::to_string(shape));
+  // create the directory chain, then write a temporary file and rename it
+  for (size_t i = 1; i < path.size(); ++i)
+    if (path[i] == '/') {
+      const std::string d = path.substr(0, i);
+      (void)mkdir(d.c_str(), 0755);
+    }
+  const std::string tmp = path + ".tmp" + std::to_string(getpid());
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const std::string& ln : keep) std::fprintf(f, "%s\n", ln.c_str());
+  const bool ok = std::fclose(f) == 0;
+  if (ok) (void)std::rename(tmp.c_str(), path.c_str());
+  else (void)std::remove(tmp.c_str());
+}
+
+// Workgroup shape of the context's fine batches in this precision: the option
+// if set, else the tuned shape, else the default.
+int fine_shape_of(const ap_ctx* c, int precision) {
+  if (c->opt_fine_shape >= 0) return c->opt_fine_shape;
+  const int t = c->tuned_shape[precision == AP_PREC_FP64 ? 1 : 0];
+  return t >= 0 ? t : 0;
 }
 
 // Samples per group of the time average: as many as make one round of
@@ -1105,6 +1199,8 @@ ap_ctx* aparareal_create(int N, double eps, double F, double nu) {
     hip_fail(e, "hipGetDevice");
     return nullptr;
   }
+  c->device_key = device_key(c->device);
+  for (int prec = 0; prec < 2; ++prec) c->tuned_shape[prec] = tune_lookup(c->device_key, N, prec);
   c->omega.resize(c->KP);
   c->akw.resize(c->KP);
   c->na_t64.resize(size_t(8) * 3 * c->KP);
@@ -1184,10 +1280,67 @@ int aparareal_fine_batch(ap_ctx* c, const double* U_in, double* U_out, int batch
   const bool f64 = precision == AP_PREC_FP64;
   hipError_t e = timed(c, AP_K_FINE, s, [&] {
     return ap::launch_fine(c->N, f64, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(), batch, steps,
-                           ft->coef64.as<cx<double>>(), ft->coef32.as<cx<float>>(), c->tabs, s);
+                           ft->coef64.as<cx<double>>(), ft->coef32.as<cx<float>>(), c->tabs, s,
+                           fine_shape_of(c, precision));
   });
   if (e != hipSuccess) return hip_fail(e, "fine launch");
   return batch_epilogue(c, U_out, batch, s);
+}
+
+int aparareal_fine_shape(ap_ctx* c, int precision, int* shape, int* threads, int* slices) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = check_prec(precision))) return rc;
+  const int sh = fine_shape_of(c, precision);
+  int j = 0;
+  const int nt = ap::fine_shape(c->N, precision == AP_PREC_FP64, sh, &j);
+  if (shape) *shape = sh;
+  if (threads) *threads = nt;
+  if (slices) *slices = j;
+  return AP_OK;
+}
+
+int aparareal_autotune_fine(ap_ctx* c, const double* U_in, int batch, double dT, int steps, int precision,
+                            void* stream, double* shape_ms, int* best) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c && !(dT > 0.0 && std::isfinite(dT))) return fail(AP_EINVAL, "dT must be > 0");
+  if (c && steps < 1) return fail(AP_EINVAL, "steps must be >= 1");
+  if (c && batch < 1) return fail(AP_EINVAL, "batch must be >= 1");
+  // the prologue checks an output pointer; the tuning runs write only the workspace
+  int rc = batch_prologue(c, U_in, const_cast<double*>(U_in), batch, precision, s);
+  if (rc) return rc;
+  FineTables* ft = nullptr;
+  if ((rc = fine_tables(c, dT / steps, &ft))) return rc;
+  const bool f64 = precision == AP_PREC_FP64;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  double ms[ap::kFineShapeCount];
+  int pick = 0;
+  for (int sh = 0; e == hipSuccess && sh < ap::kFineShapeCount; ++sh) {
+    auto run = [&] {
+      return ap::launch_fine(c->N, f64, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(), batch, steps,
+                             ft->coef64.as<cx<double>>(), ft->coef32.as<cx<float>>(), c->tabs, s, sh);
+    };
+    e = run();                                   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int r = 0; e == hipSuccess && r < 3; ++r) e = run();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float el = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&el, a, b);
+    ms[sh] = double(el) / 3.0;
+    if (e == hipSuccess && ms[sh] < ms[pick]) pick = sh;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e != hipSuccess) return hip_fail(e, "fine shape tuning");
+  c->tuned_shape[f64 ? 1 : 0] = pick;
+  tune_store(c->device_key, c->N, precision, pick);
+  if (shape_ms)
+    for (int sh = 0; sh < ap::kFineShapeCount; ++sh) shape_ms[sh] = ms[sh];
+  if (best) *best = pick;
+  return AP_OK;
 }
 
 // The fine batch with every scratch byte in the library's per-device scratch
@@ -1232,8 +1385,8 @@ int aparareal_fine_batch_noalloc(ap_ctx* c, const double* U_in, double* U_out, i
     return hip_fail(e, "coefficient copy");
   if ((e = ap::launch_to_modal(c->N, U_in, in, batch, c->tabs, s)) != hipSuccess)
     return hip_fail(e, "to_modal launch");
-  if ((e = ap::launch_fine(c->N, precision == AP_PREC_FP64, in, out, batch, steps, coef64, coef32, c->tabs, s)) !=
-      hipSuccess)
+  if ((e = ap::launch_fine(c->N, precision == AP_PREC_FP64, in, out, batch, steps, coef64, coef32, c->tabs, s,
+                           fine_shape_of(c, precision))) != hipSuccess)
     return hip_fail(e, "fine launch");
   if ((e = ap::launch_to_physical(c->N, out, U_out, batch, c->tabs, s)) != hipSuccess)
     return hip_fail(e, "to_physical launch");
@@ -1504,6 +1657,10 @@ int aparareal_set_option(ap_ctx* c, int option, int value) {
       if (value < 0 || value > 1) return fail(AP_EINVAL, "AP_OPT_COARSE takes 0 (asymptotic) or 1 (Strang)");
       c->opt_coarse = value;
       return AP_OK;
+    case AP_OPT_FINE_SHAPE:
+      if (value < -1 || value >= ap::kFineShapeCount) return fail(AP_EINVAL, "AP_OPT_FINE_SHAPE takes -1, 0, 1 or 2");
+      c->opt_fine_shape = value;
+      return AP_OK;
     default:
       return fail(AP_EINVAL, "unknown option");
   }
@@ -1523,6 +1680,7 @@ int aparareal_get_option(ap_ctx* c, int option, int* value) {
     case AP_OPT_FINE: *value = c->opt_fine; return AP_OK;
     case AP_OPT_COARSE: *value = c->opt_coarse; return AP_OK;
     case AP_OPT_FINE_GROUP: *value = c->opt_fine_group; return AP_OK;
+    case AP_OPT_FINE_SHAPE: *value = c->opt_fine_shape; return AP_OK;
     default: return fail(AP_EINVAL, "unknown option");
   }
 }

@@ -3,8 +3,8 @@
 //   k_to_modal / k_to_physical : FP64 boundary transforms, physical grid values
 //                                <-> modal amplitudes of the retained band
 //   k_nonlinear                : dealiased N (Sec. 6.1)
-//   k_fine                     : ETDRK4 over `steps` steps, one slice per workgroup
-//                                (the parallel fine sweep of Alg. 4)
+//   k_fine                     : (fine_*.hip) ETDRK4 over `steps` steps, the
+//                                parallel fine sweep of Alg. 4
 //   k_average                  : kernel-weighted time average (eq. numerical
 //                                average; Alg. 1), samples in flight together
 //   k_coarse                   : one asymptotic coarse step per state (Alg. 2)
@@ -20,36 +20,11 @@
 #include <algorithm>
 
 #include "dispatch.hpp"
+#include "fine_kernel.hpp"
 #include "pipeline.hpp"
 
 namespace ap {
 
-// Fine batches: workgroups small enough that several share a CU (VGPRs and
-// LDS permitting), each stepping as many slices as its threads own modes
-// and its wavefronts transform in one round (Engine::jmax), with two slots
-// per slice.  Threads per workgroup by precision and grid size, measured on
-// MI355X over 5120-slice batches (FP32: 128 / 192 / 192 / 192 / 384 / 704
-// for N = 64 .. 2048; FP64: 256 / 256 / 512 / 256 / 384 / 704).
-template <typename T, int NX>
-constexpr int fine_threads() {
-  if constexpr (sizeof(T) == 4) return NX == 64 ? 128 : NX <= 512 ? 192 : NX == 1024 ? 384 : 704;
-  else return NX <= 128 ? 256 : NX == 256 ? 512 : NX == 512 ? 256 : NX == 1024 ? 384 : 704;
-}
-template <typename T, int NX, int NT>
-constexpr int fine_slots() {
-  constexpr int KP = Geo<NX>::KP;
-  constexpr int MPT = (KP + NT - 1) / NT;
-  int j = MPT > 1 ? 1 : NT / KP;
-  const int by_waves = (NT / 64) * (64 / WavePlan<NX / 2>::G) / 3;
-  j = j < by_waves ? j : by_waves;
-  j = j < 16 ? (j > 0 ? j : 1) : 16;
-  const int s = max_slots<T, NX, NT>();
-  return 2 * j < s ? 2 * j : s;
-}
-template <typename T, int NX>
-constexpr int fine_slices() {
-  return Engine<T, NX, fine_threads<T, NX>(), fine_slots<T, NX, fine_threads<T, NX>()>()>::jmax();
-}
 // ------------------------------------------------- boundary transforms -----
 // physical [B][3][N] float64 -> modal [B][3][KP] complex float64 (projected)
 template <int NX, int NT>
@@ -154,27 +129,6 @@ __global__ void __launch_bounds__(NT) k_nonlinear(const cx<double>* __restrict__
   for (int j = 0; j < E_::MPT; ++j)
     if (E_::valid(j))
       for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = cvt<double>(n[j][al]);
-}
-
-// ------------------------------------------------------------ fine batch ---
-// Workgroup b steps slices b J .. min(b J + J, batch) - 1 (J = fine_slices).
-#ifndef AP_FINE_WAVES_PER_EU
-#define AP_FINE_WAVES_PER_EU 1
-#endif
-template <typename T, int NX, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(AP_FINE_WAVES_PER_EU))) k_fine(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
-                                             int batch, int steps, const cx<double>* __restrict__ coef64,
-                                             const cx<T>* __restrict__ coef, const cx<T>* __restrict__ tw,
-                                             const Basis<T>* __restrict__ basis) {
-  constexpr int S = fine_slots<T, NX, NT>();
-  using E_ = Engine<T, NX, NT, S>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  E_ en(smem_raw, tw);
-  const size_t st = size_t(3) * E_::KP;
-  const int first = blockIdx.x * E_::jmax();
-  const int J = min(E_::jmax(), batch - first);
-  fine_job<T, NX, NT, S>(en, J, Uin + first * st, Uin + (first + 1) * st, Uout + first * st, steps, coef64, coef,
-                         basis);
 }
 
 template <typename T, int NX, int NT>
@@ -338,18 +292,6 @@ static hipError_t nonlinear_nx(const cx<double>* in, cx<double>* out, int batch,
 }
 
 template <typename T, int NX>
-static hipError_t fine_nx(const cx<double>* in, cx<double>* out, int batch, int steps, const cx<double>* coef64,
-                          const cx<T>* coef, const DevTables& t, hipStream_t s) {
-  constexpr int NT = fine_threads<T, NX>();
-  const size_t lds = Engine<T, NX, NT, fine_slots<T, NX, NT>()>::lds_bytes();
-  const int J = fine_slices<T, NX>();
-  prep_lds(k_fine<T, NX, NT>, lds);
-  hipLaunchKernelGGL((k_fine<T, NX, NT>), dim3((batch + J - 1) / J), dim3(NT), lds, s, in, out, batch, steps, coef64,
-                     coef, t.tw<T>(), t.basis<T>());
-  return hipGetLastError();
-}
-
-template <typename T, int NX>
 static hipError_t strang_nx(const cx<double>* in, cx<double>* out, int batch, int steps, double h,
                             const cx<double>* coef64, const DevTables& t, hipStream_t s) {
   constexpr int NT = fine_threads<T, NX>();
@@ -409,9 +351,10 @@ hipError_t launch_nonlinear(int nx, bool fp64, const cx<double>* in, cx<double>*
   AP_DISPATCH_NX(nx, (nonlinear_nx<float, NX>(in, out, batch, t, s)));
 }
 hipError_t launch_fine(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch, int steps,
-                       const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s) {
-  if (fp64) AP_DISPATCH_NX(nx, (fine_nx<double, NX>(in, out, batch, steps, coef64, coef64, t, s)));
-  AP_DISPATCH_NX(nx, (fine_nx<float, NX>(in, out, batch, steps, coef64, coef32, t, s)));
+                       const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s,
+                       int shape) {
+  return fp64 ? launch_fine_f64(nx, shape, in, out, batch, steps, coef64, t, s)
+              : launch_fine_f32(nx, shape, in, out, batch, steps, coef64, coef32, t, s);
 }
 hipError_t launch_strang(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch, int steps, double h,
                          const cx<double>* coef64, const DevTables& t, hipStream_t s) {

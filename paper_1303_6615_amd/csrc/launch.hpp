@@ -98,8 +98,22 @@ hipError_t launch_to_physical(int nx, const cx<double>* modal, double* phys, int
                               hipStream_t s);
 hipError_t launch_nonlinear(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch,
                             const DevTables& t, hipStream_t s);
+// The fine batch in workgroup shape `shape` (0 .. 2; 0 the default); the
+// shape changes no result.
 hipError_t launch_fine(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch, int steps,
-                       const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s);
+                       const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s,
+                       int shape = 0);
+hipError_t launch_fine_f32(int nx, int shape, const cx<double>* in, cx<double>* out, int batch, int steps,
+                           const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s);
+hipError_t launch_fine_f64(int nx, int shape, const cx<double>* in, cx<double>* out, int batch, int steps,
+                           const cx<double>* coef64, const DevTables& t, hipStream_t s);
+// Threads per workgroup of a fine-batch shape (0 if none) and its slices per workgroup.
+int fine_shape_f32(int nx, int shape, int* slices);
+int fine_shape_f64(int nx, int shape, int* slices);
+inline int fine_shape(int nx, bool fp64, int shape, int* slices) {
+  return fp64 ? fine_shape_f64(nx, shape, slices) : fine_shape_f32(nx, shape, slices);
+}
+constexpr int kFineShapeCount = 3;
 // `steps` Strang steps of size h (coef64 slot 2: e^{(h/2) lambda}) per state.
 hipError_t launch_strang(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch, int steps, double h,
                          const cx<double>* coef64, const DevTables& t, hipStream_t s);

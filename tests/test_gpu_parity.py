@@ -581,3 +581,69 @@ def test_paper_experiment_replay_converges(torch_cuda):
         assert all(e[k + 1] < e[k] for k in range(len(e) - 1)), (method, e)
         assert e[-1] < 1e-3, (method, e)
         assert out[method]["tau_f_us"] > 0 and out[method]["measured_speedup_k5"] > 1
+
+
+def test_replay_asymptotic_configuration_matches_the_oracle(torch_cuda):
+    # the replay's eps = 1e-1 asymptotic parareal (Sec. 6.2 parameters as the
+    # replay reads them: analytic height, N = 128, mu = 1e-4, dT = 3 eps,
+    # Strang fine steps of eps/25 (Alg. 3), 150 slices, Mbar = 10, slow window
+    # 5 eps, K = 5) through the pipelined launch, FP64, against the oracle's
+    # Alg. 4 with the same fine and coarse solvers (Alg. 2 coarse step)
+    from oracle.strang import strang_propagate
+    from paper_1303_6615_amd.binding import AP_OPT_COARSE, AP_OPT_FINE
+    from paper_1303_6615_amd.inputs import paper_height_state
+    from paper_1303_6615_amd.replay import CASES, K_MAX, NU, NX
+    torch = torch_cuda
+    eps = 0.1
+    c = CASES[eps]
+    T, S, dT = c["slices"] * c["adT"], c["slices"], c["adT"]
+    steps = int(np.ceil(dT / c["adt"] - 1e-9))
+    T0 = c["window"] / eps
+    u0 = paper_height_state(NX)
+    Uref, rref, _ = O.parareal_solve(u0, NX, eps, 1.0, NU, T, S, K_MAX, steps, c["Mbar"], T0,
+                                     fine=lambda v: strang_propagate(v, NX, eps, 1.0, NU, dT, steps))
+    with _ctx(NX, eps, NU) as ctx:
+        ctx.set_option(AP_OPT_FINE, 1)
+        ctx.set_option(AP_OPT_COARSE, 0)
+        U, r = ctx.solve(torch.tensor(u0, device="cuda"), T, S, K_MAX, c["adt"], c["Mbar"], T0=T0, precision=FP64)
+        torch.cuda.synchronize()
+    U, r = U.cpu().numpy(), r.cpu().numpy()
+    assert _rel(U, Uref) < 1e-11
+    assert np.all(np.abs(r - np.array(rref)) <= 1e-6 * np.array(rref) + 1e-13), (r, rref)
+
+
+@pytest.mark.parametrize("n,eps,dT,steps,prec,tol", [
+    (256, 0.01, 0.03125, 8, FP32, 2e-5), (1024, 0.001, 1.0 / 256, 6, FP32, 2e-5),
+    (64, 0.01, 1.0 / 16, 9, FP64, 1e-11), (2048, 0.01, 0.01, 3, FP64, 1e-11)])
+def test_fine_batch_shapes_and_their_autotuner(torch_cuda, tmp_path, monkeypatch, n, eps, dT, steps, prec, tol):
+    # every compiled workgroup shape of the fine batch gives the same bits
+    # (a slice rounds the same way whatever workgroup steps it) and the
+    # oracle's values; the autotuner keeps the fastest, records it in the
+    # tuning cache, and a new context reads it back
+    from paper_1303_6615_amd.binding import AP_OPT_FINE_SHAPE
+    torch = torch_cuda
+    monkeypatch.setenv("APARAREAL_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    nu = NU_BY_NX[n]
+    u = _states(n, 37, 17 * n)
+    ud = torch.tensor(u, device="cuda")
+    uh = O.project(O.to_spectral(u[:4]), n)
+    ref = O.to_physical(O.fine_propagate(uh, n, eps, 1.0, nu, dT, steps), n)
+    with _ctx(n, eps, nu) as ctx:
+        outs, shapes = [], []
+        for sh in range(3):
+            ctx.set_option(AP_OPT_FINE_SHAPE, sh)
+            outs.append(ctx.fine_batch(ud, dT, steps, precision=prec))
+            shapes.append(ctx.fine_shape(prec))
+        torch.cuda.synchronize()
+        assert len({s[1] for s in shapes}) == 3, shapes           # three distinct workgroup sizes
+        for o in outs[1:]:
+            assert torch.equal(o, outs[0])
+        assert _rel(outs[0][:4].cpu().numpy(), ref) < tol
+        ctx.set_option(AP_OPT_FINE_SHAPE, -1)
+        best, ms = ctx.autotune_fine(ud, dT, steps, precision=prec)
+        assert best in (0, 1, 2) and all(m > 0 for m in ms) and ms[best] == min(ms)
+        assert ctx.fine_shape(prec)[0] == best
+        assert torch.equal(ctx.fine_batch(ud, dT, steps, precision=prec), outs[0])
+    with _ctx(n, eps, nu) as fresh:
+        assert fresh.fine_shape(prec)[0] == best
+    assert f" {n} {prec} {best}" in (tmp_path / "tune.txt").read_text()
