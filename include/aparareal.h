@@ -253,6 +253,15 @@ int aparareal_autotune_fine(ap_ctx* ctx, const double* U_in, int batch, double d
  * be NULL).                                                                    */
 int aparareal_fine_shape(ap_ctx* ctx, int precision, int* shape, int* threads, int* slices);
 
+/* Measured rates of the current device that the hot path is priced against
+ * (diagnostics): FP32 and FP64 vector FMA throughput in TFLOP/s (16
+ * independent FMA chains per lane, 16 workgroups of 256 threads per CU; FP32
+ * without packed instructions, as the library is built) and LDS read
+ * bandwidth in TB/s (conflict-free 64-bit reads by every lane).  Allocates
+ * and frees an 8-16 MiB scratch buffer and synchronises `stream`.  Outputs
+ * are host doubles.                                                          */
+int aparareal_measure_peaks(void* stream, double* fp32_tflops, double* fp64_tflops, double* lds_tbps);
+
 /* Kernel timing (diagnostics, no effect on results).  While enabled, the
  * library brackets each of its own kernel launches with a pair of HIP events
  * recorded on the launch stream and accumulates the elapsed time per kernel

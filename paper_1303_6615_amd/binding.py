@@ -63,6 +63,7 @@ _SIGNATURES = {
     "aparareal_autotune": (_i, [ctypes.POINTER(BatchItem), _i, _vp, ctypes.POINTER(_d)]),
     "aparareal_autotune_fine": (_i, [_vp, _dp, _i, _d, _i, _i, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i)]),
     "aparareal_fine_shape": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "aparareal_measure_peaks": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "aparareal_get_option": (_i, [_vp, _i, ctypes.POINTER(_i)]),
     "aparareal_pipeline_schedule": (_i, [_i, ctypes.POINTER(SolveParams), _i, _i, _i, ctypes.POINTER(_i), _i]),
     "aparareal_pipeline_schedule_batch": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(SolveParams), _i, _i, _i,
@@ -177,6 +178,15 @@ def autotune(problems, precision: int = AP_PREC_FP32) -> float:
     _check(lib().aparareal_autotune(items, len(problems), _stream(torch), ctypes.byref(ms)))
     torch.cuda.synchronize()
     return ms.value
+
+
+def measure_peaks() -> dict:
+    """Measured FP32 / FP64 vector FMA rates (TFLOP/s) and LDS read bandwidth
+    (TB/s) of the current device (microbenchmark kernels in the library)."""
+    import torch
+    a, b, c = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().aparareal_measure_peaks(_stream(torch), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return {"fp32_tflops": a.value, "fp64_tflops": b.value, "lds_tbps": c.value}
 
 
 def _check(rc: int) -> int:

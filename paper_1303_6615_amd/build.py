@@ -23,7 +23,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libaparareal.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 SOURCES = ["kernels.hip", "fine_f32.hip", "fine_f64.hip", "pipe_f32.hip", "pipe_f64.hip", "pipe_mix1024_f32.hip", "pipe_mix2048_f32.hip",
-           "pipe_mix2048_f64.hip", "noalloc.hip", "host.cpp", "server.cpp"]
+           "pipe_mix2048_f64.hip", "noalloc.hip", "peaks.hip", "host.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

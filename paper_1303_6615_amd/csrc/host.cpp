@@ -1287,6 +1287,23 @@ int aparareal_fine_batch(ap_ctx* c, const double* U_in, double* U_out, int batch
   return batch_epilogue(c, U_out, batch, s);
 }
 
+int aparareal_measure_peaks(void* stream, double* fp32_tflops, double* fp64_tflops, double* lds_tbps) {
+  if (!fp32_tflops || !fp64_tflops || !lds_tbps) return fail(AP_EINVAL, "null output");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "device query");
+  const size_t bytes = size_t(cus) * 16 * 256 * sizeof(double);
+  void* scratch = nullptr;
+  if ((e = hipMalloc(&scratch, bytes)) != hipSuccess) return hip_fail(e, "peak scratch");
+  e = ap::measure_peaks(scratch, bytes, s, fp32_tflops, fp64_tflops, lds_tbps);
+  const hipError_t f = hipFree(scratch);
+  if (e != hipSuccess) return hip_fail(e, "peak kernels");
+  if (f != hipSuccess) return hip_fail(f, "peak scratch free");
+  return AP_OK;
+}
+
 int aparareal_fine_shape(ap_ctx* c, int precision, int* shape, int* threads, int* slices) {
   int rc = check_ctx(c);
   if (rc) return rc;

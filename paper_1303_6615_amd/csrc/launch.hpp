@@ -150,6 +150,11 @@ AP_PIPE_TU(mix2048_f64)
 #undef AP_PIPE_TU
 
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+// FP32 / FP64 vector FMA throughput (TFLOP/s) and LDS read bandwidth (TB/s)
+// of the current device, from microbenchmark kernels writing to `scratch`
+// (at least 16 x CUs x 256 doubles); synchronises `s`.
+hipError_t measure_peaks(void* scratch, size_t scratch_bytes, hipStream_t s, double* fp32_tflops,
+                         double* fp64_tflops, double* lds_tbps);
 // out[r] = max_n sqrt(part[r][n].x / part[r][n].y) for r < rows; NaN if *abort
 hipError_t launch_resid(const double2* part, int Ns, int rows, double* out, const int* abort, hipStream_t s);
 // Residual rows of several problems in one launch: row r reads Ns[r] partial
