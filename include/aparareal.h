@@ -332,8 +332,10 @@ int aparareal_pipeline_trace(ap_ctx* ctx, int enable, long long* out, int max_jo
  * launch per batch, as aparareal_solve_batch) and up to four batches run at
  * once on separate streams, so requests that arrive while others are on the
  * device start as soon as memory and slots free up, and their work overlaps.
- * Each request's states stay in device memory for its whole solve.  A
- * request's result does not depend on what it was batched with.
+ * Each request's states stay in device memory for its whole solve; its
+ * coarse steps run whole (one workgroup each, AP_OPT_SPLIT 0), since a batch
+ * already fills the device with independent jobs.  A request's result does
+ * not depend on what it was batched with, and equals aparareal_solve's.
  * One worker thread owns the device work; submit, poll and stats may be
  * called from any thread.                                                   */
 typedef struct ap_server ap_server;

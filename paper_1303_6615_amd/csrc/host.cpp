@@ -28,6 +28,7 @@
 #include <limits>
 #include <map>
 #include <memory>
+#include <deque>
 #include <mutex>
 #include <queue>
 #include <string>
@@ -702,7 +703,8 @@ bool order_is_valid(const std::vector<ap::PipeJob>& jobs, const std::vector<Pipe
 struct JobDag {
   std::vector<ap::PipeJob> job;
   std::vector<double> dur;
-  std::vector<int> pred_begin;   // CSR: preds of job i at pred[pred_begin[i] .. pred_begin[i+1])
+  std::vector<char> virt;        // 1: a join point (no job, no duration, no workgroup)
+  std::vector<int> pred_begin;   // CSR: preds of node i at pred[pred_begin[i] .. pred_begin[i+1])
   std::vector<int> pred;
 };
 
@@ -716,27 +718,25 @@ struct JobDag {
 //   fine F(k,n..n+g-1):   C(k,n+g-2) (its last input; the chain orders the rest)
 // C(k,n) is complete when its whole or copy job, or every stage-2 job, is.
 // With a tolerance, the jobs completing C(k,Ns) also wait for the copies of
-// level k (they read their residual parts).
+// level k (they read their residual parts).  A split step gets two join
+// points (after its stage-1 jobs; after its stage-2 jobs, its completion), so
+// that the graph has a few edges per job instead of one per pair of group jobs.
 void problem_dag(int prob, const PipeShape& q, JobDag& d) {
   const JobCost jc = job_cost(q);
   const int Ns = q.Ns, K = q.K, fg = std::max(1, q.fg);
   const size_t cells = size_t(K + 1) * Ns;
-  std::vector<int> cfirst(cells, -1), clast(cells, -1), fjob(cells, -1);
+  std::vector<int> cnode(cells, -1), fjob(cells, -1);   // node completing C(k,n); fine job of F(k,n)
   auto at = [&](int k, int n) { return size_t(k) * Ns + n - 1; };
   std::vector<int> deps;
-  auto comp = [&](int k, int n) {   // the jobs completing C(k,n)
-    const int a = cfirst[at(k, n)], b = clast[at(k, n)];
-    const bool split = d.job[a].type == ap::kJobStage1;
-    for (int i = split ? a : b; i <= b; ++i)
-      if (d.job[i].type != ap::kJobStage1) deps.push_back(i);
-  };
+  auto comp = [&](int k, int n) { deps.push_back(cnode[at(k, n)]); };
   auto copies = [&](int k, int n) {
     if (!(q.tol > 0.0) || !q.skip || k < 1 || n != Ns) return;
     for (int m = 1; m <= std::min(k, Ns - 1); ++m) comp(k, m);
   };
-  auto add = [&](ap::PipeJob j, double dur) {
+  auto add = [&](ap::PipeJob j, double dur, bool v) {
     d.job.push_back(j);
-    d.dur.push_back(dur);
+    d.dur.push_back(v ? 0.0 : dur);
+    d.virt.push_back(v ? 1 : 0);
     d.pred.insert(d.pred.end(), deps.begin(), deps.end());
     d.pred_begin.push_back(int(d.pred.size()));
     deps.clear();
@@ -748,28 +748,29 @@ void problem_dag(int prob, const PipeShape& q, JobDag& d) {
         comp(k - 1, n);
         if (n == k) deps.push_back(fjob[at(k - 1, n)]);
         copies(k, n);
-        cfirst[at(k, n)] = clast[at(k, n)] = add({prob, ap::kJobCopy, k, n, 0}, 1.0);
+        cnode[at(k, n)] = add({prob, ap::kJobCopy, k, n, 0}, 1.0, false);
         continue;
       }
       if (q.split) {
-        int first = -1;
+        const int first = int(d.job.size());
         for (int g = 0; g < q.groups; ++g) {
           if (n > 1) comp(k, n - 1);
-          const int i = add({prob, ap::kJobStage1, k, n, g}, jc.stage1);
-          if (g == 0) first = i;
+          add({prob, ap::kJobStage1, k, n, g}, jc.stage1, false);
         }
-        int last = -1;
+        for (int g = 0; g < q.groups; ++g) deps.push_back(first + g);
+        const int j1 = add({prob, ap::kJobStage1, k, n, -1}, 0.0, true);
+        const int s2 = int(d.job.size());
         for (int g = 0; g < q.groups; ++g) {
-          for (int x = 0; x < q.groups; ++x) deps.push_back(first + x);
+          deps.push_back(j1);
           if (k >= 1) {
             deps.push_back(fjob[at(k - 1, n)]);
             comp(k - 1, n);
           }
           copies(k, n);
-          last = add({prob, ap::kJobStage2, k, n, g}, jc.stage2 + jc.finish);
+          add({prob, ap::kJobStage2, k, n, g}, jc.stage2 + jc.finish, false);
         }
-        cfirst[at(k, n)] = first;
-        clast[at(k, n)] = last;
+        for (int g = 0; g < q.groups; ++g) deps.push_back(s2 + g);
+        cnode[at(k, n)] = add({prob, ap::kJobStage2, k, n, -1}, 0.0, true);
       } else {
         if (n > 1) comp(k, n - 1);
         if (k >= 1) {
@@ -777,25 +778,35 @@ void problem_dag(int prob, const PipeShape& q, JobDag& d) {
           comp(k - 1, n);
         }
         copies(k, n);
-        cfirst[at(k, n)] = clast[at(k, n)] = add({prob, ap::kJobCoarse, k, n, 0}, jc.whole);
+        cnode[at(k, n)] = add({prob, ap::kJobCoarse, k, n, 0}, jc.whole, false);
       }
     }
     if (k == K) break;
     for (int n = q.skip && k >= 1 ? k + 1 : 1; n <= Ns; n += fg) {
       const int g = std::min(fg, Ns - n + 1);
       if (n + g - 2 >= 1) comp(k, n + g - 2);
-      const int i = add({prob, ap::kJobFine, k, n, g}, jc.fine);
+      const int i = add({prob, ap::kJobFine, k, n, g}, jc.fine, false);
       for (int x = 0; x < g; ++x) fjob[at(k, n + x)] = i;
     }
   }
 }
 
+// Delay assumed between a job's end and the start of a job waiting on it
+// (us): the producer's release, the consumer's poll and acquire, and the
+// spread of a split step's group jobs.  A single hand-off measures 1.3-3.4 us
+// on MI355X; as a scheduling weight, 6 us gave the shortest solves in a scan
+// of 0-20 us (N = 256 with 64 slices: 5.19 -> 4.7 ms; N = 1024 with 256
+// slices: 17.5 -> 15.6 ms; the 64-problem batch unchanged).  It lengthens
+// the chains of many short dependent jobs, so their jobs get priority.
+constexpr double kHandoffUs = 6.0;
+
 // Hand-out order of the jobs of several problems on `workers` resident
-// workgroups: a list schedule simulated with the jobs' duration estimates.
-// Whenever a workgroup is free it takes, among the jobs whose dependencies
-// have completed, the one with the longest remaining path to the end of its
-// problem (its own duration plus the longest chain of jobs that wait on it,
-// the "bottom level"); the jobs are handed out in the order the simulation
+// workgroups: a list schedule simulated with the jobs' duration estimates and
+// a hand-off delay kHandoffUs per dependency.  Whenever a workgroup is free
+// it takes, among the jobs whose dependencies' results have arrived, the one
+// with the longest remaining path to the end of its problem (its own
+// duration plus the longest chain of jobs and hand-offs that wait on it, the
+// "bottom level"); the jobs are handed out in the order the simulation
 // starts them.  Long chains (long fine steps or many slices) thus start
 // first and are not stretched by the jobs of short problems, while every
 // workgroup is kept busy.  The order is topological by construction.
@@ -804,7 +815,9 @@ std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes, int
   d.pred_begin.push_back(0);
   for (size_t p = 0; p < shapes.size(); ++p) problem_dag(int(p), shapes[p], d);
   const int nj = int(d.job.size());
-  // successors (CSR) and bottom levels (jobs were appended in a topological order)
+  // successors (CSR) and bottom levels (nodes were appended in a topological
+  // order); a hand-off delay separates a job from each job that waits on it
+  // (through a join point or directly)
   std::vector<int> nsucc(size_t(nj) + 1, 0), npred(nj, 0);
   for (int i = 0; i < nj; ++i) {
     npred[i] = d.pred_begin[i + 1] - d.pred_begin[i];
@@ -814,26 +827,62 @@ std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes, int
   std::vector<int> succ(d.pred.size()), fill(nsucc.begin(), nsucc.end() - 1);
   for (int i = 0; i < nj; ++i)
     for (int x = d.pred_begin[i]; x < d.pred_begin[i + 1]; ++x) succ[fill[d.pred[x]]++] = i;
+  auto edge = [&](int to) { return d.virt[to] ? 0.0 : kHandoffUs; };
   std::vector<double> bl(nj, 0.0);
   for (int i = nj - 1; i >= 0; --i) {
     double m = 0.0;
-    for (int x = nsucc[i]; x < nsucc[i + 1]; ++x) m = std::max(m, bl[succ[x]]);
+    for (int x = nsucc[i]; x < nsucc[i + 1]; ++x) m = std::max(m, edge(succ[x]) + bl[succ[x]]);
     bl[i] = d.dur[i] + m;
   }
   // event simulation: ready jobs by bottom level (ties: earlier in the list),
-  // running jobs by end time
+  // running jobs by end time, jobs waiting for their inputs to arrive by time
   auto later = [&](int a, int b) { return bl[a] != bl[b] ? bl[a] < bl[b] : a > b; };
   std::priority_queue<int, std::vector<int>, decltype(later)> ready(later);
   using Ev = std::pair<double, int>;
   std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> running;
+  // Jobs whose dependencies have completed, waiting for the results to
+  // arrive: a job released at event time t gets t + kHandoffUs, and events
+  // are processed in time order, so this queue is in time order already.
+  std::deque<Ev> pending;
+  std::vector<double> avail(nj, 0.0);   // when the last dependency's result reaches the node
+  std::vector<Ev> stack;
+  // node i has completed at time t: release its successors (join points
+  // complete at once, without a workgroup)
+  auto complete = [&](int i, double t) {
+    stack.assign(1, Ev{t, i});
+    while (!stack.empty()) {
+      const int u = stack.back().second;
+      const double tu = stack.back().first;
+      stack.pop_back();
+      for (int x = nsucc[u]; x < nsucc[u + 1]; ++x) {
+        const int v = succ[x];
+        avail[v] = std::max(avail[v], tu + edge(v));
+        if (--npred[v] > 0) continue;
+        if (d.virt[v]) {
+          stack.push_back({avail[v], v});
+        } else {
+          pending.push_back({avail[v], v});
+        }
+      }
+    }
+  };
   for (int i = 0; i < nj; ++i)
-    if (npred[i] == 0) ready.push(i);
+    if (npred[i] == 0) {
+      if (d.virt[i]) complete(i, 0.0);
+      else pending.push_back({0.0, i});
+    }
   std::vector<ap::PipeJob> out;
-  out.reserve(nj);
+  int njobs = 0;
+  for (int i = 0; i < nj; ++i) njobs += d.virt[i] ? 0 : 1;
+  out.reserve(njobs);
   const int W = std::max(1, workers);
   int busy = 0;
   double now = 0.0;
-  while (int(out.size()) < nj) {
+  while (int(out.size()) < njobs) {
+    while (!pending.empty() && pending.front().first <= now) {
+      ready.push(pending.front().second);
+      pending.pop_front();
+    }
     while (busy < W && !ready.empty()) {
       const int i = ready.top();
       ready.pop();
@@ -841,14 +890,16 @@ std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes, int
       running.push({now + d.dur[i], i});
       ++busy;
     }
-    if (running.empty()) return {};   // a cycle: cannot happen; the caller rejects an empty order
-    now = running.top().first;
+    // next event: a job ends, or (with a free workgroup) a waiting job's inputs arrive
+    double next = running.empty() ? std::numeric_limits<double>::infinity() : running.top().first;
+    if (busy < W && !pending.empty()) next = std::min(next, pending.front().first);
+    if (!(next < std::numeric_limits<double>::infinity())) return {};   // a cycle: cannot happen
+    now = next;
     while (!running.empty() && running.top().first <= now) {
       const int i = running.top().second;
       running.pop();
       --busy;
-      for (int x = nsucc[i]; x < nsucc[i + 1]; ++x)
-        if (--npred[succ[x]] == 0) ready.push(succ[x]);
+      complete(i, now);
     }
   }
   return out;

@@ -137,7 +137,13 @@ ap_ctx* take_ctx(ap_server* sv, const Request& r) {
     v.pop_back();
     return c;
   }
-  return aparareal_create(r.N, r.eps, r.F, r.nu);
+  // Batches of requests fill the GPU with independent jobs, so a coarse step
+  // runs in one workgroup (AP_OPT_SPLIT 0): fewer, longer jobs, and a job
+  // graph the host schedules in a few milliseconds instead of tens (values
+  // are unchanged; measured 163 against 98-107 solves/s closed loop).
+  ap_ctx* c = aparareal_create(r.N, r.eps, r.F, r.nu);
+  if (c) (void)aparareal_set_option(c, AP_OPT_SPLIT, 0);
+  return c;
 }
 
 void give_ctx(ap_server* sv, const Request& r, ap_ctx* c) {
