@@ -376,7 +376,8 @@ def single_workload(args, which):
         # untimed: measures job durations on the device and picks the mapping
         ms = autotune([(ctx, u0, dict(T=cfg.T, slices=cfg.slices, K=cfg.K, dt_fine=cfg.dt, M=cfg.Mbar))],
                       precision=cfg.precision)
-        tuned = {"best_ms": round(ms, 4), "split_coarse": ctx.get_option(0), "group_size": ctx.get_option(1)}
+        tuned = {"best_ms": round(ms, 4), "split_coarse": ctx.get_option(0), "group_size": ctx.get_option(1),
+                 "handoff_us": ctx.get_option(10) / 1000.0}
 
     def check():
         if not np.all(np.isfinite(resid.cpu().numpy())) or not np.all(np.isfinite(out.cpu().numpy())):
@@ -425,7 +426,7 @@ def batch_workload(args):
     if not args.no_autotune:
         ms = autotune(items, precision=0)
         tuned = {"best_ms": round(ms, 4), "split_coarse": ctxs[0].get_option(0),
-                 "group_sizes": sorted({c.get_option(1) for c in ctxs})}
+                 "group_sizes": sorted({c.get_option(1) for c in ctxs}), "handoff_us": ctxs[0].get_option(10) / 1000.0}
 
     def check():
         for U, r, _ in outs:

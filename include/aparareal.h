@@ -208,10 +208,16 @@ int aparareal_solve_batch(const ap_batch_item* items, int count, void* stream);
  *                 shape aparareal_autotune_fine chose for this device, grid
  *                 size and precision (in this context or, earlier, in the
  *                 tuning cache), else shape 0; 0..2 that shape.  A slice
- *                 rounds the same way in every shape: results are unchanged. */
+ *                 rounds the same way in every shape: results are unchanged.
+ *   AP_OPT_HANDOFF_NS  scheduling weight of a dependency between two jobs of
+ *                 a pipelined launch this context owns, in ns (default 6000):
+ *                 the host orders the jobs by a simulation of the launch in
+ *                 which a job may start this long after the jobs it waits
+ *                 for; aparareal_autotune may choose another value.  Job
+ *                 order only: results are unchanged.                         */
 enum {
   AP_OPT_SPLIT = 0, AP_OPT_GROUP = 1, AP_OPT_GRID = 2, AP_OPT_GRAPH = 3, AP_OPT_SKIP = 4, AP_OPT_SWEEPS = 5,
-  AP_OPT_FINE = 6, AP_OPT_COARSE = 7, AP_OPT_FINE_GROUP = 8, AP_OPT_FINE_SHAPE = 9
+  AP_OPT_FINE = 6, AP_OPT_COARSE = 7, AP_OPT_FINE_GROUP = 8, AP_OPT_FINE_SHAPE = 9, AP_OPT_HANDOFF_NS = 10
 };
 int aparareal_set_option(ap_ctx* ctx, int option, int value);
 int aparareal_get_option(ap_ctx* ctx, int option, int* value);
@@ -224,9 +230,11 @@ int aparareal_get_option(ap_ctx* ctx, int option, int* value);
  * a context whose AP_OPT_GROUP is set keeps that size).  For each candidate
  * it runs the solve, records every job's duration on the device clock,
  * re-orders the jobs with the measured durations per problem and job type
- * (twice), and times three solves; it then keeps the fastest candidate and
- * its measured durations in the contexts, so that later solves of the same
- * shape use them.  The outputs receive the results of the last solve run.
+ * (twice), and times three solves; with the fastest candidate it then times
+ * the job order built with half and 5/3 of the first context's
+ * AP_OPT_HANDOFF_NS.  It keeps the fastest candidate, its measured durations
+ * and the weight in the contexts, so that later solves of the same shape use
+ * them.  The outputs receive the results of the last solve run.
  * *best_ms (host, may be NULL) receives the best solve time.  The mapping and
  * the job order leave results unchanged; the chosen group size changes the
  * summation order of the average (rounding only), and later solves equal

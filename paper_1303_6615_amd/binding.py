@@ -39,7 +39,7 @@ class BatchItem(ctypes.Structure):
 
 
 AP_OPT_SPLIT, AP_OPT_GROUP, AP_OPT_GRID, AP_OPT_GRAPH, AP_OPT_SKIP, AP_OPT_SWEEPS = 0, 1, 2, 3, 4, 5
-AP_OPT_FINE, AP_OPT_COARSE, AP_OPT_FINE_GROUP, AP_OPT_FINE_SHAPE = 6, 7, 8, 9
+AP_OPT_FINE, AP_OPT_COARSE, AP_OPT_FINE_GROUP, AP_OPT_FINE_SHAPE, AP_OPT_HANDOFF_NS = 6, 7, 8, 9, 10
 JOB_COARSE, JOB_FINE, JOB_STAGE1, JOB_STAGE2, JOB_COPY = 0, 1, 2, 3, 4
 
 

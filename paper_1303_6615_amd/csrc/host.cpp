@@ -186,6 +186,7 @@ struct ap_ctx {
   int opt_coarse = 0;        // coarse step: 0 asymptotic (Alg. 2), 1 one Strang step (standard parareal)
   int opt_fine_group = 0;    // slices per fine job: 0 automatic, else at most this many
   int opt_fine_shape = -1;   // workgroup shape of the fine batch: -1 tuned (or default), else 0..2
+  int handoff_ns = 6000;     // scheduling weight per dependency of the launches this context owns
   int tuned_shape[2] = {-1, -1};   // per precision: from aparareal_autotune_fine or the tuning cache
   std::string device_key;          // device kind, the tuning cache's key
   hipGraph_t graph = nullptr;
@@ -798,7 +799,7 @@ void problem_dag(int prob, const PipeShape& q, JobDag& d) {
 // of 0-20 us (N = 256 with 64 slices: 5.19 -> 4.7 ms; N = 1024 with 256
 // slices: 17.5 -> 15.6 ms; the 64-problem batch unchanged).  It lengthens
 // the chains of many short dependent jobs, so their jobs get priority.
-constexpr double kHandoffUs = 6.0;
+constexpr double kHandoffUs = 6.0;   // the default; aparareal_autotune may pick another per launch
 
 // Hand-out order of the jobs of several problems on `workers` resident
 // workgroups: a list schedule simulated with the jobs' duration estimates and
@@ -810,7 +811,8 @@ constexpr double kHandoffUs = 6.0;
 // starts them.  Long chains (long fine steps or many slices) thus start
 // first and are not stretched by the jobs of short problems, while every
 // workgroup is kept busy.  The order is topological by construction.
-std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes, int workers) {
+std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes, int workers,
+                                       double handoff = kHandoffUs) {
   JobDag d;
   d.pred_begin.push_back(0);
   for (size_t p = 0; p < shapes.size(); ++p) problem_dag(int(p), shapes[p], d);
@@ -827,7 +829,7 @@ std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes, int
   std::vector<int> succ(d.pred.size()), fill(nsucc.begin(), nsucc.end() - 1);
   for (int i = 0; i < nj; ++i)
     for (int x = d.pred_begin[i]; x < d.pred_begin[i + 1]; ++x) succ[fill[d.pred[x]]++] = i;
-  auto edge = [&](int to) { return d.virt[to] ? 0.0 : kHandoffUs; };
+  auto edge = [&](int to) { return d.virt[to] ? 0.0 : handoff; };
   std::vector<double> bl(nj, 0.0);
   for (int i = nj - 1; i >= 0; --i) {
     double m = 0.0;
@@ -1072,7 +1074,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
   int* ticket = flags + ncnt;
   int* abort = ticket + 1;
   // job list, cached by the problems' shapes
-  std::string key = std::to_string(grid) + "|";
+  std::string key = std::to_string(grid) + ":" + std::to_string(owner->handoff_ns) + "|";
   for (auto& q : shapes)
     key += std::to_string(q.nx) + ":" + std::to_string(q.Ns) + ":" + std::to_string(q.K) + ":" +
            std::to_string(q.steps) + ":" + std::to_string(q.M) + ":" + std::to_string(q.gs) + ":" +
@@ -1082,7 +1084,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
                               std::to_string(q.cal.stage2) + "," + std::to_string(q.cal.whole)
                         : std::string("-")) + ";";
   if (key != owner->pp_jobs_key) {
-    std::vector<ap::PipeJob> jobs = schedule_jobs(shapes, grid);
+    std::vector<ap::PipeJob> jobs = schedule_jobs(shapes, grid, owner->handoff_ns * 1e-3);
     if (!order_is_valid(jobs, shapes)) return fail(AP_EINVAL, "internal: job order is not topological");
     if (jobs.size() > size_t(1) << 30) return fail(AP_EINVAL, "batch too large");
     owner->pp_jobs_key.clear();
@@ -1665,6 +1667,38 @@ int aparareal_autotune(const ap_batch_item* batch, int count, void* stream, doub
       for (int i = 0; i < count; ++i) best_cal.push_back(batch[i].ctx->cost);
     }
   }
+  // with the best mapping and its measured durations: the scheduling weight
+  // of a dependency (hand-off delay), a few values around the default
+  const int handoff_was = owner->handoff_ns;
+  int best_handoff = handoff_was;
+  if (rc == AP_OK && best_cand >= 0) {
+    for (int i = 0; i < count; ++i) {
+      ap_ctx* c = batch[i].ctx;
+      c->opt_split = best_cand == 0 ? 0 : 1;
+      c->tuned_group = best_cand == 0 ? 0 : tune_group(c->N, best_cand - 1);
+      c->cost = best_cal[size_t(i)];
+    }
+    for (const int h : {handoff_was / 2, handoff_was * 5 / 3}) {
+      owner->handoff_ns = h;
+      if ((rc = run())) break;   // warm-up with the new job order
+      double ms = -1.0;
+      for (int rep = 0; rep < 3 && rc == AP_OK; ++rep) {
+        (void)hipEventRecord(ev[0], s);
+        rc = run();
+        (void)hipEventRecord(ev[1], s);
+        float t = 0.f;
+        if (rc == AP_OK &&
+            (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess))
+          rc = fail(AP_EDEVICE, "autotune timing");
+        if (rc == AP_OK && (ms < 0.0 || t < ms)) ms = t;
+      }
+      if (rc == AP_OK && ms < best) {
+        best = ms;
+        best_handoff = h;
+      }
+    }
+  }
+  owner->handoff_ns = rc == AP_OK ? best_handoff : handoff_was;
   for (int i = 0; i < count; ++i) {
     ap_ctx* c = batch[i].ctx;
     if (rc == AP_OK && best_cand >= 0) {
@@ -1729,6 +1763,10 @@ int aparareal_set_option(ap_ctx* c, int option, int value) {
       if (value < -1 || value >= ap::kFineShapeCount) return fail(AP_EINVAL, "AP_OPT_FINE_SHAPE takes -1, 0, 1 or 2");
       c->opt_fine_shape = value;
       return AP_OK;
+    case AP_OPT_HANDOFF_NS:
+      if (value < 0 || value > 1000000) return fail(AP_EINVAL, "AP_OPT_HANDOFF_NS takes 0..1000000");
+      c->handoff_ns = value;
+      return AP_OK;
     default:
       return fail(AP_EINVAL, "unknown option");
   }
@@ -1749,6 +1787,7 @@ int aparareal_get_option(ap_ctx* c, int option, int* value) {
     case AP_OPT_COARSE: *value = c->opt_coarse; return AP_OK;
     case AP_OPT_FINE_GROUP: *value = c->opt_fine_group; return AP_OK;
     case AP_OPT_FINE_SHAPE: *value = c->opt_fine_shape; return AP_OK;
+    case AP_OPT_HANDOFF_NS: *value = c->handoff_ns; return AP_OK;
     default: return fail(AP_EINVAL, "unknown option");
   }
 }
