@@ -88,13 +88,18 @@ __device__ __forceinline__ void dft_reg(cx<T> (&x)[R]) {
 // wavefront) and n passes of radices r0 .. r3 with product P.  Every pass has
 // at least G butterflies where the length allows it (P >= 128): a pass with
 // fewer leaves lanes repeating butterflies, so radix-4 passes (and one radix-2
-// pass) beat fewer passes of radix 8.
+// pass) beat fewer passes of radix 8.  The plans for P = 128, 256, 512 and
+// 1024 are also chosen so that some exchanges between passes are row swaps
+// in registers rather than LDS round trips (see wave_pass_pair and
+// wave_pass_first_pair): at P = 512, radices 8, 4, 4, 4 take the same
+// arithmetic as 8, 8, 8 and move the data through LDS four times instead of
+// six.
 template <int P> struct WavePlan;
 template <> struct WavePlan<32>   { static constexpr int G = 8,  n = 2, r0 = 4,  r1 = 8, r2 = 1, r3 = 1; };
 template <> struct WavePlan<64>   { static constexpr int G = 16, n = 3, r0 = 4,  r1 = 4, r2 = 4, r3 = 1; };
 template <> struct WavePlan<128>  { static constexpr int G = 32, n = 4, r0 = 4,  r1 = 4, r2 = 4, r3 = 2; };
 template <> struct WavePlan<256>  { static constexpr int G = 64, n = 4, r0 = 4,  r1 = 4, r2 = 4, r3 = 4; };
-template <> struct WavePlan<512>  { static constexpr int G = 64, n = 3, r0 = 8,  r1 = 8, r2 = 8, r3 = 1; };
+template <> struct WavePlan<512>  { static constexpr int G = 64, n = 4, r0 = 8,  r1 = 4, r2 = 4, r3 = 4; };
 template <> struct WavePlan<1024> { static constexpr int G = 64, n = 3, r0 = 16, r1 = 8, r2 = 8, r3 = 1; };
 
 // Twiddle table of a grid size N = 2P: entries t < N hold exp(-2 pi i t/N)
@@ -127,7 +132,7 @@ inline void wave_plan_radices(int P, int r[4], int* n) {
     case 64: r[0] = 4; r[1] = 4; r[2] = 4; *n = 3; return;
     case 128: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 2; *n = 4; return;
     case 256: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 4; *n = 4; return;
-    case 512: r[0] = 8; r[1] = 8; r[2] = 8; *n = 3; return;
+    case 512: r[0] = 8; r[1] = 4; r[2] = 4; r[3] = 4; *n = 4; return;
     default: r[0] = 16; r[1] = 8; r[2] = 8; *n = 3; return;
   }
 }
@@ -140,7 +145,7 @@ inline void wave_plan_radices(int P, int r[4], int* n) {
 // stride-R stores of that pass hit distinct banks (chosen by a model of the
 // bank mapping).  The last pass writes natural order (its stores are
 // consecutive already), which is what the consumers read.
-enum : int { kSwzId = 0, kSwzR = 1, kSwzR5 = 2, kSwzR9 = 3, kSwzRx2 = 4, kSwzRx1 = 5 };
+enum : int { kSwzId = 0, kSwzR = 1, kSwzR5 = 2, kSwzR9 = 3, kSwzRx2 = 4, kSwzRx1 = 5, kSwzRh1 = 6 };
 template <typename T, int CODE>
 __device__ __forceinline__ int swz(int pos) {
   if constexpr (CODE == kSwzId) {
@@ -154,17 +159,20 @@ __device__ __forceinline__ int swz(int pos) {
     else if constexpr (CODE == kSwzR5) f = r * 5;
     else if constexpr (CODE == kSwzR9) f = r * 9;
     else if constexpr (CODE == kSwzRx2) f = r ^ (r << 2);
-    else f = r ^ (r << 1);
+    else if constexpr (CODE == kSwzRx1) f = r ^ (r << 1);
+    else f = r >> 1;
     return pos ^ (f & m);
   }
 }
-// layout written by pass 0 / pass 1 (not the last) for transform length P
+// layout written by pass 0 / pass 1 (not the last) for transform length P;
+// at P = 256 and 512 pass 1 stores in the rotated butterfly order of
+// wave_pass_first_pair
 template <typename T, int P>
 constexpr int swz_pass0() { return kSwzR; }
 template <typename T, int P>
 constexpr int swz_pass1() {
-  if constexpr (sizeof(T) == 4) return P <= 256 ? kSwzR5 : kSwzRx2;
-  else return P <= 256 ? kSwzR5 : P == 512 ? kSwzRx1 : kSwzId;
+  if constexpr (sizeof(T) == 4) return P < 256 ? kSwzR5 : P == 256 ? kSwzR9 : P == 512 ? kSwzRx1 : kSwzRx2;
+  else return P < 256 ? kSwzR5 : P == 256 ? kSwzR : P == 512 ? kSwzRh1 : kSwzId;
 }
 // layout written by pass 2 of a four-pass plan (radix 4 after 16 points)
 template <typename T, int P>
@@ -223,52 +231,69 @@ constexpr bool tw_in_registers() {
   return sizeof(T) == 4 && P <= 128;
 }
 
-// One in-place Stockham pass of radix R after NS points have been combined,
-// by the G lanes of one signal group: butterfly b reads positions b + q P/R
-// from `src`, twiddles by exp(DIR 2 pi i q k/(NS R)) (k = b mod NS; from `w`,
-// NS > 1), and writes (b - k) R + k + q NS through the layout map SWO.  Lane
-// lig takes butterflies lig, lig + G, ...; when the pass has fewer
-// butterflies than lanes (P/R < G), lanes lig and lig + P/R repeat the same
-// butterfly and store the same values to the same places.  The pass has no
-// branch: a branch around the LDS accesses would make the compiler wait for
-// the previous pass's stores before the next loads, which the in-order LDS
-// queue of a wavefront does not need.  BATCH: all loads of the pass, then
-// those of the next pass's register twiddles (`next`), are issued before the
-// arithmetic (for small passes; large ones leave the order to the compiler,
-// which keeps fewer values live).
-template <typename T, int P, int R, int NS, int DIR, int G, int SWO, bool BATCH, typename Src, typename W,
-          typename WN>
-__device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, const W& w, WN& next, int lig,
-                                          const Src& src) {
+// Pieces of one Stockham pass of radix R after NS points have been combined,
+// by the G lanes of one signal group: butterfly b reads positions b + q P/R,
+// twiddles by exp(DIR 2 pi i q k/(NS R)) (k = b mod NS), and writes
+// (b - k) R + k + q NS.  Lane lig takes butterflies lig, lig + G, ...; when
+// the pass has fewer butterflies than lanes (P/R < G), lanes lig and
+// lig + P/R repeat the same butterfly and store the same values to the same
+// places.
+template <int P, int R, int G>
+__device__ __forceinline__ int pass_butterfly(int lig, int i) {
+  constexpr int NB = P / R;
+  return NB < G ? (lig & (NB - 1)) : lig + G * i;
+}
+// Butterfly of lane lig and slot i in the pass after wave_pass_first_pair
+// (NS points combined before it): butterfly b = h NS + k with h = lig mod 16
+// and k = 4 i + lig / 16.
+template <int NS>
+__device__ __forceinline__ int rotated_butterfly(int lig, int i) {
+  return (lig & 15) * NS + 4 * i + (lig >> 4);
+}
+template <int P, int R, int NS, int G, bool ROT>
+__device__ __forceinline__ int butterfly_of(int lig, int i) {
+  if constexpr (ROT) return rotated_butterfly<NS>(lig, i);
+  else return pass_butterfly<P, R, G>(lig, i);
+}
+
+// Loads of a pass's inputs from `src`.  BATCH: every load is issued before the
+// first input is formed (for small passes; large ones leave the order to the
+// compiler, which keeps fewer values live).
+template <typename T, int P, int R, int G, bool BATCH, typename Src>
+__device__ __forceinline__ void pass_load(cx<T> (&x)[(P / R + G - 1) / G][R], int lig, const Src& src) {
   constexpr int NB = P / R;
   constexpr int BPL = (NB + G - 1) / G;
   static_assert(NB % G == 0 || BPL == 1, "butterflies per lane");
-  cx<T> wt[BPL][R > 1 ? R - 1 : 1];
-  cx<T> x[BPL][R];
   if constexpr (BATCH) {
     typename Src::Raw raw[BPL][R];
 #pragma unroll
-    for (int i = 0; i < BPL; ++i) {
-      const int b = NB < G ? (lig & (NB - 1)) : lig + G * i;
+    for (int i = 0; i < BPL; ++i)
 #pragma unroll
-      for (int q = 0; q < R; ++q) raw[i][q] = src.fetch(b + q * NB);
-    }
+      for (int q = 0; q < R; ++q) raw[i][q] = src.fetch(pass_butterfly<P, R, G>(lig, i) + q * NB);
 #pragma unroll
     for (int i = 0; i < BPL; ++i)
 #pragma unroll
       for (int q = 0; q < R; ++q) x[i][q] = src.make(raw[i][q]);
   } else {
 #pragma unroll
-    for (int i = 0; i < BPL; ++i) {
-      const int b = NB < G ? (lig & (NB - 1)) : lig + G * i;
+    for (int i = 0; i < BPL; ++i)
 #pragma unroll
-      for (int q = 0; q < R; ++q) x[i][q] = src.make(src.fetch(b + q * NB));
-    }
+      for (int q = 0; q < R; ++q) x[i][q] = src.make(src.fetch(pass_butterfly<P, R, G>(lig, i) + q * NB));
   }
+}
+
+// Twiddles and register DFTs of a pass whose inputs are in x; `next` loads the
+// following pass's register twiddles between the twiddle reads and the
+// arithmetic, so that they share this pass's LDS round trip.
+template <typename T, int P, int R, int NS, int DIR, int G, bool ROT = false, typename W, typename WN>
+__device__ __forceinline__ void pass_compute(cx<T> (&x)[(P / R + G - 1) / G][R], const cx<T>* tw, const W& w, WN& next,
+                                             int lig) {
+  constexpr int BPL = (P / R + G - 1) / G;
+  cx<T> wt[BPL][R > 1 ? R - 1 : 1];
 #pragma unroll
   for (int i = 0; i < BPL; ++i) {
-    const int b = NB < G ? (lig & (NB - 1)) : lig + G * i;
     if constexpr (NS > 1) {
+      const int b = butterfly_of<P, R, NS, G, ROT>(lig, i);
 #pragma unroll
       for (int q = 1; q < R; ++q) wt[i][q - 1] = w.get(tw, i, q, b & (NS - 1));
     }
@@ -282,16 +307,203 @@ __device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, const W& 
     }
     dft_reg<T, R, DIR>(x[i]);
   }
+}
+
+// Stores of a pass's outputs through the layout map SWO, ordered after every
+// lane's loads of the pass (the buffer is updated in place) and before the
+// next pass's loads.  The pass has no branch: a branch around the LDS accesses
+// would make the compiler wait for the previous pass's stores before the next
+// loads, which the in-order LDS queue of a wavefront does not need.
+template <typename T, int P, int R, int NS, int G, int SWO, bool ROT = false>
+__device__ __forceinline__ void pass_store(cx<T>* buf, const cx<T> (&x)[(P / R + G - 1) / G][R], int lig) {
+  constexpr int BPL = (P / R + G - 1) / G;
   wave_sync();
 #pragma unroll
   for (int i = 0; i < BPL; ++i) {
-    const int b = NB < G ? (lig & (NB - 1)) : lig + G * i;
+    const int b = butterfly_of<P, R, NS, G, ROT>(lig, i);
     const int k = b & (NS - 1);
     const int d = (b - k) * R + k;
 #pragma unroll
     for (int q = 0; q < R; ++q) buf[swz<T, SWO>(d + q * NS)] = x[i][q];
   }
   wave_sync();
+}
+
+// One in-place Stockham pass through LDS.
+template <typename T, int P, int R, int NS, int DIR, int G, int SWO, bool BATCH, typename Src, typename W,
+          typename WN>
+__device__ __forceinline__ void wave_pass(cx<T>* buf, const cx<T>* tw, const W& w, WN& next, int lig,
+                                          const Src& src) {
+  cx<T> x[(P / R + G - 1) / G][R];
+  pass_load<T, P, R, G, BATCH>(x, lig, src);
+  pass_compute<T, P, R, NS, DIR, G>(x, tw, w, next, lig);
+  pass_store<T, P, R, NS, G, SWO>(buf, x, lig);
+}
+
+// Exchange of 16-lane rows between two registers (v_permlane16_swap, M = 16,
+// or v_permlane32_swap, M = 32).  In a lane l with bit M clear, a keeps its
+// value and b takes a of lane l + M; in a lane with bit M set, a takes b of
+// lane l - M and b keeps its value.  Applied to the pair of registers that
+// differ in one bit of the element index, this exchanges that register bit
+// with lane bit log2 M.  Pure VALU: no LDS access.
+template <int M>
+__device__ __forceinline__ void row_swap_u32(unsigned& a, unsigned& b) {
+  static_assert(M == 16 || M == 32, "row swaps move lane bit 4 or 5");
+  if constexpr (M == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  }
+}
+template <int M>
+__device__ __forceinline__ void row_swap(float& a, float& b) {
+  unsigned ua = __float_as_uint(a), ub = __float_as_uint(b);
+  row_swap_u32<M>(ua, ub);
+  a = __uint_as_float(ua);
+  b = __uint_as_float(ub);
+}
+template <int M>
+__device__ __forceinline__ void row_swap(double& a, double& b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  unsigned alo = unsigned(ua), ahi = unsigned(ua >> 32), blo = unsigned(ub), bhi = unsigned(ub >> 32);
+  row_swap_u32<M>(alo, blo);
+  row_swap_u32<M>(ahi, bhi);
+  a = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(ahi) << 32) | alo));
+  b = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(bhi) << 32) | blo));
+}
+template <int M, typename T>
+__device__ __forceinline__ void row_swap(cx<T>& a, cx<T>& b) {
+  row_swap<M>(a.x, b.x);
+  row_swap<M>(a.y, b.y);
+}
+
+// The last two Stockham passes with the exchange between them in registers.
+// Pass A (radix RA after NSA = 16 or 32 points) leaves element
+// h NSA RA + q NSA + k of its butterfly b = NSA h + k in register q of the
+// lane that ran b: k is lane bits 0-3 (0-4), h lane bits 4-5 (5) and, with
+// two butterflies per lane, the slot bit.  The last pass B (radix RB after
+// NSA RA points) reads positions b' + q' P/RB; every one of them sits in a
+// lane whose bits 4-5 (5) equal bits of q.  Row swaps trade those lane bits
+// for register bits, after which lane lig holds exactly the inputs of its
+// butterflies lig + G i of pass B, in the order the pass takes them: the same
+// values the LDS round trip would have delivered, so the results are
+// identical.  Plans with this property:
+//   P = 128 (G = 32): A radix 4, B radix 2; lane bit 4 <-> register bit 0;
+//   P = 256 (G = 64): A radix 4, B radix 4; lane bits 4, 5 <-> register bits 0, 1;
+//   P = 512 (G = 64): A radix 4 after 32 points, 2 butterflies per lane, B
+//     radix 4; lane bit 5 <-> register bit 0 of each butterfly;
+//   P = 1024 (G = 64): A radix 8 with 2 butterflies per lane, B radix 8;
+//     lane bits 4, 5 <-> register bits 0, 1 of each butterfly.
+template <int P>
+constexpr bool last_pair_in_registers() {
+  return P == 128 || P == 256 || P == 512 || P == 1024;
+}
+
+template <typename T, int P, int RA, int NSA, int RB, int NSB, int DIR, int G, bool BATCH, typename Src, typename WA,
+          typename WB>
+__device__ __forceinline__ void wave_pass_pair(cx<T>* buf, const cx<T>* tw, const WA& wa, WB& wb, int lig,
+                                               const Src& src) {
+  static_assert((NSA == 16 || (P == 512 && NSA == 32)) && NSB == NSA * RA && NSB * RB == P, "pass pair geometry");
+  constexpr int BA = (P / RA + G - 1) / G, BB = (P / RB + G - 1) / G;
+  cx<T> x[BA][RA];
+  NoTw<T> none;
+  pass_load<T, P, RA, G, BATCH>(x, lig, src);
+  pass_compute<T, P, RA, NSA, DIR, G>(x, tw, wa, wb, lig);
+  cx<T> y[BB][RB];
+  if constexpr (P == 128) {
+    static_assert(G == 32 && RA == 4 && RB == 2, "plan");
+    row_swap<16>(x[0][0], x[0][1]);
+    row_swap<16>(x[0][2], x[0][3]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) y[i][q] = x[0][2 * i + q];
+  } else if constexpr (P == 256) {
+    static_assert(G == 64 && RA == 4 && RB == 4, "plan");
+    row_swap<16>(x[0][0], x[0][1]);
+    row_swap<16>(x[0][2], x[0][3]);
+    row_swap<32>(x[0][0], x[0][2]);
+    row_swap<32>(x[0][1], x[0][3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[0][q] = x[0][q];
+  } else if constexpr (P == 512) {
+    static_assert(G == 64 && RA == 4 && RB == 4, "plan");
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      row_swap<32>(x[i][0], x[i][1]);
+      row_swap<32>(x[i][2], x[i][3]);
+    }
+    // register s of butterfly i now holds q1 = s >> 1 and lane bit 5 = s & 1:
+    // input q' = 2 i + (s & 1) of pass-B butterfly s >> 1
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y[ib][q] = x[q >> 1][2 * ib + (q & 1)];
+  } else {
+    static_assert(P == 1024 && G == 64 && RA == 8 && RB == 8, "plan");
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int q = 0; q < 8; q += 2) row_swap<16>(x[i][q], x[i][q + 1]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if ((q & 2) == 0) row_swap<32>(x[i][q], x[i][q + 2]);
+    }
+    // register s of butterfly i now holds q2 = s >> 2 and lane bits (5, 4) = s & 3:
+    // input q' = 4 i + (s & 3) of pass-B butterfly s >> 2
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) y[ib][q] = x[q >> 2][4 * ib + (q & 3)];
+  }
+  pass_compute<T, P, RB, NSB, DIR, G>(y, tw, wb, none, lig);
+  pass_store<T, P, RB, NSB, G, kSwzId>(buf, y, lig);
+}
+
+// The first two Stockham passes with the exchange between them in registers
+// (P = 256: radices 4, 4; P = 512: radices 8, 4; G = 64).  Pass 0 runs
+// butterfly b = lig and leaves element b R0 + q in register q.  Pass 1 (after
+// R0 points) reads positions b' + q' P/R1, b' = h NS + k with k = q: its
+// inputs q' are the top two bits of b, lane bits 4 and 5.  Row swaps trade
+// them for register bits 0 and 1, so that lane lig then holds the inputs of
+// pass-1 butterflies h NS + k with h = lig mod 16 and k = 4 i + lig / 16
+// (rotated_butterfly), i = register bit 2 at P = 512.  Pass 1 runs those
+// butterflies and stores them through layout SW1 for pass 2.  The arithmetic
+// is that of the two passes through LDS.
+template <int P>
+constexpr bool first_pair_in_registers() {
+  return P == 256 || P == 512;
+}
+
+template <typename T, int P, int R0, int R1, int DIR, int G, int SW1, bool BATCH, typename Src, typename W1>
+__device__ __forceinline__ void wave_pass_first_pair(cx<T>* buf, const cx<T>* tw, const W1& w1, int lig,
+                                                     const Src& src) {
+  static_assert(G == 64 && P / R0 == G && (R0 == 4 || R0 == 8) && R1 == 4 && R0 * 16 * R1 <= 4 * P,
+                "first pair geometry");
+  constexpr int B1 = (P / R1 + G - 1) / G;
+  cx<T> x[1][R0];
+  NoTw<T> none;
+  NoTw<T> none2;
+  pass_load<T, P, R0, G, BATCH>(x, lig, src);
+  pass_compute<T, P, R0, 1, DIR, G>(x, tw, none, none2, lig);
+#pragma unroll
+  for (int q = 0; q < R0; q += 2) row_swap<16>(x[0][q], x[0][q + 1]);
+#pragma unroll
+  for (int q = 0; q < R0; ++q)
+    if ((q & 2) == 0) row_swap<32>(x[0][q], x[0][q + 2]);
+  // register s now holds bit 2 of k (P = 512) and lane bits (5, 4) = s & 3:
+  // input q' = s & 3 of slot s >> 2
+  cx<T> y[B1][R1];
+#pragma unroll
+  for (int i = 0; i < B1; ++i)
+#pragma unroll
+    for (int q = 0; q < R1; ++q) y[i][q] = x[0][4 * i + q];
+  pass_compute<T, P, R1, R0, DIR, G, true>(y, tw, w1, none, lig);
+  pass_store<T, P, R1, R0, G, SW1, true>(buf, y, lig);
 }
 
 // Unnormalised complex FFT of length P by one lane group, result in `buf`
@@ -304,20 +516,38 @@ __device__ __forceinline__ void wave_fft(cx<T>* buf, const cx<T>* tw, int lig, c
   constexpr int S1 = PL::n >= 3 ? swz_pass1<T, P>() : kSwzId;
   NoTw<T> none;
   PassTw<T, P, PL::r1, PL::r0, PL::G, pass1_tw_offset<P>(), PRE> w1;
-  wave_pass<T, P, PL::r0, 1, DIR, PL::G, S0, PRE>(buf, tw, none, w1, lig, src);
-  if constexpr (PL::n == 4) {
+  if constexpr (first_pair_in_registers<P>()) {
+    static_assert(PL::n == 4 && !PRE && last_pair_in_registers<P>(), "plan");
+    constexpr int NS2 = PL::r0 * PL::r1, NS3 = NS2 * PL::r2;
+    PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P>(), PRE> w2;
+    PassTw<T, P, PL::r3, NS3, PL::G, pass3_tw_offset<P>(), PRE> w3;
+    wave_pass_first_pair<T, P, PL::r0, PL::r1, DIR, PL::G, S1, PRE>(buf, tw, w1, lig, src);
+    wave_pass_pair<T, P, PL::r2, NS2, PL::r3, NS3, DIR, PL::G, PRE>(buf, tw, w2, w3, lig, ReadLayout<T, S1>{buf});
+  } else if constexpr (PL::n == 4) {
     constexpr int S2 = swz_pass2<T, P>();
     constexpr int NS2 = PL::r0 * PL::r1, NS3 = NS2 * PL::r2;
     PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P>(), PRE> w2;
     PassTw<T, P, PL::r3, NS3, PL::G, pass3_tw_offset<P>(), PRE> w3;
+    wave_pass<T, P, PL::r0, 1, DIR, PL::G, S0, PRE>(buf, tw, none, w1, lig, src);
     wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
-    wave_pass<T, P, PL::r2, NS2, DIR, PL::G, S2, PRE>(buf, tw, w2, w3, lig, ReadLayout<T, S1>{buf});
-    wave_pass<T, P, PL::r3, NS3, DIR, PL::G, kSwzId, PRE>(buf, tw, w3, none, lig, ReadLayout<T, S2>{buf});
+    if constexpr (last_pair_in_registers<P>()) {
+      wave_pass_pair<T, P, PL::r2, NS2, PL::r3, NS3, DIR, PL::G, PRE>(buf, tw, w2, w3, lig, ReadLayout<T, S1>{buf});
+    } else {
+      wave_pass<T, P, PL::r2, NS2, DIR, PL::G, S2, PRE>(buf, tw, w2, w3, lig, ReadLayout<T, S1>{buf});
+      wave_pass<T, P, PL::r3, NS3, DIR, PL::G, kSwzId, PRE>(buf, tw, w3, none, lig, ReadLayout<T, S2>{buf});
+    }
   } else if constexpr (PL::n == 3) {
-    PassTw<T, P, PL::r2, PL::r0 * PL::r1, PL::G, pass2_tw_offset<P>(), PRE> w2;
-    wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
-    wave_pass<T, P, PL::r2, PL::r0 * PL::r1, DIR, PL::G, kSwzId, PRE>(buf, tw, w2, none, lig, ReadLayout<T, S1>{buf});
+    constexpr int NS2 = PL::r0 * PL::r1;
+    PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P>(), PRE> w2;
+    wave_pass<T, P, PL::r0, 1, DIR, PL::G, S0, PRE>(buf, tw, none, w1, lig, src);
+    if constexpr (last_pair_in_registers<P>()) {
+      wave_pass_pair<T, P, PL::r1, PL::r0, PL::r2, NS2, DIR, PL::G, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
+    } else {
+      wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
+      wave_pass<T, P, PL::r2, NS2, DIR, PL::G, kSwzId, PRE>(buf, tw, w2, none, lig, ReadLayout<T, S1>{buf});
+    }
   } else {
+    wave_pass<T, P, PL::r0, 1, DIR, PL::G, S0, PRE>(buf, tw, none, w1, lig, src);
     wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, none, lig, ReadLayout<T, S0>{buf});
   }
 }
