@@ -116,8 +116,9 @@ struct Engine {
   };
 
   // N of the owned items' modal states x -> n for J slices, using slots
-  // slot .. slot + J - 1 (callers alternate between slots 0 and J when
-  // S >= 2 J, so consecutive evaluations need no barrier between them).
+  // slot .. slot + J - 1 (callers alternate between slots 0 and S/2, which
+  // J <= S/2 keeps apart, so consecutive evaluations need no barrier between
+  // them; with S = 1 every evaluation uses slot 0 and ends with a barrier).
   __device__ __forceinline__ void neval(int slot, int J, const Own& ow, const cx<T> (&x)[MPT][3],
                                         cx<T> (&n)[MPT][3], const Basis<T> (&bs)[MPT]) {
     cx<T>* sps = sp + slot * SL::sp_elems;
@@ -127,9 +128,9 @@ struct Engine {
       if (ow.valid(j)) put_fields<T, NX>(sps, ow.s, ow.mode(j), x[j], bs[j]);
     zero_tails<T, NX, NT>(sps, J);
     __syncthreads();
-    inverse_fields<T, NX, NT>(sps, ibs, J, tw);
+    inverse_fields<T, NX, NT, jmax()>(sps, ibs, J, tw);
     __syncthreads();
-    forward_products<T, NX, NT>(sps, ibs, J, tw);
+    forward_products<T, NX, NT, jmax()>(sps, ibs, J, tw);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
@@ -141,8 +142,15 @@ struct Engine {
                                         const Basis<T> (&bs)[MPT]) {
     neval(slot, 1, Own(1), x, n, bs);
   }
-  // the slot after `slot` for the next evaluation of a J-slice job
-  static __device__ __forceinline__ int next_slot(int slot, int J) { return S >= 2 * J ? (slot == 0 ? J : 0) : 0; }
+  // Evaluation H (0 or 1) of an alternating pair: slot 0 or S/2, known when
+  // compiling, so that the LDS addresses of the transforms are the same
+  // per-lane offsets in every evaluation plus a constant.
+  template <int H>
+  __device__ __forceinline__ void neval_half(int J, const Own& ow, const cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3],
+                                             const Basis<T> (&bs)[MPT]) {
+    constexpr int slot = H == 0 ? 0 : S / 2;
+    neval(slot, J, ow, x, n, bs);
+  }
 
   // FP64 block maximum of x over the workgroup (NaN wins); result valid in
   // every thread.  The scratch lives in `ib`, so wait for its last readers first.
@@ -239,11 +247,6 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, int Jrun, con
       cf3[j][al] = coef[7 * 3 * KP + o];
     }
   }
-  int slot = 0;
-  auto neval = [&](cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3]) {
-    en.neval(slot, J, ow, x, n, bs);
-    slot = E_::next_slot(slot, J);
-  };
   cx<T> Nx[MPT][3], st[MPT][3], E2c[MPT][3], Nu[MPT][3];
   cx<double> acc[MPT][3];
   for (int step = 0; step < steps; ++step) {
@@ -251,7 +254,7 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, int Jrun, con
     for (int j = 0; j < MPT; ++j)
 #pragma unroll
       for (int al = 0; al < 3; ++al) st[j][al] = cvt<T>(c[j][al]);
-    neval(st, Nu);
+    en.template neval_half<0>(J, ow, st, Nu, bs);
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
 #pragma unroll
@@ -260,7 +263,7 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, int Jrun, con
         st[j][al] = cfma(cQ[j][al], Nu[j][al], E2c[j][al]);                                   // a
         acc[j][al] = cE[j][al] * c[j][al] + cvt<double>(cf1[j][al] * Nu[j][al]);
       }
-    neval(st, Nx);                                                                            // N(a)
+    en.template neval_half<1>(J, ow, st, Nx, bs);                                             // N(a)
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
 #pragma unroll
@@ -270,7 +273,7 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, int Jrun, con
         st[j][al] = cfma(cQ[j][al], Nx[j][al], E2c[j][al]);                                   // b
         E2c[j][al] = cE2[j][al] * a_;                                                         // E2 a
       }
-    neval(st, Nx);                                                                            // N(b)
+    en.template neval_half<0>(J, ow, st, Nx, bs);                                             // N(b)
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
 #pragma unroll
@@ -278,7 +281,7 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, int Jrun, con
         acc[j][al] = acc[j][al] + cvt<double>(cf2[j][al] * Nx[j][al]);
         st[j][al] = cfma(cQ[j][al], T(2) * Nx[j][al] - Nu[j][al], E2c[j][al]);                // c
       }
-    neval(st, Nx);                                                                            // N(c)
+    en.template neval_half<1>(J, ow, st, Nx, bs);                                             // N(c)
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
 #pragma unroll
@@ -305,7 +308,6 @@ __device__ __forceinline__ void strang_regs(Engine<T, NX, NT, S>& en, int J,
   using E_ = Engine<T, NX, NT, S>;
   constexpr int MPT = E_::MPT;
   const T hh = T(0.5 * h), hT = T(h);
-  int slot = 0;
   cx<T> st[MPT][3], nv[MPT][3];
   cx<double> v[MPT][3];
   for (int step = 0; step < steps; ++step) {
@@ -316,14 +318,12 @@ __device__ __forceinline__ void strang_regs(Engine<T, NX, NT, S>& en, int J,
         v[j][al] = cE2[j][al] * c[j][al];
         st[j][al] = cvt<T>(v[j][al]);
       }
-    en.neval(slot, J, ow, st, nv, bs);
-    slot = E_::next_slot(slot, J);
+    en.template neval_half<0>(J, ow, st, nv, bs);
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
 #pragma unroll
       for (int al = 0; al < 3; ++al) st[j][al] = st[j][al] + hh * nv[j][al];
-    en.neval(slot, J, ow, st, nv, bs);
-    slot = E_::next_slot(slot, J);
+    en.template neval_half<1>(J, ow, st, nv, bs);
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
 #pragma unroll

@@ -590,23 +590,36 @@ struct ReadHalfSpectrum {
 // passed through an empty asm statement, so that the compiler cannot tie the
 // loads to the zero stores of zero_tails and split them into conditional
 // loads (each with its own wait).
-template <typename T, int NX, int NT>
+// Runs body(v0) for the first signal v0 of each round of transforms of this
+// wavefront over nsig signals.  When MAXNS states (3 MAXNS signals) fit one
+// round of the workgroup's wavefronts, the round is straight-line code, and
+// the signal's offsets are the same in every evaluation of a job.
+template <int NT, int SPW, int MAXNS, typename B>
+__device__ __forceinline__ void signal_rounds(int nsig, B&& body) {
+  constexpr int NW = NT / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if constexpr (MAXNS > 0 && NW * SPW >= 3 * MAXNS) {
+    if (wave * SPW < nsig) body(wave * SPW);
+  } else {
+    for (int v0 = wave * SPW; v0 < nsig; v0 += NW * SPW) body(v0);
+  }
+}
+
+template <typename T, int NX, int NT, int MAXNS = 0>
 __device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, const cx<T>* tw) {
   using G_ = Geo<NX>;
   constexpr int P = G_::P;
   constexpr int G = WavePlan<P>::G;
   constexpr int SPW = 64 / G;             // signals per wavefront
-  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63;
   const int group = lane / G, lig = lane - group * G;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nsig = 3 * ns;
-  for (int v0 = wave * SPW; v0 < nsig; v0 += NW * SPW) {
+  signal_rounds<NT, SPW, MAXNS>(nsig, [&](int v0) {
     const int v = v0 + group < nsig ? v0 + group : v0;
     int off = v * (P + 1);
     asm volatile("" : "+v"(off));
     wave_fft<T, P, +1>(ib + v * P, tw, lig, ReadHalfSpectrum<T, P>{sp + off, tw});
-  }
+  });
 }
 
 // Zeroes the entries Kd < k <= P of the 3*ns field spectra in SP (the forward
@@ -644,24 +657,22 @@ struct ReadProducts {
 // written into SP (stride P+1): v1^2/2, v1 v2x, h v1.  The first pass reads
 // both factors and scales by 1/2 or 1, with no branch on the product; lane
 // groups past the last signal repeat their wavefront's first one.
-template <typename T, int NX, int NT>
+template <typename T, int NX, int NT, int MAXNS = 0>
 __device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int ns, const cx<T>* tw) {
   constexpr int P = Geo<NX>::P;
   constexpr int G = WavePlan<P>::G;
   constexpr int SPW = 64 / G;
-  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63;
   const int group = lane / G, lig = lane - group * G;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nsig = 3 * ns;
-  for (int v0 = wave * SPW; v0 < nsig; v0 += NW * SPW) {
+  signal_rounds<NT, SPW, MAXNS>(nsig, [&](int v0) {
     const int vv = v0 + group < nsig ? v0 + group : v0;
     const int s = vv / 3, f = vv - 3 * s;
     const cx<T>* V1 = ib + (3 * s) * P;
     const cx<T>* W = ib + (3 * s + (f == 2 ? 2 : f)) * P;   // v1 itself for the square
     const T scale = f == 0 ? T(0.5) : T(1);
     wave_fft<T, P, -1>(sp + vv * (P + 1), tw, lig, ReadProducts<T>{V1, W, scale});
-  }
+  });
 }
 
 // Modal N amplitudes of retained mode k from the forward transforms of one
