@@ -667,9 +667,10 @@ __device__ __forceinline__ double level_residual(Engine<T, NX, NT, S>& en, const
 
 // ------------------------------------------------- split coarse step -------
 // A coarse step evaluated by several workgroups: the stage-1 job of group g
-// stores S_g of Nbar(w); the stage-2 job of group g sums the stored stage-1
-// group sums (0 + S_0 + S_1 + ..., the order of the single-workgroup step),
-// forms y and stores S_g of Nbar(y).
+// stores S_g of Nbar(w); the last stage-1 job to finish sums the stored group
+// sums (0 + S_0 + S_1 + ..., the order of the single-workgroup step), forms
+// the midpoint state y once and stores it; the stage-2 job of group g loads y
+// and stores S_g of Nbar(y).
 template <typename T, int NX, int NT, int S>
 __device__ __forceinline__ void sum_groups(const cx<T>* __restrict__ P, int groups,
                                            cx<T> (&acc)[Engine<T, NX, NT, S>::MPT][3]) {
@@ -710,22 +711,24 @@ __device__ __forceinline__ void store_owned(cx<T>* __restrict__ dst,
       for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = v[j][al];
 }
 
-// Stage job of group g: stage 1 stores S_g(Nbar(w)) at P1g; stage 2 forms y
-// from the stage-1 sums at P1 and stores S_g(Nbar(y)) at P2g.  On return of
-// stage 2, w holds the step's w (for the finishing job).
+// Stage job of group g: stage 1 stores S_g(Nbar(w)) at Pout; stage 2 loads
+// the step's midpoint state y from Y and stores S_g(Nbar(y)) at Pout.  On
+// return, w holds the step's w (for the midpoint and the finishing job).
 template <typename T, int NX, int NT, int S>
 __device__ __forceinline__ void stage_job(Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct,
                                           const Basis<T>* __restrict__ basis, const cx<double>* uprev, int stage,
-                                          int g, const cx<T>* P1, int groups, cx<T>* Pout,
+                                          int g, const cx<T>* Y, cx<T>* Pout,
                                           cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3],
                                           CoarseRegs<T, Engine<T, NX, NT, S>::MPT>& cr) {
-  constexpr int MPT = Engine<T, NX, NT, S>::MPT;
+  using E_ = Engine<T, NX, NT, S>;
+  constexpr int MPT = E_::MPT;
   cx<T> u[MPT][3], y[MPT][3], acc[MPT][3];
   load_owned<T, NX, NT, S>(uprev, u);
   coarse_begin<T, NX, NT, S>(ct, u, w, cr);
   if (stage == 2) {
-    sum_groups<T, NX, NT, S>(P1, groups, acc);
-    coarse_mid<T, MPT>(ct, w, acc, y);
+#pragma unroll
+    for (int j = 0; j < MPT; ++j)
+      for (int al = 0; al < 3; ++al) y[j][al] = E_::valid(j) ? Y[al * E_::KP + E_::mode(j)] : czero<T>();
   } else {
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
@@ -735,6 +738,19 @@ __device__ __forceinline__ void stage_job(Engine<T, NX, NT, S>& en, const Coarse
   const int me = min(ct.avg.M, mb + ct.avg.gs);
   nbar_range<T, NX, NT, S>(en, y, acc, mb, me, false, ct.avg, basis);
   store_owned<T, NX, NT, S>(Pout, acc);
+}
+
+// The midpoint state of a split step, formed by its last stage-1 job: the sum
+// of the stage-1 group sums at P1 (in group order), then y from w, stored at Y
+// in the working precision (the stage-2 jobs load exactly these values).
+template <typename T, int NX, int NT, int S>
+__device__ __forceinline__ void stage_mid(const CoarseTab<T>& ct, const cx<T>* P1, int groups,
+                                          const cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3], cx<T>* Y) {
+  constexpr int MPT = Engine<T, NX, NT, S>::MPT;
+  cx<T> acc[MPT][3], y[MPT][3];
+  sum_groups<T, NX, NT, S>(P1, groups, acc);
+  coarse_mid<T, MPT>(ct, w, acc, y);
+  store_owned<T, NX, NT, S>(Y, y);
 }
 
 // The finishing part of a split step: Nbar(y) = sum of the stage-2 group sums,

@@ -605,7 +605,7 @@ struct PipeShape {
 // coarse step 3 us plus 2.2 per round for each of its two averages (measured
 // on MI355X at N = 256 and 1024).
 struct JobCost {
-  double fine, stage1, stage2, finish, whole;
+  double fine, stage1, stage2, mid, finish, whole;
 };
 
 JobCost job_cost(const PipeShape& q) {
@@ -617,7 +617,8 @@ JobCost job_cost(const PipeShape& q) {
   JobCost c;
   c.fine = (q.fine_kind == 1 ? 2.0 : 4.0) * ev * q.steps + 2.0;
   c.stage1 = 3.0 + 1.5 * rounds(q.gs) * ev;
-  c.stage2 = c.stage1 + 3.0;
+  c.stage2 = c.stage1 + 0.5;
+  c.mid = 3.0;       // the last stage-1 job sums the group sums and stores y
   c.finish = 0.5;
   c.whole = q.coarse_kind == 1 ? 2.0 * ev + 3.0 : 2.0 * (3.0 + 2.2 * rounds(q.M - 1) * ev) + 1.0;
   if (q.cal.valid) {
@@ -704,7 +705,8 @@ bool order_is_valid(const std::vector<ap::PipeJob>& jobs, const std::vector<Pipe
 struct JobDag {
   std::vector<ap::PipeJob> job;
   std::vector<double> dur;
-  std::vector<char> virt;        // 1: a join point (no job, no duration, no workgroup)
+  std::vector<char> virt;        // 1: a join point (no job, no workgroup; its duration is work that the
+                                 // last job to reach it does before its successors may start)
   std::vector<int> pred_begin;   // CSR: preds of node i at pred[pred_begin[i] .. pred_begin[i+1])
   std::vector<int> pred;
 };
@@ -720,8 +722,9 @@ struct JobDag {
 // C(k,n) is complete when its whole or copy job, or every stage-2 job, is.
 // With a tolerance, the jobs completing C(k,Ns) also wait for the copies of
 // level k (they read their residual parts).  A split step gets two join
-// points (after its stage-1 jobs; after its stage-2 jobs, its completion), so
-// that the graph has a few edges per job instead of one per pair of group jobs.
+// points (after its stage-1 jobs, with the midpoint state the last of them
+// forms; after its stage-2 jobs, its completion), so that the graph has a few
+// edges per job instead of one per pair of group jobs.
 void problem_dag(int prob, const PipeShape& q, JobDag& d) {
   const JobCost jc = job_cost(q);
   const int Ns = q.Ns, K = q.K, fg = std::max(1, q.fg);
@@ -736,7 +739,7 @@ void problem_dag(int prob, const PipeShape& q, JobDag& d) {
   };
   auto add = [&](ap::PipeJob j, double dur, bool v) {
     d.job.push_back(j);
-    d.dur.push_back(v ? 0.0 : dur);
+    d.dur.push_back(dur);
     d.virt.push_back(v ? 1 : 0);
     d.pred.insert(d.pred.end(), deps.begin(), deps.end());
     d.pred_begin.push_back(int(d.pred.size()));
@@ -759,7 +762,7 @@ void problem_dag(int prob, const PipeShape& q, JobDag& d) {
           add({prob, ap::kJobStage1, k, n, g}, jc.stage1, false);
         }
         for (int g = 0; g < q.groups; ++g) deps.push_back(first + g);
-        const int j1 = add({prob, ap::kJobStage1, k, n, -1}, 0.0, true);
+        const int j1 = add({prob, ap::kJobStage1, k, n, -1}, jc.mid, true);
         const int s2 = int(d.job.size());
         for (int g = 0; g < q.groups; ++g) {
           deps.push_back(j1);
@@ -861,7 +864,7 @@ std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes, int
         avail[v] = std::max(avail[v], tu + edge(v));
         if (--npred[v] > 0) continue;
         if (d.virt[v]) {
-          stack.push_back({avail[v], v});
+          stack.push_back({avail[v] + d.dur[v], v});
         } else {
           pending.push_back({avail[v], v});
         }
@@ -870,7 +873,7 @@ std::vector<ap::PipeJob> schedule_jobs(const std::vector<PipeShape>& shapes, int
   };
   for (int i = 0; i < nj; ++i)
     if (npred[i] == 0) {
-      if (d.virt[i]) complete(i, 0.0);
+      if (d.virt[i]) complete(i, d.dur[i]);
       else pending.push_back({0.0, i});
     }
   std::vector<ap::PipeJob> out;
@@ -1036,12 +1039,14 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     ap_ctx* c = it.c;
     const size_t sb = state_bytes(c);
     const size_t pb = size_t(3) * c->KP * (f64 ? sizeof(cx<double>) : sizeof(cx<float>));
-    const size_t pbytes = q.split ? pb * size_t(q.K + 1) * q.groups : pb;
+    // stage-1 sums and the midpoint state per level; stage-2 sums per level
+    const size_t p1bytes = q.split ? pb * size_t(q.K + 1) * (q.groups + 1) : pb;
+    const size_t p2bytes = q.split ? pb * size_t(q.K + 1) * q.groups : pb;
     if ((e = ensure(c, c->pp_U, sb * size_t(q.K + 1) * (q.Ns + 1))) != hipSuccess ||
         (e = ensure(c, c->pp_F, sb * size_t(std::max(q.K, 1)) * (q.Ns + 1))) != hipSuccess ||
         (e = ensure(c, c->pp_G, sb * size_t(q.K + 1) * (q.Ns + 1))) != hipSuccess ||
         (e = ensure(c, c->pp_part, sizeof(double2) * size_t(q.Ns) * std::max(1, q.K))) != hipSuccess ||
-        (e = ensure(c, c->pp_P1, pbytes)) != hipSuccess || (e = ensure(c, c->pp_P2, pbytes)) != hipSuccess)
+        (e = ensure(c, c->pp_P1, p1bytes)) != hipSuccess || (e = ensure(c, c->pp_P2, p2bytes)) != hipSuccess)
       return hip_fail(e, "pipeline workspace");
     shapes.push_back(q);
     ncnt += ap::pipe_counters(q.Ns, q.K);

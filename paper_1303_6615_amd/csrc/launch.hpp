@@ -77,7 +77,7 @@ struct PipeProb {
   cx<double>* G;       // [K+1][Ns+1][3][KP]
   double2* part;       // [K][Ns] residual partial sums
   int* cnt;            // counters, layout above
-  cx<T>* P1;           // [K+1][groups][3][KP] stage-1 group sums (split steps)
+  cx<T>* P1;           // [K+1][groups + 1][3][KP] stage-1 group sums, then the step's midpoint state (split steps)
   cx<T>* P2;           // [K+1][groups][3][KP] stage-2 group sums
   int nx, Ns, K, steps, groups;
   int fine_kind;       // 0: ETDRK4 fine slices; 1: Strang steps (Alg. 3)

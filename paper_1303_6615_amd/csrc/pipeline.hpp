@@ -14,9 +14,11 @@ namespace ap {
 // C(k,n): G(U(k,n-1)) -> G(k,n); U(k,n) = G (k = 0) or F(k-1,n) + (G - G(k-1,n)),
 //         needs C(k,n-1), F(k-1,n), C(k-1,n).
 // F(k,n): Fine(U(k,n-1)) -> F(k,n), needs C(k,n-1).
-// Split C(k,n): stage-1 job of group g needs C(k,n-1); stage-2 job of group g
-//         needs every stage-1 job of the step; the stage-2 job that finishes
-//         last also needs F(k-1,n) and C(k-1,n) and publishes C(k,n).
+// Split C(k,n): stage-1 job of group g needs C(k,n-1); the stage-1 job that
+//         finishes last forms the step's midpoint state and publishes the
+//         stage-1 counter once more (groups + 1); stage-2 job of group g needs
+//         that; the stage-2 job that finishes last also needs F(k-1,n) and
+//         C(k-1,n) and publishes C(k,n).
 // Stall record `diag` of a launch: [0] stalled, [1] job, [2] counter index,
 // [3] jobs completed so far (every workgroup adds 1 per job it publishes).
 // A wait ends in a stall only when no job of the launch completes for
@@ -132,7 +134,7 @@ template <typename T>
 __device__ __forceinline__ bool wait_deps(const PipeJob& jb, const PipeProb<T>& p, int* diag, int jt) {
   const PipeIdx ix{p.Ns, p.K};
   const int k = jb.k, n = jb.n;
-  if (jb.type == kJobStage2) return wait_count(&p.cnt[ix.stage1(k, n)], p.groups, diag, jt, ix.stage1(k, n));
+  if (jb.type == kJobStage2) return wait_count(&p.cnt[ix.stage1(k, n)], p.groups + 1, diag, jt, ix.stage1(k, n));
   if (jb.type == kJobCopy) {
     if (n == k && !wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n))) return false;
     if (!wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n))) return false;
@@ -160,6 +162,25 @@ constexpr int pipe_slots() {
 template <typename T, int NX>
 constexpr size_t pipe_lds() {
   return Engine<T, NX, kPipeThreads, pipe_slots<T, NX>()>::lds_bytes();
+}
+
+// Counts a group job of a split step in on counter *ctr (groups jobs count
+// in): every wavefront first waits for its stores to reach the L2 (a
+// workgroup barrier waits only for LDS), thread 0's release writes them back
+// for the other XCDs, then adds 1.  Returns true in the job that arrives
+// last, after an acquire that makes every other group's stores visible.
+__device__ __forceinline__ bool count_in_last(int* ctr, int groups, int* s_flag) {
+  wait_global_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    release_for_workgroup();
+    const int before = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int last = before == groups - 1;
+    if (last) acquire_for_workgroup();
+    *s_flag = last;
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(*s_flag) != 0;
 }
 
 // The fine slices of a job, called rather than inlined: one call per job (a
@@ -197,18 +218,18 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
   const int J = jb.type == kJobFine && jb.g > 1 ? min(jb.g, E_::jmax()) : 1;
   npub = J;
   if (skip) {
-    // past the stopped level: publish only (stage-2 jobs still count in so
-    // that the last one publishes the step)
+    // past the stopped level: publish only (group jobs still count in so
+    // that the last one publishes: stage 1 its extra count, stage 2 the step)
     if (jb.type == kJobFine) return ix.fine(k, n);
-    if (jb.type == kJobStage1) return ix.stage1(k, n);
-    if (jb.type != kJobStage2) return ix.coarse(k, n);
+    if (jb.type != kJobStage1 && jb.type != kJobStage2) return ix.coarse(k, n);
+    const int c = jb.type == kJobStage1 ? ix.stage1(k, n) : ix.stage2(k, n);
     if (threadIdx.x == 0) {
-      const int before = __hip_atomic_fetch_add(&p.cnt[ix.stage2(k, n)], 1, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
+      const int before = __hip_atomic_fetch_add(&p.cnt[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       *s_flag = before == p.groups - 1;
     }
     __syncthreads();
-    return __builtin_amdgcn_readfirstlane(*s_flag) ? ix.coarse(k, n) : -1;
+    if (!__builtin_amdgcn_readfirstlane(*s_flag)) return -1;
+    return jb.type == kJobStage1 ? ix.stage1(k, n) : ix.coarse(k, n);
   }
   const bool stage = staged != static_cast<const void*>(p.tw);
   E_ en(smem, p.tw, stage);
@@ -267,15 +288,21 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
                                p.part + size_t(k - 1) * Ns + (n - 1));
     return level_done();
   }
-  // split step: group sums of level k live at P{1,2} + k * groups * st
+  // split step: the stage-1 group sums of level k live at P1 + k (groups + 1) st,
+  // followed by the step's midpoint state; the stage-2 sums at P2 + k groups st
+  const size_t lvl1 = size_t(k) * (p.groups + 1) * st;
   const size_t lvl = size_t(k) * p.groups * st;
+  cx<T>* Y = p.P1 + lvl1 + size_t(p.groups) * st;
   cx<T> w[MPT][3];
   CoarseRegs<T, MPT> cr;
   if (jb.type == kJobStage1) {
-    stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 1, jb.g, nullptr, p.groups, p.P1 + lvl + jb.g * st, w, cr);
+    stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 1, jb.g, nullptr, p.P1 + lvl1 + jb.g * st, w, cr);
+    // the last group to arrive forms y for the stage-2 jobs and publishes
+    if (!count_in_last(&p.cnt[ix.stage1(k, n)], p.groups, s_flag)) return -1;
+    stage_mid<T, NX, NT, S>(p.ct, p.P1 + lvl1, p.groups, w, Y);
     return ix.stage1(k, n);
   }
-  stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 2, jb.g, p.P1 + lvl, p.groups, p.P2 + lvl + jb.g * st, w, cr);
+  stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 2, jb.g, Y, p.P2 + lvl + jb.g * st, w, cr);
   // Count this group in; the last group to arrive finishes the step.  Every
   // wavefront first waits for its stores of the group sum to reach the L2
   // (a workgroup barrier waits only for LDS); thread 0's release then writes

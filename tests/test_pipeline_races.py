@@ -15,9 +15,12 @@ test_release_sequence.py.
 Modelled per job (type, k, n, g) of one problem (Ns slices, K iterations):
   whole coarse C(k,n): waits C(k,n-1), F(k-1,n), C(k-1,n); reads U(k,n-1),
       G(k-1,n), F(k-1,n), U(k-1,n); writes U(k,n), G(k,n), part(k-1,n)
-  stage 1 of C(k,n), group g: waits C(k,n-1); reads U(k,n-1); writes P1(k,g)
-  stage 2 of C(k,n), group g: waits all stage-1 jobs of the step; reads
-      U(k,n-1) and every P1(k,.); writes P2(k,g), then counts in
+  stage 1 of C(k,n), group g: waits C(k,n-1); reads U(k,n-1); writes P1(k,g),
+      then counts in
+  midpoint of a split C(k,n) (the last stage-1 job to count in): after every
+      stage-1 job, reads every P1(k,.); writes Y(k)
+  stage 2 of C(k,n), group g: waits the midpoint; reads U(k,n-1) and Y(k);
+      writes P2(k,g), then counts in
   finish of a split C(k,n) (the last stage-2 job to count in): after every
       stage-2 job, waits F(k-1,n), C(k-1,n); reads every P2(k,.), G(k-1,n),
       F(k-1,n), U(k-1,n); writes U(k,n), G(k,n), part(k-1,n)
@@ -104,12 +107,14 @@ def build_graph(jobs, Ns, K, tol, plant_missing_copy_wait=False):
         g.edge(host_in, start[j])
         g.edge(start[j], end[j])
         g.edge(end[j], host_out)
-    fin = {}
+    fin, mid = {}, {}
     if split:
         for j in jobs:
             if j[0] == STAGE1 and (j[1], j[2]) not in fin:
                 fin[(j[1], j[2])] = g.node()
+                mid[(j[1], j[2])] = g.node()
                 g.edge(fin[(j[1], j[2])], host_out)
+                g.edge(mid[(j[1], j[2])], host_out)
     comp, fine_comp = {}, {}
     for j in jobs:
         t, k, n, gg = j
@@ -160,12 +165,11 @@ def build_graph(jobs, Ns, K, tol, plant_missing_copy_wait=False):
                 g.edge(comp[(k, n - 1)], s)
             g.access(s, j, U(k, n - 1), False)
             g.access(e, j, ("P1", k, gg), True)
+            g.edge(e, mid[(k, n)])
         elif t == STAGE2:
-            for x in range(groups):
-                g.edge(end[(STAGE1, k, n, x)], s)
+            g.edge(mid[(k, n)], s)
             g.access(s, j, U(k, n - 1), False)
-            for x in range(groups):
-                g.access(s, j, ("P1", k, x), False)
+            g.access(s, j, ("Y", k), False)
             g.access(e, j, ("P2", k, gg), True)
             g.edge(e, fin[(k, n)])
         elif t == FINE:
@@ -187,6 +191,10 @@ def build_graph(jobs, Ns, K, tol, plant_missing_copy_wait=False):
             g.access(e, j, ("G", k, n), True)
             g.access(e, j, ("part", k - 1, n), True)
             read_parts(k, n, e, j)
+    for (k, n), m in mid.items():
+        for x in range(groups):
+            g.access(m, ("mid", k, n), ("P1", k, x), False)
+        g.access(m, ("mid", k, n), ("Y", k), True)
     for (k, n), f in fin.items():
         owner = ("finish", k, n)
         if k >= 1:
