@@ -58,9 +58,11 @@ constexpr int fine_slices() {
 }
 
 // Workgroup b steps slices b J .. min(b J + J, batch) - 1 (J = the shape's
-// slices per workgroup).
+// slices per workgroup).  FP32 kernels keep three wavefronts per SIMD (at
+// most 168 VGPRs; the second bound is the minimum of wavefronts per SIMD),
+// the occupancy their workgroups are sized for.
 template <typename T, int NX, int NT>
-__global__ void __launch_bounds__(NT) k_fine(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 3 : 1) k_fine(const cx<double>* __restrict__ Uin, cx<double>* __restrict__ Uout,
                                              int batch, int steps, const cx<double>* __restrict__ coef64,
                                              const cx<T>* __restrict__ coef, const cx<T>* __restrict__ tw,
                                              const Basis<T>* __restrict__ basis) {

@@ -156,14 +156,18 @@ struct FftParity {
 
 // ------------------------------------------------- modal <-> (v1, v2x, h) ---
 // (v1^, i k v2^, h^) of the state with modal amplitudes c = (c-, c0, c+).
+// With e = c- - c+: v1 = s (c- + c+), v2^ = i (s iw e + aw c0), so
+// v2x = i k v2^ = -k s iw e - k aw c0, and h = -s aw e + iw c0 (s = 1/sqrt 2),
+// as fused multiply-adds with per-mode real factors.
 template <typename T>
 __device__ __forceinline__ void modal_to_fields(const cx<T> c[3], T kk, Basis<T> bs, cx<T>& v1,
                                                 cx<T>& v2x, cx<T>& h) {
   const T s = T(0.70710678118654752440);
   v1 = s * (c[0] + c[2]);
-  const cx<T> d = (bs.iw * s) * (c[0] - c[2]) + bs.aw * c[1];    // v2^ = i d
-  v2x = (-kk) * d;                                               // i k (i d)
-  h = (bs.aw * s) * (c[2] - c[0]) + bs.iw * c[1];
+  const cx<T> e = c[0] - c[2];
+  const T al = -(kk * (bs.iw * s)), be = -(kk * bs.aw), ga = -(bs.aw * s);
+  v2x = cx<T>{fmat(al, e.x, be * c[1].x), fmat(al, e.y, be * c[1].y)};
+  h = cx<T>{fmat(ga, e.x, bs.iw * c[1].x), fmat(ga, e.y, bs.iw * c[1].y)};
 }
 
 // modal amplitudes of the spectral vector (n1, n2, n3)

@@ -567,7 +567,9 @@ struct Slot {
 // at a time.  The loads of the first pass are unconditional.
 // First-pass source of an inverse transform: Z[k] = (X[k] + conj X[P-k])
 // + i conj(t_k) (X[k] - conj X[P-k]) from the half spectrum X (stride P+1),
-// t_k = exp(-2 pi i k/N).
+// t_k = exp(-2 pi i k/N).  With s and d the sum and difference, the product
+// i conj(t) d has parts -(t.x d.y - t.y d.x) and t.x d.x + t.y d.y, added to s
+// by fused multiply-adds.
 template <typename T, int P>
 struct ReadHalfSpectrum {
   const cx<T>* X;
@@ -577,8 +579,9 @@ struct ReadHalfSpectrum {
   };
   __device__ __forceinline__ Raw fetch(int idx) const { return Raw{X[idx], X[P - idx], tw[idx]}; }
   __device__ __forceinline__ cx<T> make(const Raw& r) const {
-    const cx<T> xc = conj(r.xm);
-    return (r.xk + xc) + mul_i(conj(r.t) * (r.xk - xc));
+    const cx<T> s{r.xk.x + r.xm.x, r.xk.y - r.xm.y};
+    const cx<T> d{r.xk.x - r.xm.x, r.xk.y + r.xm.y};
+    return cx<T>{fmat(r.t.y, d.x, fmat(-r.t.x, d.y, s.x)), fmat(r.t.y, d.y, fmat(r.t.x, d.x, s.y))};
   }
 };
 
@@ -677,26 +680,38 @@ __device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int
 
 // Modal N amplitudes of retained mode k from the forward transforms of one
 // slot's products (SP base of the slot, stride P+1).
+//   Product spectra: Q_f = (Z[k] + conj Z[P-k]) - i w (Z[k] - conj Z[P-k]),
+//   w = exp(-2 pi i k/N), so that the product's mode k is h Q_f, h = 1/(2N).
+//   N's fields: n1 = -i k h Q_0, n2 = -h Q_1, n3 = -i k h Q_2.
+//   Modal amplitudes (fields_to_modal with those fields, s = 1/sqrt 2):
+//     out0 = i (R - s h k Q_0),  out2 = -i (R + s h k Q_0),
+//     R = s h (iw Q_1 + aw k Q_2),  out1 = i h (aw Q_1 - iw k Q_2),
+//   all as fused multiply-adds with per-mode real factors.
 template <typename T, int NX>
 __device__ __forceinline__ void get_N_sp(const cx<T>* sp_slot, int k, Basis<T> bs, const cx<T>* tw, cx<T> out[3]) {
   using G = Geo<NX>;
   constexpr int P = G::P;
-  const T half_over_n = T(0.5) / T(G::N);
   const cx<T> w = tw[k];
   const int kc = (P - k) & (P - 1);
-  cx<T> Pf[3];
+  cx<T> Q[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const cx<T>* Z = sp_slot + f * (P + 1);
     const cx<T> zk = Z[k];
-    const cx<T> zc = conj(Z[kc]);
-    Pf[f] = half_over_n * ((zk + zc) - mul_i(w * (zk - zc)));
+    const cx<T> zm = Z[kc];
+    const cx<T> s{zk.x + zm.x, zk.y - zm.y};
+    const cx<T> d{zk.x - zm.x, zk.y + zm.y};
+    Q[f] = cx<T>{fmat(w.y, d.x, fmat(w.x, d.y, s.x)), fmat(w.y, d.y, fmat(-w.x, d.x, s.y))};
   }
+  constexpr T h = T(0.5 / double(G::N));
+  constexpr T sh = T(0.70710678118654752440 * (0.5 / double(G::N)));
   const T kk = T(k);
-  const cx<T> n1 = (-kk) * mul_i(Pf[0]);
-  const cx<T> n2 = T(-1) * Pf[1];
-  const cx<T> n3 = (-kk) * mul_i(Pf[2]);
-  fields_to_modal<T>(n1, n2, n3, bs, out);
+  const T a0 = sh * kk, b1 = sh * bs.iw, c2 = a0 * bs.aw, d1 = h * bs.aw, e2 = (h * kk) * bs.iw;
+  const cx<T> R{fmat(c2, Q[2].x, b1 * Q[1].x), fmat(c2, Q[2].y, b1 * Q[1].y)};
+  // i z = (-z.y, z.x)
+  out[0] = cx<T>{fmat(a0, Q[0].y, -R.y), fmat(-a0, Q[0].x, R.x)};
+  out[2] = cx<T>{fmat(a0, Q[0].y, R.y), fmat(-a0, Q[0].x, -R.x)};
+  out[1] = cx<T>{fmat(e2, Q[2].y, -(d1 * Q[1].y)), fmat(-e2, Q[2].x, d1 * Q[1].x)};
 }
 
 }  // namespace ap
