@@ -152,6 +152,11 @@ struct Engine {
     neval(slot, J, ow, x, n, bs);
   }
 
+  // Largest power of two not above NT: a tree reduction first folds the
+  // threads from there on into the first ones (nothing to fold when NT is a
+  // power of two).
+  static constexpr int kFold = 1 << ilog2(NT);
+
   // FP64 block maximum of x over the workgroup (NaN wins); result valid in
   // every thread.  The scratch lives in `ib`, so wait for its last readers first.
   __device__ __forceinline__ double block_max(double x) {
@@ -159,7 +164,14 @@ struct Engine {
     __syncthreads();
     red[threadIdx.x] = x;
     __syncthreads();
-    for (int off = NT / 2; off > 0; off >>= 1) {
+    if constexpr (kFold < NT) {
+      if (threadIdx.x < NT - kFold) {
+        const double o = red[threadIdx.x + kFold];
+        if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
+      }
+      __syncthreads();
+    }
+    for (int off = kFold / 2; off > 0; off >>= 1) {
       if (threadIdx.x < off) {
         const double o = red[threadIdx.x + off];
         if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
@@ -179,7 +191,14 @@ struct Engine {
     red[threadIdx.x] = x;
     red[NT + threadIdx.x] = yv;
     __syncthreads();
-    for (int off = NT / 2; off > 0; off >>= 1) {
+    if constexpr (kFold < NT) {
+      if (threadIdx.x < NT - kFold) {
+        red[threadIdx.x] += red[threadIdx.x + kFold];
+        red[NT + threadIdx.x] += red[NT + threadIdx.x + kFold];
+      }
+      __syncthreads();
+    }
+    for (int off = kFold / 2; off > 0; off >>= 1) {
       if (threadIdx.x < off) {
         red[threadIdx.x] += red[threadIdx.x + off];
         red[NT + threadIdx.x] += red[NT + threadIdx.x + off];
