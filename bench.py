@@ -84,14 +84,14 @@ def host_workers() -> int:
 def fine_batch_measure(slices):
     """Throughput form of the fine propagator: aparareal_fine_batch over
     `slices` independent N = 256 FP32 slices of the C2 shape (63 ETDRK4 steps
-    each).  The workgroup shape is first chosen by the fine-batch autotuner on
-    the same states; then three launches are timed on the fine kernel alone
-    with HIP events."""
+    each).  The configuration (workgroup shape and FFT plan) is first chosen
+    by the fine-batch autotuner on the same states; then three launches are
+    timed on the fine kernel alone with HIP events."""
     import numpy as np
     import torch
 
     from paper_1303_6615_amd import metrics
-    from paper_1303_6615_amd.binding import Context
+    from paper_1303_6615_amd.binding import Context, fft_plan
     from paper_1303_6615_amd.inputs import C2, seeded_state
 
     cfg = C2
@@ -116,9 +116,10 @@ def fine_batch_measure(slices):
     gp = slices * cfg.fine_steps * cfg.nx
     flops = metrics.fine_flops(cfg.nx, slices, cfg.fine_steps)
     return {"workload": f"rsw-n256-eps1e-2 fine batch, {slices} slices x {cfg.fine_steps} ETDRK4 steps, fp32",
-            "kernel": f"k_fine<float,256,{threads}>", "avg_launch_ms": round(avg_s * 1e3, 4),
+            "kernel": f"k_fine<float,256,{threads},{shape // 3}>", "avg_launch_ms": round(avg_s * 1e3, 4),
             "value": round(gp / avg_s, 1), "unit": "fine grid-point-steps/s",
-            "tuned_shape": {"shape": shape, "threads": threads, "slices_per_workgroup": per_wg,
+            "tuned_shape": {"config": shape, "shape": shape % 3, "threads": threads, "slices_per_workgroup": per_wg,
+                            "fft_plan": fft_plan(cfg.nx, shape // 3),
                             "candidate_ms": [round(x, 4) for x in cand_ms]},
             "roofline": {"bound": "alu", "achieved": round(flops / avg_s / 1e12, 4),
                          "peak": metrics.PEAK_FP32_TFLOPS, "unit": "TFLOP/s",

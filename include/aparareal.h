@@ -202,13 +202,16 @@ int aparareal_solve_batch(const ap_batch_item* items, int count, void* stream);
  *                 (16, 10, 5, 2, 1, 1 for N = 64 .. 2048); n >= 1: at most n.
  *                 A group starts when its last slice's input is ready, so
  *                 grouping trades latency for throughput.
- *   AP_OPT_FINE_SHAPE  workgroup shape of aparareal_fine_batch (threads and
- *                 slices per workgroup; three are compiled per precision and
- *                 grid size, see aparareal_fine_shape): -1 (default) the
- *                 shape aparareal_autotune_fine chose for this device, grid
- *                 size and precision (in this context or, earlier, in the
- *                 tuning cache), else shape 0; 0..2 that shape.  A slice
- *                 rounds the same way in every shape: results are unchanged.
+ *   AP_OPT_FINE_SHAPE  configuration of aparareal_fine_batch: workgroup shape
+ *                 (threads and slices per workgroup; three are compiled per
+ *                 precision and grid size) and FFT plan (aparareal_fft_plan;
+ *                 two for N >= 256): -1 (default) the configuration
+ *                 aparareal_autotune_fine chose for this device, grid size
+ *                 and precision (in this context or, earlier, in the tuning
+ *                 cache), else 0; c = shape + 3 plan sets that one
+ *                 (AP_EINVAL if it is not compiled for this N).  The shape
+ *                 does not change results; plan 1 rounds differently at
+ *                 N = 1024 (other radices), identically elsewhere.
  *   AP_OPT_HANDOFF_NS  scheduling weight of a dependency between two jobs of
  *                 a pipelined launch this context owns, in ns (default 6000):
  *                 the host orders the jobs by a simulation of the launch in
@@ -242,24 +245,38 @@ int aparareal_get_option(ap_ctx* ctx, int option, int* value);
 int aparareal_autotune(const ap_batch_item* items, int count, void* stream, double* best_ms);
 
 /* Autotuner of the fine batch (the parareal fine sweep over independent
- * states, spec batching pattern): times aparareal_fine_batch's three
- * compiled workgroup shapes for this grid size and precision on the caller's
- * states (one warm-up and three timed launches each, HIP events on `stream`;
- * the call synchronises), keeps the fastest in the context, and records it in
- * the tuning cache, a text file read by every later context of this device
- * kind, grid size and precision: $APARAREAL_TUNE_CACHE, else
- * $XDG_CACHE_HOME/aparareal/tune.txt, else $HOME/.cache/aparareal/tune.txt
- * (a write that fails is ignored).  U_in physical [batch][3][N], unchanged.
- * shape_ms (host, 3 doubles, may be NULL) receives the mean launch time of
- * each shape, *best (may be NULL) the chosen shape.  Results do not depend on
- * the shape.                                                                  */
+ * states): times every configuration of aparareal_fine_batch compiled for
+ * this grid size (AP_FINE_CONFIGS slots: configuration c is workgroup shape
+ * c % 3 with FFT plan c / 3, see aparareal_fft_plan; plan 1 exists for
+ * N >= 256) in this precision on the caller's states (one warm-up and three
+ * timed launches each, HIP events on `stream`; the call synchronises), keeps
+ * the fastest in the context, and records it in the tuning cache, a text file
+ * read by every later context of this device kind, grid size and precision:
+ * $APARAREAL_TUNE_CACHE, else $XDG_CACHE_HOME/aparareal/tune.txt, else
+ * $HOME/.cache/aparareal/tune.txt (a write that fails is ignored).  U_in
+ * physical [batch][3][N], unchanged.  shape_ms (host, AP_FINE_CONFIGS doubles,
+ * may be NULL) receives the mean launch time of each configuration (-1 for
+ * one not compiled at this N), *best (may be NULL) the chosen one.  The
+ * workgroup shape does not change results; the FFT plan changes the rounding
+ * at N = 1024 only (other radices).                                          */
+enum { AP_FINE_CONFIGS = 6 };
 int aparareal_autotune_fine(ap_ctx* ctx, const double* U_in, int batch, double dT, int steps, int precision,
                             void* stream, double* shape_ms, int* best);
 
-/* The workgroup shape the context's fine batches use in this precision: its
- * index (0..2), threads per workgroup and slices per workgroup (outputs may
- * be NULL).                                                                    */
+/* The configuration the context's fine batches use in this precision: its
+ * index (0 .. AP_FINE_CONFIGS - 1: workgroup shape index % 3, FFT plan
+ * index / 3), threads per workgroup and slices per workgroup (outputs may be
+ * NULL).                                                                       */
 int aparareal_fine_shape(ap_ctx* ctx, int precision, int* shape, int* threads, int* slices);
+
+/* The wave-local FFT of length N/2 (Sec. 6.2's pseudo-spectral evaluation of
+ * N: each real field of length N as a complex transform of half the length)
+ * in plan `plan` (0: the plan every kernel uses; 1: the fine batch's
+ * alternative, N >= 256): its Stockham passes' radices (radices[0 ..
+ * *passes - 1], host int[4]) and how many exchanges between passes are row
+ * swaps in registers instead of LDS round trips (*reg_exchanges).  Host only;
+ * AP_EINVAL for an N or a plan that does not exist.                          */
+int aparareal_fft_plan(int N, int plan, int* radices, int* passes, int* reg_exchanges);
 
 /* Measured rates of the current device that the hot path is priced against
  * (diagnostics): FP32 and FP64 vector FMA throughput in TFLOP/s (16

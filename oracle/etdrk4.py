@@ -1,7 +1,7 @@
 """Fine propagator: exponential time differencing RK4 (Cox & Matthews).
 
-Sec. 6.2 uses ETDRK4 as the fine integrator (cited, formulas not printed); the
-spec workload uses it for every parareal slice.  For
+Sec. 6.2 uses ETDRK4 as the fine integrator (cited, formulas not printed);
+every workload here steps each parareal slice with it.  For
 u' = A u + N(u), step h, with the coefficient matrices of matfun:
 
     a  = E2 u + Q N(u)

@@ -40,6 +40,7 @@ class BatchItem(ctypes.Structure):
 
 AP_OPT_SPLIT, AP_OPT_GROUP, AP_OPT_GRID, AP_OPT_GRAPH, AP_OPT_SKIP, AP_OPT_SWEEPS = 0, 1, 2, 3, 4, 5
 AP_OPT_FINE, AP_OPT_COARSE, AP_OPT_FINE_GROUP, AP_OPT_FINE_SHAPE, AP_OPT_HANDOFF_NS = 6, 7, 8, 9, 10
+AP_FINE_CONFIGS = 6
 JOB_COARSE, JOB_FINE, JOB_STAGE1, JOB_STAGE2, JOB_COPY = 0, 1, 2, 3, 4
 
 
@@ -63,6 +64,7 @@ _SIGNATURES = {
     "aparareal_autotune": (_i, [ctypes.POINTER(BatchItem), _i, _vp, ctypes.POINTER(_d)]),
     "aparareal_autotune_fine": (_i, [_vp, _dp, _i, _d, _i, _i, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i)]),
     "aparareal_fine_shape": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "aparareal_fft_plan": (_i, [_i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "aparareal_measure_peaks": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "aparareal_get_option": (_i, [_vp, _i, ctypes.POINTER(_i)]),
     "aparareal_pipeline_schedule": (_i, [_i, ctypes.POINTER(SolveParams), _i, _i, _i, ctypes.POINTER(_i), _i]),
@@ -180,6 +182,15 @@ def autotune(problems, precision: int = AP_PREC_FP32) -> float:
     return ms.value
 
 
+def fft_plan(N: int, plan: int = 0) -> dict:
+    """Radices of FFT plan `plan` for grid size N, and how many exchanges
+    between its passes are register row swaps."""
+    r = (ctypes.c_int * 4)()
+    n, x = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().aparareal_fft_plan(int(N), int(plan), r, ctypes.byref(n), ctypes.byref(x)))
+    return {"plan": int(plan), "radices": list(r)[:n.value], "register_exchanges": x.value}
+
+
 def measure_peaks() -> dict:
     """Measured FP32 / FP64 vector FMA rates (TFLOP/s) and LDS read bandwidth
     (TB/s) of the current device (microbenchmark kernels in the library)."""
@@ -259,11 +270,12 @@ class Context:
         return self._batched(lib().aparareal_fine_batch_noalloc, U, float(dT), int(steps), precision, out=out)
 
     def autotune_fine(self, U, dT: float, steps: int, precision: int = AP_PREC_FP32):
-        """Time the fine batch's workgroup shapes on U, keep and cache the
-        fastest; returns (best shape, [mean ms per shape])."""
+        """Time the fine batch's configurations (workgroup shape c % 3, FFT
+        plan c // 3) on U, keep and cache the fastest; returns (best
+        configuration, [mean ms per configuration, -1 where not compiled])."""
         import torch
         U = _states(U, self.N, "U")
-        ms = (ctypes.c_double * 3)()
+        ms = (ctypes.c_double * AP_FINE_CONFIGS)()
         best = ctypes.c_int(0)
         _check(lib().aparareal_autotune_fine(self._h, ctypes.c_void_p(U.data_ptr()), U.numel() // (3 * self.N),
                                              float(dT), int(steps), int(precision), _stream(torch), ms,
@@ -271,7 +283,8 @@ class Context:
         return best.value, list(ms)
 
     def fine_shape(self, precision: int = AP_PREC_FP32) -> tuple[int, int, int]:
-        """(shape, threads per workgroup, slices per workgroup) of fine batches."""
+        """(configuration, threads per workgroup, slices per workgroup) of fine
+        batches; configuration c is workgroup shape c % 3 with FFT plan c // 3."""
         sh, nt, j = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
         _check(lib().aparareal_fine_shape(self._h, int(precision), ctypes.byref(sh), ctypes.byref(nt),
                                           ctypes.byref(j)))

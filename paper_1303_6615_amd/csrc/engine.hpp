@@ -22,27 +22,28 @@ constexpr size_t y_bytes() {
   return 3 * size_t(Geo<NX>::KP) * sizeof(cx<T>);
 }
 
-template <typename T, int NX>
+template <typename T, int NX, int PLAN = 0>
 constexpr bool twiddles_in_lds() {
-  return tw_elems<NX / 2>() * sizeof(cx<T>) + Slot<T, NX>::bytes + y_bytes<T, NX>() <= kLdsBudget;
+  return tw_elems<NX / 2, PLAN>() * sizeof(cx<T>) + Slot<T, NX>::bytes + y_bytes<T, NX>() <= kLdsBudget;
 }
 
-template <typename T, int NX, int NT>
+template <typename T, int NX, int NT, int PLAN = 0>
 constexpr int max_slots() {
-  const size_t fixed = (twiddles_in_lds<T, NX>() ? tw_elems<NX / 2>() * sizeof(cx<T>) : 0) + y_bytes<T, NX>();
+  const size_t fixed =
+      (twiddles_in_lds<T, NX, PLAN>() ? tw_elems<NX / 2, PLAN>() * sizeof(cx<T>) : 0) + y_bytes<T, NX>();
   const size_t s = (kLdsBudget - fixed) / Slot<T, NX>::bytes;
   return s >= 32 ? 32 : (s < 1 ? 1 : int(s));
 }
 
-template <typename T, int NX, int NT, int S>
+template <typename T, int NX, int NT, int S, int PLAN = 0>
 struct Engine {
   using G = Geo<NX>;
   using SL = Slot<T, NX>;
   static constexpr int P = G::P;
   static constexpr int KP = G::KP;
   static constexpr int MPT = (KP + NT - 1) / NT;
-  static constexpr bool TW_LDS = twiddles_in_lds<T, NX>();
-  static constexpr int TWN = tw_elems<NX / 2>();   // twiddle table entries
+  static constexpr bool TW_LDS = twiddles_in_lds<T, NX, PLAN>();
+  static constexpr int TWN = tw_elems<NX / 2, PLAN>();   // twiddle table entries of FFT plan PLAN
   static_assert(NT % 64 == 0, "whole wavefronts");
   static_assert(SL::ib_elems >= size_t(3) * KP, "per-sample contributions fit a slot's ib");
   static constexpr size_t lds_bytes() {
@@ -128,9 +129,9 @@ struct Engine {
       if (ow.valid(j)) put_fields<T, NX>(sps, ow.s, ow.mode(j), x[j], bs[j]);
     zero_tails<T, NX, NT>(sps, J);
     __syncthreads();
-    inverse_fields<T, NX, NT, jmax()>(sps, ibs, J, tw);
+    inverse_fields<T, NX, NT, jmax(), PLAN>(sps, ibs, J, tw);
     __syncthreads();
-    forward_products<T, NX, NT, jmax()>(sps, ibs, J, tw);
+    forward_products<T, NX, NT, jmax(), PLAN>(sps, ibs, J, tw);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
@@ -234,12 +235,12 @@ __device__ __forceinline__ cx<T> rot_out(cx<T> c, cx<T> e, int alpha_idx) {
 // state would drop those increments coherently step after step.  With
 // T = float the stage states a, b, c, the nonlinear evaluations and the
 // products f*N run in FP32.
-template <typename T, int NX, int NT, int S, int JM = 0>
-__device__ __forceinline__ void fine_job(Engine<T, NX, NT, S>& en, int Jrun, const cx<double>* __restrict__ src0,
+template <typename T, int NX, int NT, int S, int JM = 0, int PLAN = 0>
+__device__ __forceinline__ void fine_job(Engine<T, NX, NT, S, PLAN>& en, int Jrun, const cx<double>* __restrict__ src0,
                                          const cx<double>* __restrict__ src1, cx<double>* __restrict__ dst,
                                          int steps, const cx<double>* __restrict__ coef64,
                                          const cx<T>* __restrict__ coef, const Basis<T>* __restrict__ basis) {
-  using E_ = Engine<T, NX, NT, S>;
+  using E_ = Engine<T, NX, NT, S, PLAN>;
   constexpr int KP = E_::KP;
   constexpr int MPT = E_::MPT;
   const int J = JM == 1 ? 1 : Jrun;   // JM = 1: a single slice, known when compiling

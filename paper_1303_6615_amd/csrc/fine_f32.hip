@@ -7,7 +7,7 @@ namespace ap {
 
 hipError_t launch_fine_f32(int nx, int shape, const cx<double>* in, cx<double>* out, int batch, int steps,
                            const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s) {
-  AP_DISPATCH_NX(nx, (fine_launch_shape<float, NX>(shape, in, out, batch, steps, coef64, coef32, t.tw32, t.basis32, s)));
+  AP_DISPATCH_NX(nx, (fine_launch_config<float, NX>(shape, in, out, batch, steps, coef64, coef32, t, s)));
 }
 int fine_shape_f32(int nx, int shape, int* slices) {
   AP_DISPATCH_NX_INT(nx, (fine_shape_info<float, NX>(shape, slices)));

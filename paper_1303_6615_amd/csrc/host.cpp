@@ -368,7 +368,12 @@ std::vector<std::string> read_lines(const std::string& path) {
   return out;
 }
 
-// The cached shape for (device, N, precision), or -1.
+// A fine-batch configuration (workgroup shape and FFT plan) compiled for N.
+bool fine_config_valid(int N, int config) {
+  return config >= 0 && config < ap::kFineConfigCount && ap::fine_shape(N, false, config, nullptr) > 0;
+}
+
+// The cached configuration for (device, N, precision), or -1.
 int tune_lookup(const std::string& dev, int N, int precision) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   const std::string key = "fine " + dev + " " + std::to_string(N) + " " + std::to_string(precision) + " ";
@@ -376,7 +381,7 @@ int tune_lookup(const std::string& dev, int N, int precision) {
   for (const std::string& ln : read_lines(tune_cache_path()))
     if (ln.compare(0, key.size(), key) == 0) {
       const int v = std::atoi(ln.c_str() + key.size());
-      if (v >= 0 && v < ap::kFineShapeCount) shape = v;
+      if (fine_config_valid(N, v)) shape = v;
     }
   return shape;
 }
@@ -405,8 +410,8 @@ void tune_store(const std::string& dev, int N, int precision, int shape) {
   else (void)std::remove(tmp.c_str());
 }
 
-// Workgroup shape of the context's fine batches in this precision: the option
-// if set, else the tuned shape, else the default.
+// Configuration (workgroup shape and FFT plan) of the context's fine batches
+// in this precision: the option if set, else the tuned one, else the default.
 int fine_shape_of(const ap_ctx* c, int precision) {
   if (c->opt_fine_shape >= 0) return c->opt_fine_shape;
   const int t = c->tuned_shape[precision == AP_PREC_FP64 ? 1 : 0];
@@ -1273,18 +1278,20 @@ ap_ctx* aparareal_create(int N, double eps, double F, double nu) {
     b64[k] = {1.0 / w, a / w};
     b32[k] = {float(1.0 / w), float(a / w)};
   }
-  // twiddles: exp(-2 pi i t/N), t < N, then the per-pass tables of the
-  // wave-local FFT of length N/2 (exp(-2 pi i q k/(NS R)) at (q-1) NS + k)
+  // twiddles, per FFT plan: exp(-2 pi i t/N), t < N, then the per-pass
+  // tables of the wave-local FFT of length N/2 (exp(-2 pi i q k/(NS R)) at
+  // (q-1) NS + k); plan 1's table (where there is one) follows plan 0's
   std::vector<cx<double>> t64;
   std::vector<cx<float>> t32;
   auto push = [&](double th) {
     t64.push_back(cx<double>{std::cos(th), -std::sin(th)});
     t32.push_back(cx<float>{float(std::cos(th)), float(-std::sin(th))});
   };
-  for (int t = 0; t < N; ++t) push(2.0 * M_PI * double(t) / double(N));
-  {
+  for (int plan = 0; plan < ap::wave_plans(N / 2); ++plan) {
+    if (plan == 1) c->tabs.tw_plan1 = int(t64.size());
+    for (int t = 0; t < N; ++t) push(2.0 * M_PI * double(t) / double(N));
     int r[4], npass = 0;
-    ap::wave_plan_radices(N / 2, r, &npass);
+    ap::wave_plan_radices(N / 2, r, &npass, plan);
     int NS = r[0];
     for (int j = 1; j < npass; ++j) {
       const int R = r[j];
@@ -1375,6 +1382,18 @@ int aparareal_fine_shape(ap_ctx* c, int precision, int* shape, int* threads, int
   return AP_OK;
 }
 
+int aparareal_fft_plan(int N, int plan, int* radices, int* passes, int* reg_exchanges) {
+  if (N < 64 || N > 2048 || (N & (N - 1)) != 0) return fail(AP_EINVAL, "N must be a power of two in [64, 2048]");
+  if (plan < 0 || plan >= ap::wave_plans(N / 2)) return fail(AP_EINVAL, "no such FFT plan for this N");
+  int r[4], n = 0, x = 0;
+  ap::wave_plan_radices(N / 2, r, &n, plan, &x);
+  if (radices)
+    for (int i = 0; i < 4; ++i) radices[i] = i < n ? r[i] : 1;
+  if (passes) *passes = n;
+  if (reg_exchanges) *reg_exchanges = x;
+  return AP_OK;
+}
+
 int aparareal_autotune_fine(ap_ctx* c, const double* U_in, int batch, double dT, int steps, int precision,
                             void* stream, double* shape_ms, int* best) {
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1390,9 +1409,11 @@ int aparareal_autotune_fine(ap_ctx* c, const double* U_in, int batch, double dT,
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
-  double ms[ap::kFineShapeCount];
+  double ms[ap::kFineConfigCount];
   int pick = 0;
-  for (int sh = 0; e == hipSuccess && sh < ap::kFineShapeCount; ++sh) {
+  for (int sh = 0; e == hipSuccess && sh < ap::kFineConfigCount; ++sh) {
+    ms[sh] = -1.0;
+    if (!fine_config_valid(c->N, sh)) continue;
     auto run = [&] {
       return ap::launch_fine(c->N, f64, c->ws_in.as<cx<double>>(), c->ws_out.as<cx<double>>(), batch, steps,
                              ft->coef64.as<cx<double>>(), ft->coef32.as<cx<float>>(), c->tabs, s, sh);
@@ -1409,11 +1430,11 @@ int aparareal_autotune_fine(ap_ctx* c, const double* U_in, int batch, double dT,
   }
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
-  if (e != hipSuccess) return hip_fail(e, "fine shape tuning");
+  if (e != hipSuccess) return hip_fail(e, "fine configuration tuning");
   c->tuned_shape[f64 ? 1 : 0] = pick;
   tune_store(c->device_key, c->N, precision, pick);
   if (shape_ms)
-    for (int sh = 0; sh < ap::kFineShapeCount; ++sh) shape_ms[sh] = ms[sh];
+    for (int sh = 0; sh < ap::kFineConfigCount; ++sh) shape_ms[sh] = ms[sh];
   if (best) *best = pick;
   return AP_OK;
 }
@@ -1765,7 +1786,9 @@ int aparareal_set_option(ap_ctx* c, int option, int value) {
       c->opt_coarse = value;
       return AP_OK;
     case AP_OPT_FINE_SHAPE:
-      if (value < -1 || value >= ap::kFineShapeCount) return fail(AP_EINVAL, "AP_OPT_FINE_SHAPE takes -1, 0, 1 or 2");
+      if (value != -1 && !fine_config_valid(c->N, value))
+        return fail(AP_EINVAL, "AP_OPT_FINE_SHAPE takes -1 or a configuration 0..5 compiled for this N "
+                               "(3..5 need N >= 256)");
       c->opt_fine_shape = value;
       return AP_OK;
     case AP_OPT_HANDOFF_NS:

@@ -8,12 +8,14 @@ namespace ap {
 
 // Per-context device tables that depend only on the grid and F.
 struct DevTables {
-  const cx<double>* tw64 = nullptr;      // exp(-2 pi i t / N), t < N
+  const cx<double>* tw64 = nullptr;      // exp(-2 pi i t / N), t < N, then FFT plan 0's pass tables
   const cx<float>* tw32 = nullptr;
   const Basis<double>* basis64 = nullptr;  // per retained k: 1/omega_k, a_k/omega_k
   const Basis<float>* basis32 = nullptr;
+  int tw_plan1 = 0;                      // entry where FFT plan 1's table starts (same layout)
   template <typename T> const cx<T>* tw() const;
   template <typename T> const Basis<T>* basis() const;
+  template <typename T> const cx<T>* tw_plan(int plan) const { return tw<T>() + (plan == 1 ? tw_plan1 : 0); }
 };
 template <> inline const cx<double>* DevTables::tw<double>() const { return tw64; }
 template <> inline const cx<float>* DevTables::tw<float>() const { return tw32; }
@@ -98,8 +100,9 @@ hipError_t launch_to_physical(int nx, const cx<double>* modal, double* phys, int
                               hipStream_t s);
 hipError_t launch_nonlinear(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch,
                             const DevTables& t, hipStream_t s);
-// The fine batch in workgroup shape `shape` (0 .. 2; 0 the default); the
-// shape changes no result.
+// The fine batch in configuration `shape` (0 .. 5: workgroup shape
+// shape % 3, FFT plan shape / 3; 0 the default); the workgroup shape changes
+// no result, plan 1 rounds differently at N = 1024 only.
 hipError_t launch_fine(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch, int steps,
                        const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s,
                        int shape = 0);
@@ -107,13 +110,14 @@ hipError_t launch_fine_f32(int nx, int shape, const cx<double>* in, cx<double>* 
                            const cx<double>* coef64, const cx<float>* coef32, const DevTables& t, hipStream_t s);
 hipError_t launch_fine_f64(int nx, int shape, const cx<double>* in, cx<double>* out, int batch, int steps,
                            const cx<double>* coef64, const DevTables& t, hipStream_t s);
-// Threads per workgroup of a fine-batch shape (0 if none) and its slices per workgroup.
+// Threads per workgroup of a fine-batch configuration (0 if it is not
+// compiled at this grid size) and its slices per workgroup.
 int fine_shape_f32(int nx, int shape, int* slices);
 int fine_shape_f64(int nx, int shape, int* slices);
 inline int fine_shape(int nx, bool fp64, int shape, int* slices) {
   return fp64 ? fine_shape_f64(nx, shape, slices) : fine_shape_f32(nx, shape, slices);
 }
-constexpr int kFineShapeCount = 3;
+constexpr int kFineConfigCount = 6;   // 3 workgroup shapes x 2 FFT plans
 // `steps` Strang steps of size h (coef64 slot 2: e^{(h/2) lambda}) per state.
 hipError_t launch_strang(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch, int steps, double h,
                          const cx<double>* coef64, const DevTables& t, hipStream_t s);

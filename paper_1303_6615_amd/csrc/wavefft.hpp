@@ -94,47 +94,66 @@ __device__ __forceinline__ void dft_reg(cx<T> (&x)[R]) {
 // wave_pass_first_pair): at P = 512, radices 8, 4, 4, 4 take the same
 // arithmetic as 8, 8, 8 and move the data through LDS four times instead of
 // six.
-template <int P> struct WavePlan;
+//   PLAN 0 is that plan (the one every kernel uses).  PLAN 1, an alternative
+// for the fine batch's autotuner at P >= 128, is the classic Stockham FFT:
+// the same radices with every exchange through LDS, and at P = 512 radices
+// 8, 8, 8.  PLAN 1 rounds like PLAN 0 except at P = 512.
+template <int P, int PLAN = 0> struct WavePlan;
 template <> struct WavePlan<32>   { static constexpr int G = 8,  n = 2, r0 = 4,  r1 = 8, r2 = 1, r3 = 1; };
 template <> struct WavePlan<64>   { static constexpr int G = 16, n = 3, r0 = 4,  r1 = 4, r2 = 4, r3 = 1; };
 template <> struct WavePlan<128>  { static constexpr int G = 32, n = 4, r0 = 4,  r1 = 4, r2 = 4, r3 = 2; };
 template <> struct WavePlan<256>  { static constexpr int G = 64, n = 4, r0 = 4,  r1 = 4, r2 = 4, r3 = 4; };
 template <> struct WavePlan<512>  { static constexpr int G = 64, n = 4, r0 = 8,  r1 = 4, r2 = 4, r3 = 4; };
 template <> struct WavePlan<1024> { static constexpr int G = 64, n = 3, r0 = 16, r1 = 8, r2 = 8, r3 = 1; };
+template <int P> struct WavePlan<P, 1> : WavePlan<P, 0> {};
+template <> struct WavePlan<512, 1> { static constexpr int G = 64, n = 3, r0 = 8, r1 = 8, r2 = 8, r3 = 1; };
+
+// FFT plans compiled for transform length P (PLAN 1 only where it differs).
+constexpr int wave_plans(int P) { return P >= 128 ? 2 : 1; }
 
 // Twiddle table of a grid size N = 2P: entries t < N hold exp(-2 pi i t/N)
 // (real-signal pre/post-processing); then, for each pass j after the first,
 // exp(-2 pi i q k / (NS R)) at [offset_j + (q-1) NS + k] (q = 1..R-1, k < NS;
 // NS points combined before the pass, radix R), contiguous in k so that the
 // lanes of a pass read consecutive entries.
-template <int P>
+// Each plan has a table of its own (the host stores plan 1's after plan 0's).
+template <int P, int PLAN = 0>
 constexpr int pass1_tw_offset() { return 2 * P; }
-template <int P>
-constexpr int pass2_tw_offset() { return 2 * P + (WavePlan<P>::r1 - 1) * WavePlan<P>::r0; }
-template <int P>
+template <int P, int PLAN = 0>
+constexpr int pass2_tw_offset() { return 2 * P + (WavePlan<P, PLAN>::r1 - 1) * WavePlan<P, PLAN>::r0; }
+template <int P, int PLAN = 0>
 constexpr int pass3_tw_offset() {
-  using PL = WavePlan<P>;
-  return pass2_tw_offset<P>() + (PL::r2 - 1) * PL::r0 * PL::r1;
+  using PL = WavePlan<P, PLAN>;
+  return pass2_tw_offset<P, PLAN>() + (PL::r2 - 1) * PL::r0 * PL::r1;
 }
-template <int P>
+template <int P, int PLAN = 0>
 constexpr int tw_elems() {
-  using PL = WavePlan<P>;
-  return PL::n == 4   ? pass3_tw_offset<P>() + (PL::r3 - 1) * PL::r0 * PL::r1 * PL::r2
-         : PL::n == 3 ? pass3_tw_offset<P>()
-                      : pass2_tw_offset<P>();
+  using PL = WavePlan<P, PLAN>;
+  return PL::n == 4   ? pass3_tw_offset<P, PLAN>() + (PL::r3 - 1) * PL::r0 * PL::r1 * PL::r2
+         : PL::n == 3 ? pass3_tw_offset<P, PLAN>()
+                      : pass2_tw_offset<P, PLAN>();
 }
 
-// The radices of the plan for transform length P (host side, for the tables).
-inline void wave_plan_radices(int P, int r[4], int* n) {
+// The radices of plan `plan` for transform length P (host side, for the
+// tables and the plan queries); *regx: exchanges done by row swaps.
+inline void wave_plan_radices(int P, int r[4], int* n, int plan = 0, int* regx = nullptr) {
   r[3] = 1;
+  int x = 0;
   switch (P) {
-    case 32: r[0] = 4; r[1] = 8; r[2] = 1; *n = 2; return;
-    case 64: r[0] = 4; r[1] = 4; r[2] = 4; *n = 3; return;
-    case 128: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 2; *n = 4; return;
-    case 256: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 4; *n = 4; return;
-    case 512: r[0] = 8; r[1] = 4; r[2] = 4; r[3] = 4; *n = 4; return;
-    default: r[0] = 16; r[1] = 8; r[2] = 8; *n = 3; return;
+    case 32: r[0] = 4; r[1] = 8; r[2] = 1; *n = 2; break;
+    case 64: r[0] = 4; r[1] = 4; r[2] = 4; *n = 3; break;
+    case 128: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 2; *n = 4; x = 1; break;
+    case 256: r[0] = 4; r[1] = 4; r[2] = 4; r[3] = 4; *n = 4; x = 2; break;
+    case 512:
+      if (plan == 1) {
+        r[0] = 8; r[1] = 8; r[2] = 8; *n = 3;
+      } else {
+        r[0] = 8; r[1] = 4; r[2] = 4; r[3] = 4; *n = 4; x = 2;
+      }
+      break;
+    default: r[0] = 16; r[1] = 8; r[2] = 8; *n = 3; x = 1; break;
   }
+  if (regx) *regx = plan == 1 ? 0 : x;
 }
 
 // LDS layouts between passes.  A pass writes position pos to
@@ -169,10 +188,16 @@ __device__ __forceinline__ int swz(int pos) {
 // wave_pass_first_pair
 template <typename T, int P>
 constexpr int swz_pass0() { return kSwzR; }
-template <typename T, int P>
+template <typename T, int P, int PLAN = 0>
 constexpr int swz_pass1() {
-  if constexpr (sizeof(T) == 4) return P < 256 ? kSwzR5 : P == 256 ? kSwzR9 : P == 512 ? kSwzRx1 : kSwzRx2;
-  else return P < 256 ? kSwzR5 : P == 256 ? kSwzR : P == 512 ? kSwzRh1 : kSwzId;
+  if constexpr (PLAN == 1) {
+    if constexpr (sizeof(T) == 4) return P <= 256 ? kSwzR5 : kSwzRx2;
+    else return P <= 256 ? kSwzR5 : P == 512 ? kSwzRx1 : kSwzId;
+  } else if constexpr (sizeof(T) == 4) {
+    return P < 256 ? kSwzR5 : P == 256 ? kSwzR9 : P == 512 ? kSwzRx1 : kSwzRx2;
+  } else {
+    return P < 256 ? kSwzR5 : P == 256 ? kSwzR : P == 512 ? kSwzRh1 : kSwzId;
+  }
 }
 // layout written by pass 2 of a four-pass plan (radix 4 after 16 points)
 template <typename T, int P>
@@ -398,9 +423,9 @@ __device__ __forceinline__ void row_swap(cx<T>& a, cx<T>& b) {
 //     radix 4; lane bit 5 <-> register bit 0 of each butterfly;
 //   P = 1024 (G = 64): A radix 8 with 2 butterflies per lane, B radix 8;
 //     lane bits 4, 5 <-> register bits 0, 1 of each butterfly.
-template <int P>
+template <int P, int PLAN = 0>
 constexpr bool last_pair_in_registers() {
-  return P == 128 || P == 256 || P == 512 || P == 1024;
+  return PLAN == 0 && (P == 128 || P == 256 || P == 512 || P == 1024);
 }
 
 template <typename T, int P, int RA, int NSA, int RB, int NSB, int DIR, int G, bool BATCH, typename Src, typename WA,
@@ -474,9 +499,9 @@ __device__ __forceinline__ void wave_pass_pair(cx<T>* buf, const cx<T>* tw, cons
 // (rotated_butterfly), i = register bit 2 at P = 512.  Pass 1 runs those
 // butterflies and stores them through layout SW1 for pass 2.  The arithmetic
 // is that of the two passes through LDS.
-template <int P>
+template <int P, int PLAN = 0>
 constexpr bool first_pair_in_registers() {
-  return P == 256 || P == 512;
+  return PLAN == 0 && (P == 256 || P == 512);
 }
 
 template <typename T, int P, int R0, int R1, int DIR, int G, int SW1, bool BATCH, typename Src, typename W1>
@@ -508,29 +533,29 @@ __device__ __forceinline__ void wave_pass_first_pair(cx<T>* buf, const cx<T>* tw
 
 // Unnormalised complex FFT of length P by one lane group, result in `buf`
 // (natural order); the first pass reads its inputs from `src`.
-template <typename T, int P, int DIR, typename Src>
+template <typename T, int P, int DIR, int PLAN = 0, typename Src>
 __device__ __forceinline__ void wave_fft(cx<T>* buf, const cx<T>* tw, int lig, const Src& src) {
-  using PL = WavePlan<P>;
+  using PL = WavePlan<P, PLAN>;
   constexpr bool PRE = tw_in_registers<T, P>();
   constexpr int S0 = swz_pass0<T, P>();
-  constexpr int S1 = PL::n >= 3 ? swz_pass1<T, P>() : kSwzId;
+  constexpr int S1 = PL::n >= 3 ? swz_pass1<T, P, PLAN>() : kSwzId;
   NoTw<T> none;
-  PassTw<T, P, PL::r1, PL::r0, PL::G, pass1_tw_offset<P>(), PRE> w1;
-  if constexpr (first_pair_in_registers<P>()) {
-    static_assert(PL::n == 4 && !PRE && last_pair_in_registers<P>(), "plan");
+  PassTw<T, P, PL::r1, PL::r0, PL::G, pass1_tw_offset<P, PLAN>(), PRE> w1;
+  if constexpr (first_pair_in_registers<P, PLAN>()) {
+    static_assert(PL::n == 4 && !PRE && last_pair_in_registers<P, PLAN>(), "plan");
     constexpr int NS2 = PL::r0 * PL::r1, NS3 = NS2 * PL::r2;
-    PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P>(), PRE> w2;
-    PassTw<T, P, PL::r3, NS3, PL::G, pass3_tw_offset<P>(), PRE> w3;
+    PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P, PLAN>(), PRE> w2;
+    PassTw<T, P, PL::r3, NS3, PL::G, pass3_tw_offset<P, PLAN>(), PRE> w3;
     wave_pass_first_pair<T, P, PL::r0, PL::r1, DIR, PL::G, S1, PRE>(buf, tw, w1, lig, src);
     wave_pass_pair<T, P, PL::r2, NS2, PL::r3, NS3, DIR, PL::G, PRE>(buf, tw, w2, w3, lig, ReadLayout<T, S1>{buf});
   } else if constexpr (PL::n == 4) {
     constexpr int S2 = swz_pass2<T, P>();
     constexpr int NS2 = PL::r0 * PL::r1, NS3 = NS2 * PL::r2;
-    PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P>(), PRE> w2;
-    PassTw<T, P, PL::r3, NS3, PL::G, pass3_tw_offset<P>(), PRE> w3;
+    PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P, PLAN>(), PRE> w2;
+    PassTw<T, P, PL::r3, NS3, PL::G, pass3_tw_offset<P, PLAN>(), PRE> w3;
     wave_pass<T, P, PL::r0, 1, DIR, PL::G, S0, PRE>(buf, tw, none, w1, lig, src);
     wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
-    if constexpr (last_pair_in_registers<P>()) {
+    if constexpr (last_pair_in_registers<P, PLAN>()) {
       wave_pass_pair<T, P, PL::r2, NS2, PL::r3, NS3, DIR, PL::G, PRE>(buf, tw, w2, w3, lig, ReadLayout<T, S1>{buf});
     } else {
       wave_pass<T, P, PL::r2, NS2, DIR, PL::G, S2, PRE>(buf, tw, w2, w3, lig, ReadLayout<T, S1>{buf});
@@ -538,9 +563,9 @@ __device__ __forceinline__ void wave_fft(cx<T>* buf, const cx<T>* tw, int lig, c
     }
   } else if constexpr (PL::n == 3) {
     constexpr int NS2 = PL::r0 * PL::r1;
-    PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P>(), PRE> w2;
+    PassTw<T, P, PL::r2, NS2, PL::G, pass2_tw_offset<P, PLAN>(), PRE> w2;
     wave_pass<T, P, PL::r0, 1, DIR, PL::G, S0, PRE>(buf, tw, none, w1, lig, src);
-    if constexpr (last_pair_in_registers<P>()) {
+    if constexpr (last_pair_in_registers<P, PLAN>()) {
       wave_pass_pair<T, P, PL::r1, PL::r0, PL::r2, NS2, DIR, PL::G, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
     } else {
       wave_pass<T, P, PL::r1, PL::r0, DIR, PL::G, S1, PRE>(buf, tw, w1, w2, lig, ReadLayout<T, S0>{buf});
@@ -608,7 +633,7 @@ __device__ __forceinline__ void signal_rounds(int nsig, B&& body) {
   }
 }
 
-template <typename T, int NX, int NT, int MAXNS = 0>
+template <typename T, int NX, int NT, int MAXNS = 0, int PLAN = 0>
 __device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, const cx<T>* tw) {
   using G_ = Geo<NX>;
   constexpr int P = G_::P;
@@ -621,7 +646,7 @@ __device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, con
     const int v = v0 + group < nsig ? v0 + group : v0;
     int off = v * (P + 1);
     asm volatile("" : "+v"(off));
-    wave_fft<T, P, +1>(ib + v * P, tw, lig, ReadHalfSpectrum<T, P>{sp + off, tw});
+    wave_fft<T, P, +1, PLAN>(ib + v * P, tw, lig, ReadHalfSpectrum<T, P>{sp + off, tw});
   });
 }
 
@@ -660,7 +685,7 @@ struct ReadProducts {
 // written into SP (stride P+1): v1^2/2, v1 v2x, h v1.  The first pass reads
 // both factors and scales by 1/2 or 1, with no branch on the product; lane
 // groups past the last signal repeat their wavefront's first one.
-template <typename T, int NX, int NT, int MAXNS = 0>
+template <typename T, int NX, int NT, int MAXNS = 0, int PLAN = 0>
 __device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int ns, const cx<T>* tw) {
   constexpr int P = Geo<NX>::P;
   constexpr int G = WavePlan<P>::G;
@@ -674,7 +699,7 @@ __device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int
     const cx<T>* V1 = ib + (3 * s) * P;
     const cx<T>* W = ib + (3 * s + (f == 2 ? 2 : f)) * P;   // v1 itself for the square
     const T scale = f == 0 ? T(0.5) : T(1);
-    wave_fft<T, P, -1>(sp + vv * (P + 1), tw, lig, ReadProducts<T>{V1, W, scale});
+    wave_fft<T, P, -1, PLAN>(sp + vv * (P + 1), tw, lig, ReadProducts<T>{V1, W, scale});
   });
 }
 

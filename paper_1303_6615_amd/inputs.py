@@ -97,7 +97,7 @@ class SolveConfig:
         return self.K * self.slices * self.fine_steps * self.nx
 
 
-# Single-solve workloads (sizes of the spec configurations).
+# Single-solve workloads: N = 64 FP64 (small), N = 256 and N = 1024 (FP32 propagators).
 C1 = SolveConfig("rsw-n64-eps1e-2-s16-k5-fp64", nx=64, eps=0.01, nu=1e-4, T=1.0,
                  slices=16, K=5, dt=0.01 / 20, Mbar=16, k_ic=8, seed=1,
                  precision=PREC_FP64)

@@ -221,3 +221,27 @@ def test_counted_work_matches_the_jobs_run(L, Ns, K):
     gp, flops = metrics.pipelined_work(256, Ns, K, 7, 32)
     assert gp == fine * 7 * 256
     assert flops == pytest.approx(metrics.fine_flops(256, fine, 7) + coarse * metrics.coarse_step_flops(256, 32))
+
+
+def test_fft_plans_multiply_to_the_transform_length(L):
+    # the wave-local FFT of length N/2 (host query, no device): every plan's
+    # radices multiply to N/2; plan 1 (the fine batch's alternative) exists
+    # from N = 256 on, moves every exchange through LDS, and at N = 1024 uses
+    # radices 8, 8, 8 instead of plan 0's 8, 4, 4, 4
+    import re
+    hdr = open(os.path.join(os.path.dirname(LIB_PATH), "..", "include", "aparareal.h")).read()
+    assert int(re.search(r"AP_FINE_CONFIGS\s*=\s*(\d+)", hdr).group(1)) == binding.AP_FINE_CONFIGS == 6
+    for N in (64, 128, 256, 512, 1024, 2048):
+        p0 = binding.fft_plan(N, 0)
+        assert math.prod(p0["radices"]) == N // 2 and all(r in (2, 4, 8, 16) for r in p0["radices"])
+        assert p0["register_exchanges"] == {64: 0, 128: 0, 256: 1, 512: 2, 1024: 2, 2048: 1}[N]
+        if N >= 256:
+            p1 = binding.fft_plan(N, 1)
+            assert math.prod(p1["radices"]) == N // 2 and p1["register_exchanges"] == 0
+            assert p1["radices"] == ([8, 8, 8] if N == 1024 else p0["radices"])
+        else:
+            with pytest.raises(binding.APError):
+                binding.fft_plan(N, 1)
+    for N, plan in ((100, 0), (4096, 0), (256, 2), (256, -1)):
+        with pytest.raises(binding.APError):
+            binding.fft_plan(N, plan)

@@ -614,13 +614,17 @@ def test_replay_asymptotic_configuration_matches_the_oracle(torch_cuda):
 
 @pytest.mark.parametrize("n,eps,dT,steps,prec,tol", [
     (256, 0.01, 0.03125, 8, FP32, 2e-5), (1024, 0.001, 1.0 / 256, 6, FP32, 2e-5),
+    (512, 0.01, 1.0 / 64, 5, FP64, 1e-11), (1024, 0.01, 1.0 / 64, 4, FP64, 1e-11),
     (64, 0.01, 1.0 / 16, 9, FP64, 1e-11), (2048, 0.01, 0.01, 3, FP64, 1e-11)])
-def test_fine_batch_shapes_and_their_autotuner(torch_cuda, tmp_path, monkeypatch, n, eps, dT, steps, prec, tol):
-    # every compiled workgroup shape of the fine batch gives the same bits
-    # (a slice rounds the same way whatever workgroup steps it) and the
-    # oracle's values; the autotuner keeps the fastest, records it in the
-    # tuning cache, and a new context reads it back
-    from paper_1303_6615_amd.binding import AP_OPT_FINE_SHAPE
+def test_fine_batch_configurations_and_their_autotuner(torch_cuda, tmp_path, monkeypatch, n, eps, dT, steps, prec,
+                                                       tol):
+    # every compiled configuration of the fine batch (workgroup shape c % 3,
+    # FFT plan c // 3, plan 1 from N = 256 on) keeps the oracle's values; the
+    # workgroup shape gives the same bits (a slice rounds the same way whatever
+    # workgroup steps it), and so does plan 1 except at N = 1024, whose plan 1
+    # has other radices; the autotuner keeps the fastest configuration,
+    # records it in the tuning cache, and a new context reads it back
+    from paper_1303_6615_amd.binding import AP_OPT_FINE_SHAPE, AP_FINE_CONFIGS, APError
     torch = torch_cuda
     monkeypatch.setenv("APARAREAL_TUNE_CACHE", str(tmp_path / "tune.txt"))
     nu = NU_BY_NX[n]
@@ -628,22 +632,32 @@ def test_fine_batch_shapes_and_their_autotuner(torch_cuda, tmp_path, monkeypatch
     ud = torch.tensor(u, device="cuda")
     uh = O.project(O.to_spectral(u[:4]), n)
     ref = O.to_physical(O.fine_propagate(uh, n, eps, 1.0, nu, dT, steps), n)
+    configs = list(range(AP_FINE_CONFIGS if n >= 256 else 3))
     with _ctx(n, eps, nu) as ctx:
-        outs, shapes = [], []
-        for sh in range(3):
-            ctx.set_option(AP_OPT_FINE_SHAPE, sh)
-            outs.append(ctx.fine_batch(ud, dT, steps, precision=prec))
-            shapes.append(ctx.fine_shape(prec))
+        outs, shapes = {}, {}
+        for c in configs:
+            ctx.set_option(AP_OPT_FINE_SHAPE, c)
+            outs[c] = ctx.fine_batch(ud, dT, steps, precision=prec)
+            shapes[c] = ctx.fine_shape(prec)
         torch.cuda.synchronize()
-        assert len({s[1] for s in shapes}) == 3, shapes           # three distinct workgroup sizes
-        for o in outs[1:]:
-            assert torch.equal(o, outs[0])
-        assert _rel(outs[0][:4].cpu().numpy(), ref) < tol
+        if n < 256:
+            with pytest.raises(APError):
+                ctx.set_option(AP_OPT_FINE_SHAPE, 3)
+        assert len({shapes[c][1] for c in range(3)}) == 3, shapes       # three distinct workgroup sizes
+        for c in configs:
+            assert shapes[c][0] == c
+            same = c < 3 or n != 1024
+            if same:
+                assert torch.equal(outs[c], outs[0]), c
+            else:
+                assert torch.equal(outs[c], outs[3]), c                 # shapes of plan 1 agree bitwise
+            assert _rel(outs[c][:4].cpu().numpy(), ref) < tol, c
         ctx.set_option(AP_OPT_FINE_SHAPE, -1)
         best, ms = ctx.autotune_fine(ud, dT, steps, precision=prec)
-        assert best in (0, 1, 2) and all(m > 0 for m in ms) and ms[best] == min(ms)
+        assert best in configs and all(ms[c] > 0 for c in configs) and ms[best] == min(ms[c] for c in configs)
+        assert all(ms[c] == -1 for c in range(AP_FINE_CONFIGS) if c not in configs)
         assert ctx.fine_shape(prec)[0] == best
-        assert torch.equal(ctx.fine_batch(ud, dT, steps, precision=prec), outs[0])
+        assert torch.equal(ctx.fine_batch(ud, dT, steps, precision=prec), outs[best])
     with _ctx(n, eps, nu) as fresh:
         assert fresh.fine_shape(prec)[0] == best
     assert f" {n} {prec} {best}" in (tmp_path / "tune.txt").read_text()
