@@ -35,13 +35,17 @@ constexpr int max_slots() {
   return s >= 32 ? 32 : (s < 1 ? 1 : int(s));
 }
 
-template <typename T, int NX, int NT, int S, int PLAN = 0>
+template <typename T, int NX, int NT, int S, int PLAN = 0, int IMAX = 1>
 struct Engine {
   using G = Geo<NX>;
   using SL = Slot<T, NX>;
   static constexpr int P = G::P;
   static constexpr int KP = G::KP;
   static constexpr int MPT = (KP + NT - 1) / NT;
+  // (slice, mode) items a thread may own in a job over several slices: IMAX
+  // (when above MPT) lets a job step more slices than one mode per thread
+  // allows, with that many items per thread
+  static constexpr int IPT = IMAX > MPT ? IMAX : MPT;
   static constexpr bool TW_LDS = twiddles_in_lds<T, NX, PLAN>();
   static constexpr int TWN = tw_elems<NX / 2, PLAN>();   // twiddle table entries of FFT plan PLAN
   static_assert(NT % 64 == 0, "whole wavefronts");
@@ -79,12 +83,13 @@ struct Engine {
   static __device__ __forceinline__ int mode(int j) { return threadIdx.x + j * NT; }
   static __device__ __forceinline__ bool valid(int j) { return mode(j) < KP; }
 
-  // Most slices one job can step together: one retained mode per thread, and
-  // one round of transforms over the wavefronts, and two slots per slice
-  // (alternating evaluations need no extra barrier).
+  // Most slices one job can step together: IPT items per thread (one mode
+  // per thread unless IMAX says more), one round of transforms over the
+  // wavefronts, and two slots per slice (alternating evaluations need no
+  // extra barrier).
   static constexpr int jmax() {
-    if (MPT > 1) return 1;
-    const int by_threads = NT / KP;
+    if (MPT > 1 && IPT <= MPT) return 1;
+    const int by_threads = IPT * NT / KP;
     const int by_waves = (NT / 64) * (64 / WavePlan<P>::G) / 3;
     const int by_slots = S / 2 > 0 ? S / 2 : 1;
     int j = by_threads < by_waves ? by_threads : by_waves;
@@ -93,40 +98,46 @@ struct Engine {
     return j > 0 ? j : 1;
   }
 
-  // The (slice, mode) items a thread owns in a job over J slices: for J = 1,
-  // modes threadIdx.x + j NT (j < MPT); for J > 1 (J <= jmax), mode
-  // threadIdx.x mod KP of slice threadIdx.x / KP.  Threads past the last
-  // slice own nothing (their slice index reads as 0, an address in range).
-  struct Own {
-    int s, base;
-    bool in;
-    __device__ __forceinline__ explicit Own(int J) {
-      if (J > 1) {
-        const int q = int(threadIdx.x) / KP;
-        in = q < J;
-        s = in ? q : 0;
-        base = int(threadIdx.x) - q * KP;
-      } else {
-        s = 0;
-        base = threadIdx.x;
-        in = true;
+  // Items a thread needs for a job over J slices.
+  static constexpr int items(int J) { return (J * KP + NT - 1) / NT; }
+
+  // The (slice, mode) items a thread owns in a job over J slices: item j is
+  // i = threadIdx.x + j NT, mode i mod KP of slice i / KP, valid while the
+  // slice is below J (for J = 1: the modes threadIdx.x + j NT below KP; for
+  // one item per thread: mode threadIdx.x mod KP of slice threadIdx.x / KP).
+  // An invalid item reads as slice 0, mode 0 (addresses in range).
+  template <int NI>
+  struct OwnT {
+    int s[NI], m[NI];
+    bool v[NI];
+    __device__ __forceinline__ explicit OwnT(int J) {
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int i = int(threadIdx.x) + j * NT;
+        const int q = i / KP;
+        v[j] = q < J;
+        s[j] = v[j] ? q : 0;
+        m[j] = v[j] ? i - q * KP : 0;
       }
     }
-    __device__ __forceinline__ int mode(int j) const { return base + j * NT; }
-    __device__ __forceinline__ bool valid(int j) const { return in && base + j * NT < KP; }
+    __device__ __forceinline__ int slice(int j) const { return s[j]; }
+    __device__ __forceinline__ int mode(int j) const { return m[j]; }
+    __device__ __forceinline__ bool valid(int j) const { return v[j]; }
   };
+  using Own = OwnT<MPT>;
 
   // N of the owned items' modal states x -> n for J slices, using slots
   // slot .. slot + J - 1 (callers alternate between slots 0 and S/2, which
   // J <= S/2 keeps apart, so consecutive evaluations need no barrier between
   // them; with S = 1 every evaluation uses slot 0 and ends with a barrier).
-  __device__ __forceinline__ void neval(int slot, int J, const Own& ow, const cx<T> (&x)[MPT][3],
-                                        cx<T> (&n)[MPT][3], const Basis<T> (&bs)[MPT]) {
+  template <int NI>
+  __device__ __forceinline__ void neval(int slot, int J, const OwnT<NI>& ow, const cx<T> (&x)[NI][3],
+                                        cx<T> (&n)[NI][3], const Basis<T> (&bs)[NI]) {
     cx<T>* sps = sp + slot * SL::sp_elems;
     cx<T>* ibs = ib + slot * SL::ib_elems;
 #pragma unroll
-    for (int j = 0; j < MPT; ++j)
-      if (ow.valid(j)) put_fields<T, NX>(sps, ow.s, ow.mode(j), x[j], bs[j]);
+    for (int j = 0; j < NI; ++j)
+      if (ow.valid(j)) put_fields<T, NX>(sps, ow.slice(j), ow.mode(j), x[j], bs[j]);
     zero_tails<T, NX, NT>(sps, J);
     __syncthreads();
     inverse_fields<T, NX, NT, jmax(), PLAN>(sps, ibs, J, tw);
@@ -134,8 +145,8 @@ struct Engine {
     forward_products<T, NX, NT, jmax(), PLAN>(sps, ibs, J, tw);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < MPT; ++j)
-      if (ow.valid(j)) get_N_sp<T, NX>(sps + ow.s * SL::sp_elems, ow.mode(j), bs[j], tw, n[j]);
+    for (int j = 0; j < NI; ++j)
+      if (ow.valid(j)) get_N_sp<T, NX>(sps + ow.slice(j) * SL::sp_elems, ow.mode(j), bs[j], tw, n[j]);
     if (S < 2 * J) __syncthreads();
   }
   // one slice (slot, thread-owned modes as mode(j))
@@ -146,9 +157,9 @@ struct Engine {
   // Evaluation H (0 or 1) of an alternating pair: slot 0 or S/2, known when
   // compiling, so that the LDS addresses of the transforms are the same
   // per-lane offsets in every evaluation plus a constant.
-  template <int H>
-  __device__ __forceinline__ void neval_half(int J, const Own& ow, const cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3],
-                                             const Basis<T> (&bs)[MPT]) {
+  template <int H, int NI>
+  __device__ __forceinline__ void neval_half(int J, const OwnT<NI>& ow, const cx<T> (&x)[NI][3], cx<T> (&n)[NI][3],
+                                             const Basis<T> (&bs)[NI]) {
     constexpr int slot = H == 0 ? 0 : S / 2;
     neval(slot, J, ow, x, n, bs);
   }
@@ -235,25 +246,28 @@ __device__ __forceinline__ cx<T> rot_out(cx<T> c, cx<T> e, int alpha_idx) {
 // state would drop those increments coherently step after step.  With
 // T = float the stage states a, b, c, the nonlinear evaluations and the
 // products f*N run in FP32.
-template <typename T, int NX, int NT, int S, int JM = 0, int PLAN = 0>
-__device__ __forceinline__ void fine_job(Engine<T, NX, NT, S, PLAN>& en, int Jrun, const cx<double>* __restrict__ src0,
-                                         const cx<double>* __restrict__ src1, cx<double>* __restrict__ dst,
-                                         int steps, const cx<double>* __restrict__ coef64,
-                                         const cx<T>* __restrict__ coef, const Basis<T>* __restrict__ basis) {
-  using E_ = Engine<T, NX, NT, S, PLAN>;
+template <typename T, int NX, int NT, int S, int JM = 0, int PLAN = 0, int IMAX = 1>
+__device__ __forceinline__ void fine_job(Engine<T, NX, NT, S, PLAN, IMAX>& en, int Jrun,
+                                         const cx<double>* __restrict__ src0, const cx<double>* __restrict__ src1,
+                                         cx<double>* __restrict__ dst, int steps,
+                                         const cx<double>* __restrict__ coef64, const cx<T>* __restrict__ coef,
+                                         const Basis<T>* __restrict__ basis) {
+  using E_ = Engine<T, NX, NT, S, PLAN, IMAX>;
   constexpr int KP = E_::KP;
-  constexpr int MPT = E_::MPT;
+  // items per thread: the modes of one slice (JM = 1), else as many as the
+  // largest job of this engine needs
+  constexpr int MPT = JM == 1 ? E_::MPT : (E_::items(E_::jmax()) > E_::MPT ? E_::items(E_::jmax()) : E_::MPT);
   const int J = JM == 1 ? 1 : Jrun;   // JM = 1: a single slice, known when compiling
-  const typename E_::Own ow(J);
+  const typename E_::template OwnT<MPT> ow(J);
   // slice s reads src0 (s = 0) or src1 + (s - 1) * 3 KP and writes dst + s * 3 KP
-  const cx<double>* src = ow.s == 0 ? src0 : src1 + size_t(ow.s - 1) * 3 * KP;
-  cx<double>* out = dst + size_t(ow.s) * 3 * KP;
+  auto src_of = [&](int sl) { return sl == 0 ? src0 : src1 + size_t(sl - 1) * 3 * KP; };
   cx<double> c[MPT][3], cE[MPT][3];
   cx<T> cE2[MPT][3], cQ[MPT][3], cf1[MPT][3], cf2[MPT][3], cf3[MPT][3];
   Basis<T> bs[MPT];
 #pragma unroll
   for (int j = 0; j < MPT; ++j) {
     const int k = ow.valid(j) ? ow.mode(j) : KP - 1;
+    const cx<double>* src = src_of(ow.slice(j));
     bs[j] = basis[k];
 #pragma unroll
     for (int al = 0; al < 3; ++al) {
@@ -309,8 +323,10 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S, PLAN>& en, int Jru
   }
 #pragma unroll
   for (int j = 0; j < MPT; ++j)
-    if (ow.valid(j))
+    if (ow.valid(j)) {
+      cx<double>* out = dst + size_t(ow.slice(j)) * 3 * KP;
       for (int al = 0; al < 3; ++al) out[al * KP + ow.mode(j)] = c[j][al];
+    }
 }
 
 // --------------------------------------------------------- Strang steps ---
@@ -388,13 +404,13 @@ __device__ __forceinline__ void strang_job(Engine<T, NX, NT, S>& en, int Jrun, c
   constexpr int KP = E_::KP;
   const int J = JM == 1 ? 1 : Jrun;   // JM = 1: a single slice, known when compiling
   const typename E_::Own ow(J);
-  const cx<double>* src = ow.s == 0 ? src0 : src1 + size_t(ow.s - 1) * 3 * KP;
-  cx<double>* out = dst + size_t(ow.s) * 3 * KP;
   cx<double> c[MPT][3], cE2[MPT][3];
   Basis<T> bs[MPT];
 #pragma unroll
   for (int j = 0; j < MPT; ++j) {
     const int k = ow.valid(j) ? ow.mode(j) : KP - 1;
+    const int sl = ow.slice(j);
+    const cx<double>* src = sl == 0 ? src0 : src1 + size_t(sl - 1) * 3 * KP;
     bs[j] = basis[k];
     for (int al = 0; al < 3; ++al) c[j][al] = src[al * KP + k];
   }
@@ -402,8 +418,10 @@ __device__ __forceinline__ void strang_job(Engine<T, NX, NT, S>& en, int Jrun, c
   strang_regs<T, NX, NT, S>(en, J, ow, c, steps, cE2, h, bs);
 #pragma unroll
   for (int j = 0; j < MPT; ++j)
-    if (ow.valid(j))
+    if (ow.valid(j)) {
+      cx<double>* out = dst + size_t(ow.slice(j)) * 3 * KP;
       for (int al = 0; al < 3; ++al) out[al * KP + ow.mode(j)] = c[j][al];
+    }
 }
 
 // ----------------------------------------------------------- time average ---

@@ -1070,7 +1070,7 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
   long long slices_total = 0;
   for (auto& it : items) slices_total += it.q.Ns;
   for (size_t i = 0; i < items.size(); ++i) {
-    const int jm = ap::pipeline_fine_slices(items[i].q.nx, f64);
+    const int jm = ap::pipeline_fine_slices(items[i].q.nx, f64, items[i].q.fine_kind);
     const int want = items[i].c->opt_fine_group;
     items[i].q.fg = want > 0 ? std::min(want, jm) : (slices_total > grid ? jm : 1);
     shapes[i].fg = items[i].q.fg;
@@ -1854,7 +1854,7 @@ int query_shape(int N, const ap_solve_params* p, int split, int group, int fine_
   q->split = split < 0 ? q->groups >= 2 : split != 0;
   q->skip = true;
   q->tol = p->tol > 0.0 ? p->tol : 0.0;
-  q->fg = std::min(fine_group, ap::pipeline_fine_slices(N, q->fp64));
+  q->fg = std::min(fine_group, ap::pipeline_fine_slices(N, q->fp64, q->fine_kind));
   if (cost) {
     for (int i = 0; i < 4; ++i)
       if (!(cost[i] >= 0.0) || !(cost[i] < 1e9)) return fail(AP_EINVAL, "bad job duration");

@@ -405,19 +405,18 @@ static bool pipe_kernel(int nx, int nx_max, bool fp64, PipeLaunchFn* fn, PipeOcc
 }
 
 template <typename T>
-static int pipeline_fine_slices_t(int nx) {
-  constexpr int NT = kPipeThreads;
+static int pipeline_fine_slices_t(int nx, int kind) {
   switch (nx) {
-    case 64: return Engine<T, 64, NT, pipe_slots<T, 64>()>::jmax();
-    case 128: return Engine<T, 128, NT, pipe_slots<T, 128>()>::jmax();
-    case 256: return Engine<T, 256, NT, pipe_slots<T, 256>()>::jmax();
-    case 512: return Engine<T, 512, NT, pipe_slots<T, 512>()>::jmax();
-    case 1024: return Engine<T, 1024, NT, pipe_slots<T, 1024>()>::jmax();
-    default: return Engine<T, 2048, NT, pipe_slots<T, 2048>()>::jmax();
+    case 64: return pipe_fine_slices<T, 64>(kind);
+    case 128: return pipe_fine_slices<T, 128>(kind);
+    case 256: return pipe_fine_slices<T, 256>(kind);
+    case 512: return pipe_fine_slices<T, 512>(kind);
+    case 1024: return pipe_fine_slices<T, 1024>(kind);
+    default: return pipe_fine_slices<T, 2048>(kind);
   }
 }
-int pipeline_fine_slices(int nx, bool fp64) {
-  return fp64 ? pipeline_fine_slices_t<double>(nx) : pipeline_fine_slices_t<float>(nx);
+int pipeline_fine_slices(int nx, bool fp64, int kind) {
+  return fp64 ? pipeline_fine_slices_t<double>(nx, kind) : pipeline_fine_slices_t<float>(nx, kind);
 }
 
 int pipeline_max_grid(int nx, int nx_max, bool fp64) {

@@ -137,8 +137,9 @@ hipError_t launch_pipeline(int nx, int nx_max, bool fp64, const void* jobs, int 
 size_t pipeline_lds(int nx, int nx_max, bool fp64);
 // Pipeline workgroups resident on the current device at once (0 on error).
 int pipeline_max_grid(int nx, int nx_max, bool fp64);
-// Most slices one fine job of the pipelined solve steps together at grid size nx.
-int pipeline_fine_slices(int nx, bool fp64);
+// Most slices one fine job of the pipelined solve steps together at grid size
+// nx, for fine propagator `kind` (0 ETDRK4, 1 Strang).
+int pipeline_fine_slices(int nx, bool fp64, int kind);
 // Per-translation-unit pipeline kernels (pipe_*.hip): launch with `lds`
 // bytes of LDS, and workgroups resident at once.
 #define AP_PIPE_TU(tag)                                                                                  \

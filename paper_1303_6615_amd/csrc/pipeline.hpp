@@ -163,6 +163,17 @@ template <typename T, int NX>
 constexpr size_t pipe_lds() {
   return Engine<T, NX, kPipeThreads, pipe_slots<T, NX>()>::lds_bytes();
 }
+// (slice, mode) items per thread in the pipeline's ETDRK4 fine jobs: two, so
+// that a job at N = 1024 (342 modes per slice, 512 threads) steps two slices,
+// six transforms per round instead of three; the Strang fine job keeps one.
+constexpr int kPipeFineItems = 2;
+template <typename T, int NX>
+using PipeFineEngine = Engine<T, NX, kPipeThreads, pipe_slots<T, NX>(), 0, kPipeFineItems>;
+// Most slices per fine job of the pipeline: ETDRK4 (kind 0) or Strang (kind 1).
+template <typename T, int NX>
+constexpr int pipe_fine_slices(int kind) {
+  return kind == 1 ? Engine<T, NX, kPipeThreads, pipe_slots<T, NX>()>::jmax() : PipeFineEngine<T, NX>::jmax();
+}
 
 // Counts a group job of a split step in on counter *ctr (groups jobs count
 // in): every wavefront first waits for its stores to reach the L2 (a
@@ -194,12 +205,13 @@ __device__ __attribute__((noinline)) void fine_slices_job(unsigned char* smem, c
                                                           const cx<double>* src0, const cx<double>* src1,
                                                           cx<double>* dst, int steps, const cx<double>* coef64,
                                                           const cx<T>* coef, double hf, const Basis<T>* basis) {
-  using E_ = Engine<T, NX, kPipeThreads, pipe_slots<T, NX>()>;
-  E_ en(smem, tw, false);
-  if (kind == 1)
+  if (kind == 1) {
+    Engine<T, NX, kPipeThreads, pipe_slots<T, NX>()> en(smem, tw, false);
     strang_job<T, NX, kPipeThreads, pipe_slots<T, NX>(), JM>(en, J, src0, src1, dst, steps, coef64, hf, basis);
-  else
+  } else {
+    PipeFineEngine<T, NX> en(smem, tw, false);
     fine_job<T, NX, kPipeThreads, pipe_slots<T, NX>(), JM>(en, J, src0, src1, dst, steps, coef64, coef, basis);
+  }
 }
 
 // Runs job jb of problem p (grid size NX) in this workgroup.  Returns the
@@ -215,7 +227,7 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
   const PipeIdx ix{p.Ns, p.K};
   const int Ns = p.Ns, k = jb.k, n = jb.n;
   // a fine job steps J consecutive slices together and publishes their J counters
-  const int J = jb.type == kJobFine && jb.g > 1 ? min(jb.g, E_::jmax()) : 1;
+  const int J = jb.type == kJobFine && jb.g > 1 ? min(jb.g, pipe_fine_slices<T, NX>(p.fine_kind)) : 1;
   npub = J;
   if (skip) {
     // past the stopped level: publish only (group jobs still count in so
