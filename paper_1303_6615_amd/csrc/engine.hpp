@@ -90,7 +90,10 @@ struct Engine {
   static constexpr int jmax() {
     if (MPT > 1 && IPT <= MPT) return 1;
     const int by_threads = IPT * NT / KP;
-    const int by_waves = (NT / 64) * (64 / WavePlan<P>::G) / 3;
+    // signals per round of transforms; with several items per thread, two
+    // rounds where one would leave more than a fifth of the lane groups idle
+    const int per_round = (NT / 64) * (64 / WavePlan<P>::G);
+    const int by_waves = IPT > MPT && 5 * 3 * (per_round / 3) < 4 * per_round ? 2 * per_round / 3 : per_round / 3;
     const int by_slots = S / 2 > 0 ? S / 2 : 1;
     int j = by_threads < by_waves ? by_threads : by_waves;
     j = j < by_slots ? j : by_slots;

@@ -75,8 +75,9 @@ def _deps(job, K, groups, split, fine_of):
 
 
 # most slices per ETDRK4 fine job by grid size (FP32 pipeline workgroups of 512
-# threads; two (slice, mode) items per thread, so N = 1024 steps two slices)
-_FINE_MAX = {64: 16, 128: 10, 256: 5, 512: 2, 1024: 2, 2048: 1}
+# threads; two (slice, mode) items per thread: N = 1024 steps two slices, N = 512
+# five in two rounds of transforms)
+_FINE_MAX = {64: 16, 128: 10, 256: 5, 512: 5, 1024: 2, 2048: 1}
 
 
 @pytest.mark.parametrize("N,T,Ns,K,dt,M,split,group,fg", [
