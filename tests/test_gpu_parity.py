@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from paper_1303_6615_amd.inputs import C1, C2, seeded_state, NU_BY_NX
+from paper_1303_6615_amd.inputs import C1, C2, SolveConfig, seeded_state, NU_BY_NX
 
 pytestmark = pytest.mark.gpu
 
@@ -116,10 +116,19 @@ def test_fine_batch_slices_stepped_together_equal_alone(torch_cuda, n, prec, str
     assert torch.equal(together, alone)
 
 
-@pytest.mark.parametrize("cfg,prec,fine_kind", [(C1, FP64, 0), (C2, FP32, 0), (C2, FP32, 1)])
+_G512 = SolveConfig("grouped-n512", nx=512, eps=0.01, nu=NU_BY_NX[512], T=0.2, slices=14, K=3, dt=0.01 / 20,
+                    Mbar=16, k_ic=64, seed=31)
+_G1024 = SolveConfig("grouped-n1024", nx=1024, eps=0.01, nu=NU_BY_NX[1024], T=0.1, slices=9, K=3, dt=0.01 / 20,
+                     Mbar=16, k_ic=128, seed=32)
+
+
+@pytest.mark.parametrize("cfg,prec,fine_kind", [(C1, FP64, 0), (C2, FP32, 0), (C2, FP32, 1), (_G512, FP32, 0),
+                                                (_G1024, FP32, 0), (_G1024, FP32, 1), (_G512, FP64, 0)])
 def test_grouped_fine_jobs_change_no_value(torch_cuda, cfg, prec, fine_kind):
     # fine jobs of the pipelined solve over up to 16 / 5 consecutive slices
-    # (AP_OPT_FINE_GROUP) give the single-slice results bitwise
+    # (AP_OPT_FINE_GROUP) give the single-slice results bitwise; at N = 512
+    # and 1024 the FP32 ETDRK4 jobs hold two (slice, mode) items per thread
+    # (5 slices in two rounds of transforms, 2 slices)
     from paper_1303_6615_amd.binding import AP_OPT_FINE, AP_OPT_FINE_GROUP
     torch = torch_cuda
     with _ctx(cfg.nx, cfg.eps, cfg.nu) as ctx:
