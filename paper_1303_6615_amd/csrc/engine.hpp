@@ -755,18 +755,23 @@ __device__ __forceinline__ void store_owned(cx<T>* __restrict__ dst,
 // Stage job of group g: stage 1 stores S_g(Nbar(w)) at Pout; stage 2 loads
 // the step's midpoint state y from Y and stores S_g(Nbar(y)) at Pout.  On
 // return, w holds the step's w (for the midpoint and the finishing job).
-template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void stage_job(Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct,
+// Stage 2 calls wait_y() (every thread; true when y is published) after
+// forming w from uprev, so that loading uprev and the first half step overlap
+// the wait for the midpoint; it returns false (and does nothing more) when
+// wait_y() does.
+template <typename T, int NX, int NT, int S, typename WaitY>
+__device__ __forceinline__ bool stage_job(Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct,
                                           const Basis<T>* __restrict__ basis, const cx<double>* uprev, int stage,
                                           int g, const cx<T>* Y, cx<T>* Pout,
                                           cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3],
-                                          CoarseRegs<T, Engine<T, NX, NT, S>::MPT>& cr) {
+                                          CoarseRegs<T, Engine<T, NX, NT, S>::MPT>& cr, WaitY&& wait_y) {
   using E_ = Engine<T, NX, NT, S>;
   constexpr int MPT = E_::MPT;
   cx<T> u[MPT][3], y[MPT][3], acc[MPT][3];
   load_owned<T, NX, NT, S>(uprev, u);
   coarse_begin<T, NX, NT, S>(ct, u, w, cr);
   if (stage == 2) {
+    if (!wait_y()) return false;
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
       for (int al = 0; al < 3; ++al) y[j][al] = E_::valid(j) ? Y[al * E_::KP + E_::mode(j)] : czero<T>();
@@ -779,6 +784,7 @@ __device__ __forceinline__ void stage_job(Engine<T, NX, NT, S>& en, const Coarse
   const int me = min(ct.avg.M, mb + ct.avg.gs);
   nbar_range<T, NX, NT, S>(en, y, acc, mb, me, false, ct.avg, basis);
   store_owned<T, NX, NT, S>(Pout, acc);
+  return true;
 }
 
 // The midpoint state of a split step, formed by its last stage-1 job: the sum

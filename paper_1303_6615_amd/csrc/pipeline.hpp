@@ -17,8 +17,9 @@ namespace ap {
 // Split C(k,n): stage-1 job of group g needs C(k,n-1); the stage-1 job that
 //         finishes last forms the step's midpoint state and publishes the
 //         stage-1 counter once more (groups + 1); stage-2 job of group g needs
-//         that; the stage-2 job that finishes last also needs F(k-1,n) and
-//         C(k-1,n) and publishes C(k,n).
+//         C(k,n-1) to start and that count before it reads the midpoint; the
+//         stage-2 job that finishes last also needs F(k-1,n) and C(k-1,n) and
+//         publishes C(k,n).
 // Stall record `diag` of a launch: [0] stalled, [1] job, [2] counter index,
 // [3] jobs completed so far (every workgroup adds 1 per job it publishes).
 // A wait ends in a stall only when no job of the launch completes for
@@ -134,7 +135,8 @@ template <typename T>
 __device__ __forceinline__ bool wait_deps(const PipeJob& jb, const PipeProb<T>& p, int* diag, int jt) {
   const PipeIdx ix{p.Ns, p.K};
   const int k = jb.k, n = jb.n;
-  if (jb.type == kJobStage2) return wait_count(&p.cnt[ix.stage1(k, n)], p.groups + 1, diag, jt, ix.stage1(k, n));
+  // a stage-2 job starts on U(k, n-1) and waits for the midpoint inside (run_job)
+  if (jb.type == kJobStage2) return n == 1 || wait_count(&p.cnt[ix.coarse(k, n - 1)], 1, diag, jt, ix.coarse(k, n - 1));
   if (jb.type == kJobCopy) {
     if (n == k && !wait_count(&p.cnt[ix.fine(k - 1, n)], 1, diag, jt, ix.fine(k - 1, n))) return false;
     if (!wait_count(&p.cnt[ix.coarse(k - 1, n)], 1, diag, jt, ix.coarse(k - 1, n))) return false;
@@ -308,13 +310,22 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
   cx<T> w[MPT][3];
   CoarseRegs<T, MPT> cr;
   if (jb.type == kJobStage1) {
-    stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 1, jb.g, nullptr, p.P1 + lvl1 + jb.g * st, w, cr);
+    stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 1, jb.g, nullptr, p.P1 + lvl1 + jb.g * st, w, cr,
+                            [] { return true; });
     // the last group to arrive forms y for the stage-2 jobs and publishes
     if (!count_in_last(&p.cnt[ix.stage1(k, n)], p.groups, s_flag)) return -1;
     stage_mid<T, NX, NT, S>(p.ct, p.P1 + lvl1, p.groups, w, Y);
     return ix.stage1(k, n);
   }
-  stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 2, jb.g, Y, p.P2 + lvl + jb.g * st, w, cr);
+  // wait for the midpoint (every stage-1 group and y): thread 0 for the
+  // workgroup, after the job has formed w from uprev
+  auto wait_y = [&] {
+    if (threadIdx.x == 0) *s_flag = wait_count(&p.cnt[ix.stage1(k, n)], p.groups + 1, diag, jt, ix.stage1(k, n));
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*s_flag) != 0;
+  };
+  if (!stage_job<T, NX, NT, S>(en, p.ct, p.basis, uprev, 2, jb.g, Y, p.P2 + lvl + jb.g * st, w, cr, wait_y))
+    return -1;
   // Count this group in; the last group to arrive finishes the step.  Every
   // wavefront first waits for its stores of the group sum to reach the L2
   // (a workgroup barrier waits only for LDS); thread 0's release then writes

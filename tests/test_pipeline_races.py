@@ -19,8 +19,8 @@ Modelled per job (type, k, n, g) of one problem (Ns slices, K iterations):
       then counts in
   midpoint of a split C(k,n) (the last stage-1 job to count in): after every
       stage-1 job, reads every P1(k,.); writes Y(k)
-  stage 2 of C(k,n), group g: waits the midpoint; reads U(k,n-1) and Y(k);
-      writes P2(k,g), then counts in
+  stage 2 of C(k,n), group g: waits C(k,n-1); reads U(k,n-1); then waits the
+      midpoint and reads Y(k); writes P2(k,g), then counts in
   finish of a split C(k,n) (the last stage-2 job to count in): after every
       stage-2 job, waits F(k-1,n), C(k-1,n); reads every P2(k,.), G(k-1,n),
       F(k-1,n), U(k-1,n); writes U(k,n), G(k,n), part(k-1,n)
@@ -167,9 +167,14 @@ def build_graph(jobs, Ns, K, tol, plant_missing_copy_wait=False):
             g.access(e, j, ("P1", k, gg), True)
             g.edge(e, mid[(k, n)])
         elif t == STAGE2:
-            g.edge(mid[(k, n)], s)
+            if n > 1:
+                g.edge(comp[(k, n - 1)], s)
             g.access(s, j, U(k, n - 1), False)
-            g.access(s, j, ("Y", k), False)
+            after_mid = g.node()
+            g.edge(s, after_mid)
+            g.edge(mid[(k, n)], after_mid)
+            g.edge(after_mid, e)
+            g.access(after_mid, j, ("Y", k), False)
             g.access(e, j, ("P2", k, gg), True)
             g.edge(e, fin[(k, n)])
         elif t == FINE:
