@@ -167,62 +167,54 @@ struct Engine {
     neval(slot, J, ow, x, n, bs);
   }
 
-  // Largest power of two not above NT: a tree reduction first folds the
-  // threads from there on into the first ones (nothing to fold when NT is a
-  // power of two).
-  static constexpr int kFold = 1 << ilog2(NT);
+  // Block reductions: a butterfly over the 64 lanes of each wavefront
+  // (cross-lane shuffles, no barrier), then the NT / 64 wavefront results
+  // combined in wavefront order by every thread, so that every thread returns
+  // the same value.  The scratch lives in `ib`: the first barrier waits for
+  // its last readers, the last one for this reduction's readers.
+  static constexpr int kWaves = NT / 64;
 
-  // FP64 block maximum of x over the workgroup (NaN wins); result valid in
-  // every thread.  The scratch lives in `ib`, so wait for its last readers first.
+  // FP64 block maximum of x over the workgroup (NaN wins).
   __device__ __forceinline__ double block_max(double x) {
-    static_assert(S * SL::ib_elems * sizeof(cx<T>) >= NT * sizeof(double), "reduction scratch");
-    __syncthreads();
-    red[threadIdx.x] = x;
-    __syncthreads();
-    if constexpr (kFold < NT) {
-      if (threadIdx.x < NT - kFold) {
-        const double o = red[threadIdx.x + kFold];
-        if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
-      }
-      __syncthreads();
+    static_assert(S * SL::ib_elems * sizeof(cx<T>) >= kWaves * sizeof(double), "reduction scratch");
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(x, off);
+      if (o > x || o != o) x = o;
     }
-    for (int off = kFold / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) {
-        const double o = red[threadIdx.x + off];
-        if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
-      }
-      __syncthreads();
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double r = red[0];
+    for (int w = 1; w < kWaves; ++w) {
+      const double o = red[w];
+      if (o > r || o != o) r = o;
     }
-    const double r = red[0];
     __syncthreads();
     return r;
   }
 
-  // FP64 block sum of (x, y) over the workgroup; result valid in every thread.
-  // The scratch lives in `ib`, so wait for its last readers first.
+  // FP64 block sum of (x, y) over the workgroup.
   __device__ __forceinline__ double2 block_sum2(double x, double yv) {
-    static_assert(S * SL::ib_elems * sizeof(cx<T>) >= 2 * NT * sizeof(double), "reduction scratch");
-    __syncthreads();
-    red[threadIdx.x] = x;
-    red[NT + threadIdx.x] = yv;
-    __syncthreads();
-    if constexpr (kFold < NT) {
-      if (threadIdx.x < NT - kFold) {
-        red[threadIdx.x] += red[threadIdx.x + kFold];
-        red[NT + threadIdx.x] += red[NT + threadIdx.x + kFold];
-      }
-      __syncthreads();
+    static_assert(S * SL::ib_elems * sizeof(cx<T>) >= 2 * kWaves * sizeof(double), "reduction scratch");
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      x += __shfl_xor(x, off);
+      yv += __shfl_xor(yv, off);
     }
-    for (int off = kFold / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) {
-        red[threadIdx.x] += red[threadIdx.x + off];
-        red[NT + threadIdx.x] += red[NT + threadIdx.x + off];
-      }
-      __syncthreads();
-    }
-    const double2 r = make_double2(red[0], red[NT]);
     __syncthreads();
-    return r;
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6] = x;
+      red[kWaves + (threadIdx.x >> 6)] = yv;
+    }
+    __syncthreads();
+    double sx = red[0], sy = red[kWaves];
+    for (int w = 1; w < kWaves; ++w) {
+      sx += red[w];
+      sy += red[kWaves + w];
+    }
+    __syncthreads();
+    return make_double2(sx, sy);
   }
 };
 
