@@ -60,13 +60,27 @@ struct Engine {
   cx<T>* y;
   double* red;
 
+  unsigned tid;   // this thread's index in the workgroup
+
   // stage == false: the twiddles of this grid size are already in LDS (the
   // previous job of this workgroup staged them and nothing overwrote them).
-  __device__ __forceinline__ Engine(unsigned char* smem, const cx<T>* __restrict__ tw_global, bool stage = true) {
+  __device__ __forceinline__ Engine(unsigned char* smem, const cx<T>* tw_global, bool stage = true)
+      : Engine(smem, tw_global, stage, threadIdx.x, ThreadIndex{}) {}
+  // For persistent kernels: the thread index salted with the number of the
+  // job (salted_thread), so that nothing a job derives from it is hoisted out
+  // of the job loop.
+  __device__ __forceinline__ Engine(unsigned char* smem, const cx<T>* tw_global, bool stage, int salt)
+      : Engine(smem, tw_global, stage, salted_thread<NT>(salt), ThreadIndex{}) {}
+
+ private:
+  struct ThreadIndex {};
+  __device__ __forceinline__ Engine(unsigned char* smem, const cx<T>* __restrict__ tw_global, bool stage, unsigned t,
+                                    ThreadIndex)
+      : tid(t) {
     cx<T>* base = reinterpret_cast<cx<T>*>(smem);
     if constexpr (TW_LDS) {
       if (stage) {
-        for (int i = threadIdx.x; i < TWN; i += NT) base[i] = tw_global[i];
+        for (int i = tid; i < TWN; i += NT) base[i] = tw_global[i];
         __syncthreads();
       }
       tw = base;
@@ -80,8 +94,9 @@ struct Engine {
     red = reinterpret_cast<double*>(ib);
   }
 
-  static __device__ __forceinline__ int mode(int j) { return threadIdx.x + j * NT; }
-  static __device__ __forceinline__ bool valid(int j) { return mode(j) < KP; }
+ public:
+  __device__ __forceinline__ int mode(int j) const { return tid + j * NT; }
+  __device__ __forceinline__ bool valid(int j) const { return mode(j) < KP; }
 
   // Most slices one job can step together: IPT items per thread (one mode
   // per thread unless IMAX says more), one round of transforms over the
@@ -105,18 +120,18 @@ struct Engine {
   static constexpr int items(int J) { return (J * KP + NT - 1) / NT; }
 
   // The (slice, mode) items a thread owns in a job over J slices: item j is
-  // i = threadIdx.x + j NT, mode i mod KP of slice i / KP, valid while the
-  // slice is below J (for J = 1: the modes threadIdx.x + j NT below KP; for
-  // one item per thread: mode threadIdx.x mod KP of slice threadIdx.x / KP).
+  // i = tid + j NT, mode i mod KP of slice i / KP, valid while the slice is
+  // below J (for J = 1: the modes tid + j NT below KP; for one item per
+  // thread: mode tid mod KP of slice tid / KP), tid the engine's thread index.
   // An invalid item reads as slice 0, mode 0 (addresses in range).
   template <int NI>
   struct OwnT {
     int s[NI], m[NI];
     bool v[NI];
-    __device__ __forceinline__ explicit OwnT(int J) {
+    __device__ __forceinline__ OwnT(unsigned tid, int J) {
 #pragma unroll
       for (int j = 0; j < NI; ++j) {
-        const int i = int(threadIdx.x) + j * NT;
+        const int i = int(tid) + j * NT;
         const int q = i / KP;
         v[j] = q < J;
         s[j] = v[j] ? q : 0;
@@ -141,11 +156,11 @@ struct Engine {
 #pragma unroll
     for (int j = 0; j < NI; ++j)
       if (ow.valid(j)) put_fields<T, NX>(sps, ow.slice(j), ow.mode(j), x[j], bs[j]);
-    zero_tails<T, NX, NT>(sps, J);
+    zero_tails<T, NX, NT>(sps, J, tid);
     __syncthreads();
-    inverse_fields<T, NX, NT, jmax(), PLAN>(sps, ibs, J, tw);
+    inverse_fields<T, NX, NT, jmax(), PLAN>(sps, ibs, J, tw, tid);
     __syncthreads();
-    forward_products<T, NX, NT, jmax(), PLAN>(sps, ibs, J, tw);
+    forward_products<T, NX, NT, jmax(), PLAN>(sps, ibs, J, tw, tid);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NI; ++j)
@@ -155,7 +170,7 @@ struct Engine {
   // one slice (slot, thread-owned modes as mode(j))
   __device__ __forceinline__ void neval(int slot, const cx<T> (&x)[MPT][3], cx<T> (&n)[MPT][3],
                                         const Basis<T> (&bs)[MPT]) {
-    neval(slot, 1, Own(1), x, n, bs);
+    neval(slot, 1, Own(tid, 1), x, n, bs);
   }
   // Evaluation H (0 or 1) of an alternating pair: slot 0 or S/2, known when
   // compiling, so that the LDS addresses of the transforms are the same
@@ -183,7 +198,7 @@ struct Engine {
       if (o > x || o != o) x = o;
     }
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    if ((tid & 63) == 0) red[tid >> 6] = x;
     __syncthreads();
     double r = red[0];
     for (int w = 1; w < kWaves; ++w) {
@@ -203,9 +218,9 @@ struct Engine {
       yv += __shfl_xor(yv, off);
     }
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-      red[threadIdx.x >> 6] = x;
-      red[kWaves + (threadIdx.x >> 6)] = yv;
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = x;
+      red[kWaves + (tid >> 6)] = yv;
     }
     __syncthreads();
     double sx = red[0], sy = red[kWaves];
@@ -253,7 +268,7 @@ __device__ __forceinline__ void fine_job(Engine<T, NX, NT, S, PLAN, IMAX>& en, i
   // largest job of this engine needs
   constexpr int MPT = JM == 1 ? E_::MPT : (E_::items(E_::jmax()) > E_::MPT ? E_::items(E_::jmax()) : E_::MPT);
   const int J = JM == 1 ? 1 : Jrun;   // JM = 1: a single slice, known when compiling
-  const typename E_::template OwnT<MPT> ow(J);
+  const typename E_::template OwnT<MPT> ow(en.tid, J);
   // slice s reads src0 (s = 0) or src1 + (s - 1) * 3 KP and writes dst + s * 3 KP
   auto src_of = [&](int sl) { return sl == 0 ? src0 : src1 + size_t(sl - 1) * 3 * KP; };
   cx<double> c[MPT][3], cE[MPT][3];
@@ -365,7 +380,7 @@ template <typename T, int NX, int NT, int S>
 __device__ __forceinline__ void strang_regs(Engine<T, NX, NT, S>& en, cx<double> (&c)[Engine<T, NX, NT, S>::MPT][3],
                                             int steps, const cx<double> (&cE2)[Engine<T, NX, NT, S>::MPT][3],
                                             double h, const Basis<T> (&bs)[Engine<T, NX, NT, S>::MPT]) {
-  strang_regs<T, NX, NT, S>(en, 1, typename Engine<T, NX, NT, S>::Own(1), c, steps, cE2, h, bs);
+  strang_regs<T, NX, NT, S>(en, 1, typename Engine<T, NX, NT, S>::Own(en.tid, 1), c, steps, cE2, h, bs);
 }
 
 // Owned items of the FP64 coefficient slot `slot` of a [8][3][KP] table.
@@ -381,9 +396,9 @@ __device__ __forceinline__ void load_coef64(const cx<double>* __restrict__ coef6
   }
 }
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void load_coef64(const cx<double>* __restrict__ coef64, int slot,
-                                            cx<double> (&out)[Engine<T, NX, NT, S>::MPT][3]) {
-  load_coef64<T, NX, NT, S>(coef64, slot, typename Engine<T, NX, NT, S>::Own(1), out);
+__device__ __forceinline__ void load_coef64(const Engine<T, NX, NT, S>& en, const cx<double>* __restrict__ coef64,
+                                            int slot, cx<double> (&out)[Engine<T, NX, NT, S>::MPT][3]) {
+  load_coef64<T, NX, NT, S>(coef64, slot, typename Engine<T, NX, NT, S>::Own(en.tid, 1), out);
 }
 
 // `steps` Strang steps of size h for J slices (as fine_job: slice s from src0
@@ -398,7 +413,7 @@ __device__ __forceinline__ void strang_job(Engine<T, NX, NT, S>& en, int Jrun, c
   constexpr int MPT = E_::MPT;
   constexpr int KP = E_::KP;
   const int J = JM == 1 ? 1 : Jrun;   // JM = 1: a single slice, known when compiling
-  const typename E_::Own ow(J);
+  const typename E_::Own ow(en.tid, J);
   cx<double> c[MPT][3], cE2[MPT][3];
   Basis<T> bs[MPT];
 #pragma unroll
@@ -447,26 +462,26 @@ __device__ __forceinline__ void nbar_range(Engine<T, NX, NT, S>& en,
       acc[j][al] = czero<T>();
       pg[j][al] = czero<T>();
     }
-    if (E_::valid(j))
-      for (int al = 0; al < 3; ++al) en.y[al * KP + E_::mode(j)] = yv[j][al];
+    if (en.valid(j))
+      for (int al = 0; al < 3; ++al) en.y[al * KP + en.mode(j)] = yv[j][al];
   }
   __syncthreads();
   for (int m0 = mb; m0 < me; m0 += S) {
     const int ns = min(S, me - m0);
-    for (int i = threadIdx.x; i < ns * KP; i += NT) {
+    for (int i = en.tid; i < ns * KP; i += NT) {
       const int s = i / KP, k = i - s * KP;
       const cx<T> e = av.rot[size_t(m0 + s) * KP + k];
       cx<T> x[3];
       for (int al = 0; al < 3; ++al) x[al] = rot_in(en.y[al * KP + k], e, al);
       put_fields<T, NX>(en.sp, s, k, x, basis[k]);
     }
-    zero_tails<T, NX, NT>(en.sp, ns);
+    zero_tails<T, NX, NT>(en.sp, ns, en.tid);
     __syncthreads();
-    inverse_fields<T, NX, NT>(en.sp, en.ib, ns, en.tw);
+    inverse_fields<T, NX, NT>(en.sp, en.ib, ns, en.tw, en.tid);
     __syncthreads();
-    forward_products<T, NX, NT>(en.sp, en.ib, ns, en.tw);
+    forward_products<T, NX, NT>(en.sp, en.ib, ns, en.tw, en.tid);
     __syncthreads();
-    for (int i = threadIdx.x; i < ns * KP; i += NT) {
+    for (int i = en.tid; i < ns * KP; i += NT) {
       const int s = i / KP, k = i - s * KP;
       const cx<T> e = av.rot[size_t(m0 + s) * KP + k];
       const T wm = av.w[m0 + s];
@@ -483,8 +498,8 @@ __device__ __forceinline__ void nbar_range(Engine<T, NX, NT, S>& en,
       const cx<T>* c = en.ib + s * SL::ib_elems;
 #pragma unroll
       for (int j = 0; j < MPT; ++j) {
-        if (!E_::valid(j)) continue;
-        const int k = E_::mode(j);
+        if (!en.valid(j)) continue;
+        const int k = en.mode(j);
         for (int al = 0; al < 3; ++al) {
           const cx<T> v = c[al * KP + k];
           pg[j][al] = first ? v : pg[j][al] + v;
@@ -517,13 +532,14 @@ struct CoarseRegs {
 };
 
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void coarse_begin(const CoarseTab<T>& ct, const cx<T> (&u)[Engine<T, NX, NT, S>::MPT][3],
+__device__ __forceinline__ void coarse_begin(const Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct,
+                                             const cx<T> (&u)[Engine<T, NX, NT, S>::MPT][3],
                                              cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3],
                                              CoarseRegs<T, Engine<T, NX, NT, S>::MPT>& cr) {
   using E_ = Engine<T, NX, NT, S>;
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : 0;
+    const int k = en.valid(j) ? en.mode(j) : 0;
     cr.hd[j] = ct.hd[k];
     cr.rT[j] = ct.rotT[k];
     for (int al = 0; al < 3; ++al) w[j][al] = cr.hd[j] * u[j][al];
@@ -560,7 +576,7 @@ __device__ __forceinline__ void coarse_owned(Engine<T, NX, NT, S>& en,
   constexpr int MPT = Engine<T, NX, NT, S>::MPT;
   cx<T> w[MPT][3], y[MPT][3], kk[MPT][3];
   CoarseRegs<T, MPT> cr;
-  coarse_begin<T, NX, NT, S>(ct, u, w, cr);
+  coarse_begin<T, NX, NT, S>(en, ct, u, w, cr);
   nbar_owned<T, NX, NT, S>(en, w, kk, ct.avg, basis);
   coarse_mid<T, MPT>(ct, w, kk, y);
   nbar_owned<T, NX, NT, S>(en, y, kk, ct.avg, basis);
@@ -569,13 +585,13 @@ __device__ __forceinline__ void coarse_owned(Engine<T, NX, NT, S>& en,
 
 // Owned modes of a modal FP64 state, rounded to T (zero for unowned slots).
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void load_owned(const cx<double>* __restrict__ src,
+__device__ __forceinline__ void load_owned(const Engine<T, NX, NT, S>& en, const cx<double>* __restrict__ src,
                                            cx<T> (&u)[Engine<T, NX, NT, S>::MPT][3]) {
   using E_ = Engine<T, NX, NT, S>;
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : 0;
-    for (int al = 0; al < 3; ++al) u[j][al] = E_::valid(j) ? cvt<T>(src[al * E_::KP + k]) : czero<T>();
+    const int k = en.valid(j) ? en.mode(j) : 0;
+    for (int al = 0; al < 3; ++al) u[j][al] = en.valid(j) ? cvt<T>(src[al * E_::KP + k]) : czero<T>();
   }
 }
 
@@ -595,8 +611,8 @@ __device__ __forceinline__ void coarse_correct(Engine<T, NX, NT, S>& en,
   double num = 0.0, den = 0.0;
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j) {
-    if (!E_::valid(j)) continue;
-    const int k = E_::mode(j);
+    if (!en.valid(j)) continue;
+    const int k = en.mode(j);
     const double wgt = k == 0 ? 1.0 : 2.0;
     for (int al = 0; al < 3; ++al) {
       const int o = al * KP + k;
@@ -614,7 +630,7 @@ __device__ __forceinline__ void coarse_correct(Engine<T, NX, NT, S>& en,
   }
   if (uold) {
     const double2 r = en.block_sum2(num, den);
-    if (threadIdx.x == 0) *part = r;
+    if (en.tid == 0) *part = r;
   }
 }
 
@@ -632,11 +648,11 @@ __device__ __forceinline__ void strang_coarse_job(Engine<T, NX, NT, S>& en, cons
   Basis<T> bs[MPT];
 #pragma unroll
   for (int j = 0; j < MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : 0;
+    const int k = en.valid(j) ? en.mode(j) : 0;
     bs[j] = basis[k];
-    for (int al = 0; al < 3; ++al) g[j][al] = E_::valid(j) ? uprev[al * E_::KP + k] : czero<double>();
+    for (int al = 0; al < 3; ++al) g[j][al] = en.valid(j) ? uprev[al * E_::KP + k] : czero<double>();
   }
-  load_coef64<T, NX, NT, S>(ccoef64, 2, cE2);
+  load_coef64<T, NX, NT, S>(en, ccoef64, 2, cE2);
   strang_regs<T, NX, NT, S>(en, g, 1, cE2, dT, bs);
   coarse_correct<T, NX, NT, S, double>(en, g, unew, gnew, gold, fold, uold, part);
 }
@@ -650,7 +666,7 @@ __device__ __forceinline__ void coarse_job(Engine<T, NX, NT, S>& en, const Coars
                                            const cx<double>* fold, const cx<double>* uold, double2* part) {
   constexpr int MPT = Engine<T, NX, NT, S>::MPT;
   cx<T> u[MPT][3], g[MPT][3];
-  load_owned<T, NX, NT, S>(uprev, u);
+  load_owned<T, NX, NT, S>(en, uprev, u);
   coarse_owned<T, NX, NT, S>(en, u, g, ct, basis);
   coarse_correct<T, NX, NT, S>(en, g, unew, gnew, gold, fold, uold, part);
 }
@@ -668,8 +684,8 @@ __device__ __forceinline__ void copy_job(Engine<T, NX, NT, S>& en, const cx<doub
   double num = 0.0, den = 0.0;
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j) {
-    if (!E_::valid(j)) continue;
-    const int k = E_::mode(j);
+    if (!en.valid(j)) continue;
+    const int k = en.mode(j);
     const double wgt = k == 0 ? 1.0 : 2.0;
     for (int al = 0; al < 3; ++al) {
       const int o = al * KP + k;
@@ -682,7 +698,7 @@ __device__ __forceinline__ void copy_job(Engine<T, NX, NT, S>& en, const cx<doub
     }
   }
   const double2 r = en.block_sum2(num, den);
-  if (threadIdx.x == 0) *part = r;
+  if (en.tid == 0) *part = r;
 }
 
 // r^k = max_n sqrt(num_n / den_n) over the residual parts of one level.
@@ -690,7 +706,7 @@ template <typename T, int NX, int NT, int S>
 __device__ __forceinline__ double level_residual(Engine<T, NX, NT, S>& en, const double2* part, int Ns) {
   __syncthreads();   // the last part was written by thread 0 of this workgroup
   double m = 0.0;
-  for (int n = threadIdx.x; n < Ns; n += NT) {
+  for (int n = en.tid; n < Ns; n += NT) {
     const double2 q = part[n];
     const double r = q.y > 0.0 ? sqrt(q.x / q.y) : (q.x > 0.0 ? INFINITY : 0.0);
     m = (r > m || r != r) ? r : m;
@@ -705,7 +721,7 @@ __device__ __forceinline__ double level_residual(Engine<T, NX, NT, S>& en, const
 // the midpoint state y once and stores it; the stage-2 job of group g loads y
 // and stores S_g of Nbar(y).
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void sum_groups(const cx<T>* __restrict__ P, int groups,
+__device__ __forceinline__ void sum_groups(const Engine<T, NX, NT, S>& en, const cx<T>* __restrict__ P, int groups,
                                            cx<T> (&acc)[Engine<T, NX, NT, S>::MPT][3]) {
   using E_ = Engine<T, NX, NT, S>;
   constexpr int KP = E_::KP;
@@ -722,7 +738,7 @@ __device__ __forceinline__ void sum_groups(const cx<T>* __restrict__ P, int grou
       const cx<T>* Pg = P + size_t(g0 + (b < nb ? b : 0)) * 3 * KP;
 #pragma unroll
       for (int j = 0; j < E_::MPT; ++j)
-        for (int al = 0; al < 3; ++al) v[b][j][al] = E_::valid(j) ? Pg[al * KP + E_::mode(j)] : czero<T>();
+        for (int al = 0; al < 3; ++al) v[b][j][al] = en.valid(j) ? Pg[al * KP + en.mode(j)] : czero<T>();
     }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -735,13 +751,13 @@ __device__ __forceinline__ void sum_groups(const cx<T>* __restrict__ P, int grou
 }
 
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void store_owned(cx<T>* __restrict__ dst,
+__device__ __forceinline__ void store_owned(const Engine<T, NX, NT, S>& en, cx<T>* __restrict__ dst,
                                             const cx<T> (&v)[Engine<T, NX, NT, S>::MPT][3]) {
   using E_ = Engine<T, NX, NT, S>;
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j)
-    if (E_::valid(j))
-      for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = v[j][al];
+    if (en.valid(j))
+      for (int al = 0; al < 3; ++al) dst[al * E_::KP + en.mode(j)] = v[j][al];
 }
 
 // Stage job of group g: stage 1 stores S_g(Nbar(w)) at Pout; stage 2 loads
@@ -760,13 +776,13 @@ __device__ __forceinline__ bool stage_job(Engine<T, NX, NT, S>& en, const Coarse
   using E_ = Engine<T, NX, NT, S>;
   constexpr int MPT = E_::MPT;
   cx<T> u[MPT][3], y[MPT][3], acc[MPT][3];
-  load_owned<T, NX, NT, S>(uprev, u);
-  coarse_begin<T, NX, NT, S>(ct, u, w, cr);
+  load_owned<T, NX, NT, S>(en, uprev, u);
+  coarse_begin<T, NX, NT, S>(en, ct, u, w, cr);
   if (stage == 2) {
     if (!wait_y()) return false;
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
-      for (int al = 0; al < 3; ++al) y[j][al] = E_::valid(j) ? Y[al * E_::KP + E_::mode(j)] : czero<T>();
+      for (int al = 0; al < 3; ++al) y[j][al] = en.valid(j) ? Y[al * E_::KP + en.mode(j)] : czero<T>();
   } else {
 #pragma unroll
     for (int j = 0; j < MPT; ++j)
@@ -775,7 +791,7 @@ __device__ __forceinline__ bool stage_job(Engine<T, NX, NT, S>& en, const Coarse
   const int mb = 1 + g * ct.avg.gs;
   const int me = min(ct.avg.M, mb + ct.avg.gs);
   nbar_range<T, NX, NT, S>(en, y, acc, mb, me, false, ct.avg, basis);
-  store_owned<T, NX, NT, S>(Pout, acc);
+  store_owned<T, NX, NT, S>(en, Pout, acc);
   return true;
 }
 
@@ -783,25 +799,25 @@ __device__ __forceinline__ bool stage_job(Engine<T, NX, NT, S>& en, const Coarse
 // of the stage-1 group sums at P1 (in group order), then y from w, stored at Y
 // in the working precision (the stage-2 jobs load exactly these values).
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void stage_mid(const CoarseTab<T>& ct, const cx<T>* P1, int groups,
-                                          const cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3], cx<T>* Y) {
+__device__ __forceinline__ void stage_mid(const Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct, const cx<T>* P1,
+                                          int groups, const cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3], cx<T>* Y) {
   constexpr int MPT = Engine<T, NX, NT, S>::MPT;
   cx<T> acc[MPT][3], y[MPT][3];
-  sum_groups<T, NX, NT, S>(P1, groups, acc);
+  sum_groups<T, NX, NT, S>(en, P1, groups, acc);
   coarse_mid<T, MPT>(ct, w, acc, y);
-  store_owned<T, NX, NT, S>(Y, y);
+  store_owned<T, NX, NT, S>(en, Y, y);
 }
 
 // The finishing part of a split step: Nbar(y) = sum of the stage-2 group sums,
 // then the end of the step (the correction follows via coarse_correct).
 template <typename T, int NX, int NT, int S>
-__device__ __forceinline__ void stage_finish(const CoarseTab<T>& ct, const cx<T>* P2, int groups,
-                                             const cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3],
+__device__ __forceinline__ void stage_finish(const Engine<T, NX, NT, S>& en, const CoarseTab<T>& ct, const cx<T>* P2,
+                                             int groups, const cx<T> (&w)[Engine<T, NX, NT, S>::MPT][3],
                                              const CoarseRegs<T, Engine<T, NX, NT, S>::MPT>& cr,
                                              cx<T> (&g)[Engine<T, NX, NT, S>::MPT][3]) {
   constexpr int MPT = Engine<T, NX, NT, S>::MPT;
   cx<T> k2[MPT][3];
-  sum_groups<T, NX, NT, S>(P2, groups, k2);
+  sum_groups<T, NX, NT, S>(en, P2, groups, k2);
   coarse_end<T, MPT>(ct, cr, w, k2, g);
 }
 

@@ -120,15 +120,15 @@ __global__ void __launch_bounds__(NT) k_nonlinear(const cx<double>* __restrict__
   Basis<T> bs[E_::MPT];
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j) {
-    const int k = E_::valid(j) ? E_::mode(j) : 0;
+    const int k = en.valid(j) ? en.mode(j) : 0;
     bs[j] = basis[k];
-    for (int al = 0; al < 3; ++al) c[j][al] = E_::valid(j) ? cvt<T>(src[al * E_::KP + k]) : czero<T>();
+    for (int al = 0; al < 3; ++al) c[j][al] = en.valid(j) ? cvt<T>(src[al * E_::KP + k]) : czero<T>();
   }
   en.neval(0, c, n, bs);
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j)
-    if (E_::valid(j))
-      for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = cvt<double>(n[j][al]);
+    if (en.valid(j))
+      for (int al = 0; al < 3; ++al) dst[al * E_::KP + en.mode(j)] = cvt<double>(n[j][al]);
 }
 
 template <typename T, int NX, int NT>
@@ -157,12 +157,12 @@ __global__ void __launch_bounds__(NT) k_average(const cx<double>* __restrict__ U
   const cx<double>* src = Uin + size_t(blockIdx.x) * 3 * E_::KP;
   cx<double>* dst = Nout + size_t(blockIdx.x) * 3 * E_::KP;
   cx<T> y[E_::MPT][3], acc[E_::MPT][3];
-  load_owned<T, NX, NT, S>(src, y);
+  load_owned<T, NX, NT, S>(en, src, y);
   nbar_owned<T, NX, NT, S>(en, y, acc, av, basis);
 #pragma unroll
   for (int j = 0; j < E_::MPT; ++j)
-    if (E_::valid(j))
-      for (int al = 0; al < 3; ++al) dst[al * E_::KP + E_::mode(j)] = cvt<double>(acc[j][al]);
+    if (en.valid(j))
+      for (int al = 0; al < 3; ++al) dst[al * E_::KP + en.mode(j)] = cvt<double>(acc[j][al]);
 }
 
 template <typename T, int NX, int NT, int S>

@@ -196,18 +196,17 @@ __device__ __forceinline__ bool count_in_last(int* ctr, int groups, int* s_flag)
   return __builtin_amdgcn_readfirstlane(*s_flag) != 0;
 }
 
-// The fine slices of a job, called rather than inlined: one call per job (a
-// job steps for hundreds of microseconds, so the call costs nothing
-// measurable), and the stepping loop gets a register allocation of its own
-// instead of sharing one with every other job type (and, in a kernel for
-// several grid sizes, with every other size).  The caller has staged the
-// twiddles.
-template <typename T, int NX, int JM>
-__device__ __attribute__((noinline)) void fine_slices_job(unsigned char* smem, const cx<T>* tw, int kind, int J,
+// The fine slices of a job as an out-of-line call, Strang (KIND 1) or ETDRK4
+// (KIND 0): one call per job, and the stepping loop gets a register
+// allocation of its own instead of sharing one with every other job type.
+// The caller has staged the twiddles.  A kernel for several grid sizes runs
+// its ETDRK4 fine jobs inline instead (run_fine_job).
+template <typename T, int NX, int JM, int KIND>
+__device__ __attribute__((noinline)) void fine_slices_job(unsigned char* smem, const cx<T>* tw, int J,
                                                           const cx<double>* src0, const cx<double>* src1,
                                                           cx<double>* dst, int steps, const cx<double>* coef64,
                                                           const cx<T>* coef, double hf, const Basis<T>* basis) {
-  if (kind == 1) {
+  if constexpr (KIND == 1) {
     Engine<T, NX, kPipeThreads, pipe_slots<T, NX>()> en(smem, tw, false);
     strang_job<T, NX, kPipeThreads, pipe_slots<T, NX>(), JM>(en, J, src0, src1, dst, steps, coef64, hf, basis);
   } else {
@@ -216,10 +215,58 @@ __device__ __attribute__((noinline)) void fine_slices_job(unsigned char* smem, c
   }
 }
 
+// State of slice `slice` at level lvl in a problem's U, F or G array (Ns + 1
+// slices per level, 3 KP coefficients per slice).
+__device__ __forceinline__ cx<double>* pipe_state(cx<double>* A, int Ns, size_t st, int lvl, int slice) {
+  return A + (size_t(lvl) * (Ns + 1) + slice) * st;
+}
+
+// An ETDRK4 fine job (slices n .. n + J - 1 of level k) of grid size NX,
+// inlined into a kernel for several grid sizes rather than called.  The
+// stepping loop keeps up to 256 VGPRs live; in a called function the calling
+// convention makes it save and restore every callee-saved one of them around
+// each job, some 200 KiB of scratch traffic each way per job at 512 threads.
+// A kernel saves none.  The engine's thread index is salted with the job
+// number jt, so that the job's per-thread values stay inside the job.
+// Returns the first fine counter to publish; npub = J.
+template <typename T, int NX>
+__device__ __forceinline__ int run_fine_job(unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
+                                            const void*& staged, int jt, int& npub) {
+  using FE = PipeFineEngine<T, NX>;
+  constexpr int S = pipe_slots<T, NX>();
+  const PipeIdx ix{p.Ns, p.K};
+  const int Ns = p.Ns, k = jb.k, n = jb.n;
+  const int J = jb.g > 1 ? min(jb.g, pipe_fine_slices<T, NX>(0)) : 1;
+  npub = J;
+  FE en(smem, p.tw, staged != static_cast<const void*>(p.tw), jt);
+  staged = FE::TW_LDS ? static_cast<const void*>(p.tw) : nullptr;
+  const size_t st = size_t(3) * FE::KP;
+  // slice n reads U(k, n - 1) (U(0, 0) for n = 1), slices n + s read U(k, n + s - 1)
+  const cx<double>* src0 = n == 1 ? p.U : pipe_state(p.U, Ns, st, k, n - 1);
+  const cx<double>* src1 = pipe_state(p.U, Ns, st, k, n);
+  cx<double>* dst = pipe_state(p.F, Ns, st, k, n);
+  if (J == 1)
+    fine_job<T, NX, kPipeThreads, S, 1>(en, 1, src0, src1, dst, p.steps, p.coef64, p.coef, p.basis);
+  else
+    fine_job<T, NX, kPipeThreads, S, 0>(en, J, src0, src1, dst, p.steps, p.coef64, p.coef, p.basis);
+  return ix.fine(k, n);
+}
+
+template <typename T, int NX, int... REST>
+__device__ __forceinline__ int dispatch_fine(int nx, unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
+                                             const void*& staged, int jt, int& npub) {
+  if (nx == NX) return run_fine_job<T, NX>(smem, jb, p, staged, jt, npub);
+  if constexpr (sizeof...(REST) > 0)
+    return dispatch_fine<T, REST...>(nx, smem, jb, p, staged, jt, npub);
+  else
+    return -1;
+}
+
 // Runs job jb of problem p (grid size NX) in this workgroup.  Returns the
 // counter index to publish when the job's results are complete, or -1.
-// `staged` tracks the twiddle table held in LDS across jobs.
-template <typename T, int NX>
+// `staged` tracks the twiddle table held in LDS across jobs.  KFINE: the
+// kernel runs ETDRK4 fine jobs itself (run_fine_job), so jb is never one.
+template <typename T, int NX, bool KFINE>
 __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
                                        const void*& staged, int* diag, int jt, int* s_flag, bool skip, int& npub) {
   constexpr int NT = kPipeThreads;
@@ -249,7 +296,7 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
   E_ en(smem, p.tw, stage);
   staged = E_::TW_LDS ? static_cast<const void*>(p.tw) : nullptr;
   const size_t st = size_t(3) * E_::KP;
-  auto state = [&](cx<double>* A, int lvl, int slice) { return A + (size_t(lvl) * (Ns + 1) + slice) * st; };
+  auto state = [&](cx<double>* A, int lvl, int slice) { return pipe_state(A, Ns, st, lvl, slice); };
   const cx<double>* uprev = n == 1 ? state(p.U, 0, 0) : state(p.U, k, n - 1);
   // Completing C(k, Ns) completes level k: with a tolerance, its residual
   // decides whether the problem stops here (levels complete in order).
@@ -268,12 +315,22 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
     // slice n reads uprev, slices n + s (s >= 1) read U(k, n + s - 1), stored in order from U(k, n)
     const cx<double>* src1 = state(p.U, k, n);
     cx<double>* dst = state(p.F, k, n);
-    if (J == 1)
-      fine_slices_job<T, NX, 1>(smem, p.tw, p.fine_kind, 1, uprev, src1, dst, p.steps, p.coef64, p.coef, p.hf,
-                                p.basis);
-    else
-      fine_slices_job<T, NX, 0>(smem, p.tw, p.fine_kind, J, uprev, src1, dst, p.steps, p.coef64, p.coef, p.hf,
-                                p.basis);
+    bool done = false;
+    if constexpr (!KFINE) {
+      if (p.fine_kind == 0) {
+        if (J == 1)
+          fine_slices_job<T, NX, 1, 0>(smem, p.tw, 1, uprev, src1, dst, p.steps, p.coef64, p.coef, p.hf, p.basis);
+        else
+          fine_slices_job<T, NX, 0, 0>(smem, p.tw, J, uprev, src1, dst, p.steps, p.coef64, p.coef, p.hf, p.basis);
+        done = true;
+      }
+    }
+    if (!done) {
+      if (J == 1)
+        fine_slices_job<T, NX, 1, 1>(smem, p.tw, 1, uprev, src1, dst, p.steps, p.coef64, p.coef, p.hf, p.basis);
+      else
+        fine_slices_job<T, NX, 0, 1>(smem, p.tw, J, uprev, src1, dst, p.steps, p.coef64, p.coef, p.hf, p.basis);
+    }
     return ix.fine(k, n);
   }
   if (jb.type == kJobCopy) {
@@ -314,7 +371,7 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
                             [] { return true; });
     // the last group to arrive forms y for the stage-2 jobs and publishes
     if (!count_in_last(&p.cnt[ix.stage1(k, n)], p.groups, s_flag)) return -1;
-    stage_mid<T, NX, NT, S>(p.ct, p.P1 + lvl1, p.groups, w, Y);
+    stage_mid<T, NX, NT, S>(en, p.ct, p.P1 + lvl1, p.groups, w, Y);
     return ix.stage1(k, n);
   }
   // wait for the midpoint (every stage-1 group and y): thread 0 for the
@@ -353,7 +410,7 @@ __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, c
   const int finish = __builtin_amdgcn_readfirstlane(*s_flag);
   if (!finish) return -1;
   cx<T> g[MPT][3];
-  stage_finish<T, NX, NT, S>(p.ct, p.P2 + lvl, p.groups, w, cr, g);
+  stage_finish<T, NX, NT, S>(en, p.ct, p.P2 + lvl, p.groups, w, cr, g);
   if (k == 0)
     coarse_correct<T, NX, NT, S>(en, g, state(p.U, 0, n), state(p.G, 0, n), nullptr, nullptr, nullptr, nullptr);
   else
@@ -381,7 +438,7 @@ __device__ __attribute__((noinline)) JobOut run_job_call(unsigned char* smem, Pi
   JobOut o;
   o.staged = staged;
   o.npub = 1;
-  o.pub = run_job<T, NX>(smem, jb, *p, o.staged, diag, jt, s_flag, skip, o.npub);
+  o.pub = run_job<T, NX, true>(smem, jb, *p, o.staged, diag, jt, s_flag, skip, o.npub);
   return o;
 }
 
@@ -396,7 +453,7 @@ __device__ __forceinline__ int dispatch_job(int nx, unsigned char* smem, const P
       npub = o.npub;
       return o.pub;
     } else {
-      return run_job<T, NX>(smem, jb, p, staged, diag, jt, s_flag, skip, npub);
+      return run_job<T, NX, false>(smem, jb, p, staged, diag, jt, s_flag, skip, npub);
     }
   }
   if constexpr (sizeof...(REST) > 0)
@@ -461,8 +518,18 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
     const int nx = __builtin_amdgcn_readfirstlane(p.nx);
     const bool skip = __builtin_amdgcn_readfirstlane(s_skip) != 0;
     int np = 1;
-    pub = __builtin_amdgcn_readfirstlane(
-        dispatch_job<T, (sizeof...(NXS) > 1), NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip, np));
+    // a kernel for several grid sizes runs ETDRK4 fine jobs inline, the other jobs as calls
+    constexpr bool kMulti = sizeof...(NXS) > 1;
+    bool ran = false;
+    if constexpr (kMulti) {
+      if (!skip && jb.type == kJobFine && __builtin_amdgcn_readfirstlane(p.fine_kind) == 0) {
+        pub = __builtin_amdgcn_readfirstlane(dispatch_fine<T, NXS...>(nx, smem_raw, jb, p, staged, j, np));
+        ran = true;
+      }
+    }
+    if (!ran)
+      pub = __builtin_amdgcn_readfirstlane(
+          dispatch_job<T, kMulti, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip, np));
     npub = __builtin_amdgcn_readfirstlane(np);
     pub_cnt = p.cnt;
     // Every wavefront waits for its stores of the job's results to reach the

@@ -20,6 +20,21 @@
 
 namespace ap {
 
+// This thread's index in its workgroup of NT threads, passed through an empty
+// asm statement that also takes `salt`.  A persistent kernel passes the
+// number of the job it runs: what a job derives from the index (mode numbers,
+// wavenumbers, LDS addresses) then depends on the job, and the compiler cannot
+// hoist it out of the job loop, where it would stay live across every other
+// kind of job and spill.  The statement has no side effects, so the uses
+// within one job still share one value.
+template <int NT>
+__device__ __forceinline__ unsigned salted_thread(int salt) {
+  unsigned t = threadIdx.x;
+  asm("" : "+v"(t) : "s"(salt));
+  __builtin_assume(t < NT);
+  return t;
+}
+
 // Complex value aligned to its size, so that LDS and global accesses are
 // single 64-bit (float) or 128-bit (double) operations.  Two 32-bit LDS
 // accesses to consecutive complex floats would map lanes i and i + 32 to one

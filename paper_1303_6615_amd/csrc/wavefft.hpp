@@ -587,9 +587,6 @@ struct Slot {
   static constexpr size_t bytes = (sp_elems + ib_elems) * sizeof(cx<T>);
 };
 
-// Inverse transforms of the 3*ns field spectra in SP (entries k <= Kd written,
-// entries Kd < k <= P zero: see zero_tails) into IB, one signal per lane group
-// at a time.  The loads of the first pass are unconditional.
 // First-pass source of an inverse transform: Z[k] = (X[k] + conj X[P-k])
 // + i conj(t_k) (X[k] - conj X[P-k]) from the half spectrum X (stride P+1),
 // t_k = exp(-2 pi i k/N).  With s and d the sum and difference, the product
@@ -619,13 +616,14 @@ struct ReadHalfSpectrum {
 // loads to the zero stores of zero_tails and split them into conditional
 // loads (each with its own wait).
 // Runs body(v0) for the first signal v0 of each round of transforms of this
-// wavefront over nsig signals.  When MAXNS states (3 MAXNS signals) fit one
+// wavefront over nsig signals (tid: the thread's index in the workgroup, as
+// in the engine; the field and product transforms take it too).  When MAXNS states (3 MAXNS signals) fit one
 // round of the workgroup's wavefronts, the round is straight-line code, and
 // the signal's offsets are the same in every evaluation of a job.
 template <int NT, int SPW, int MAXNS, typename B>
-__device__ __forceinline__ void signal_rounds(int nsig, B&& body) {
+__device__ __forceinline__ void signal_rounds(int nsig, unsigned tid, B&& body) {
   constexpr int NW = NT / 64;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if constexpr (MAXNS > 0 && NW * SPW >= 3 * MAXNS) {
     if (wave * SPW < nsig) body(wave * SPW);
   } else {
@@ -634,15 +632,15 @@ __device__ __forceinline__ void signal_rounds(int nsig, B&& body) {
 }
 
 template <typename T, int NX, int NT, int MAXNS = 0, int PLAN = 0>
-__device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, const cx<T>* tw) {
+__device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, const cx<T>* tw, unsigned tid) {
   using G_ = Geo<NX>;
   constexpr int P = G_::P;
   constexpr int G = WavePlan<P>::G;
   constexpr int SPW = 64 / G;             // signals per wavefront
-  const int lane = threadIdx.x & 63;
+  const int lane = tid & 63;
   const int group = lane / G, lig = lane - group * G;
   const int nsig = 3 * ns;
-  signal_rounds<NT, SPW, MAXNS>(nsig, [&](int v0) {
+  signal_rounds<NT, SPW, MAXNS>(nsig, tid, [&](int v0) {
     const int v = v0 + group < nsig ? v0 + group : v0;
     int off = v * (P + 1);
     asm volatile("" : "+v"(off));
@@ -655,11 +653,11 @@ __device__ __forceinline__ void inverse_fields(cx<T>* sp, cx<T>* ib, int ns, con
 // thread between the writes of the retained modes and the barrier before the
 // inverse transforms.
 template <typename T, int NX, int NT>
-__device__ __forceinline__ void zero_tails(cx<T>* sp, int ns) {
+__device__ __forceinline__ void zero_tails(cx<T>* sp, int ns, unsigned tid) {
   constexpr int P = Geo<NX>::P;
   constexpr int KD = Geo<NX>::KD;
   constexpr int TL = P - KD;
-  for (int i = threadIdx.x; i < 3 * ns * TL; i += NT) {
+  for (int i = tid; i < 3 * ns * TL; i += NT) {
     const int v = i / TL;
     sp[v * (P + 1) + KD + 1 + (i - v * TL)] = czero<T>();
   }
@@ -686,14 +684,15 @@ struct ReadProducts {
 // both factors and scales by 1/2 or 1, with no branch on the product; lane
 // groups past the last signal repeat their wavefront's first one.
 template <typename T, int NX, int NT, int MAXNS = 0, int PLAN = 0>
-__device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int ns, const cx<T>* tw) {
+__device__ __forceinline__ void forward_products(cx<T>* sp, const cx<T>* ib, int ns, const cx<T>* tw,
+                                                 unsigned tid) {
   constexpr int P = Geo<NX>::P;
   constexpr int G = WavePlan<P>::G;
   constexpr int SPW = 64 / G;
-  const int lane = threadIdx.x & 63;
+  const int lane = tid & 63;
   const int group = lane / G, lig = lane - group * G;
   const int nsig = 3 * ns;
-  signal_rounds<NT, SPW, MAXNS>(nsig, [&](int v0) {
+  signal_rounds<NT, SPW, MAXNS>(nsig, tid, [&](int v0) {
     const int vv = v0 + group < nsig ? v0 + group : v0;
     const int s = vv / 3, f = vv - 3 * s;
     const cx<T>* V1 = ib + (3 * s) * P;
