@@ -221,8 +221,20 @@ __device__ __forceinline__ cx<double>* pipe_state(cx<double>* A, int Ns, size_t 
   return A + (size_t(lvl) * (Ns + 1) + slice) * st;
 }
 
+// Whether a pipeline kernel runs the ETDRK4 fine jobs of grid size NX inline
+// (run_fine_job) rather than as calls (MULTI: the kernel serves several
+// sizes; its other jobs are calls).  FP32 only, and up to N = 1024 (several
+// sizes) or N = 256 (one size, whose other jobs are inlined too): there the
+// inlined job needs little or no scratch.  Larger sizes, FP64, and N = 1024
+// beside an inlined coarse path spilled inside the stepping loop, and the
+// N = 1024 solve ran slower than with the called job.
+template <typename T, int NX, bool MULTI>
+constexpr bool pipe_inline_fine() {
+  return sizeof(T) == 4 && NX <= (MULTI ? 1024 : 256);
+}
+
 // An ETDRK4 fine job (slices n .. n + J - 1 of level k) of grid size NX,
-// inlined into a kernel for several grid sizes rather than called.  The
+// inlined into the pipeline kernel rather than called.  The
 // stepping loop keeps up to 256 VGPRs live; in a called function the calling
 // convention makes it save and restore every callee-saved one of them around
 // each job, some 200 KiB of scratch traffic each way per job at 512 threads.
@@ -252,20 +264,25 @@ __device__ __forceinline__ int run_fine_job(unsigned char* smem, const PipeJob& 
   return ix.fine(k, n);
 }
 
-template <typename T, int NX, int... REST>
+// Runs an ETDRK4 fine job of grid size nx inline when the kernel does so for
+// that size; returns its first counter, or kNotRun.
+constexpr int kNotRun = -2;
+template <typename T, bool MULTI, int NX, int... REST>
 __device__ __forceinline__ int dispatch_fine(int nx, unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
                                              const void*& staged, int jt, int& npub) {
-  if (nx == NX) return run_fine_job<T, NX>(smem, jb, p, staged, jt, npub);
+  if constexpr (pipe_inline_fine<T, NX, MULTI>())
+    if (nx == NX) return run_fine_job<T, NX>(smem, jb, p, staged, jt, npub);
   if constexpr (sizeof...(REST) > 0)
-    return dispatch_fine<T, REST...>(nx, smem, jb, p, staged, jt, npub);
+    return dispatch_fine<T, MULTI, REST...>(nx, smem, jb, p, staged, jt, npub);
   else
-    return -1;
+    return kNotRun;
 }
 
 // Runs job jb of problem p (grid size NX) in this workgroup.  Returns the
 // counter index to publish when the job's results are complete, or -1.
 // `staged` tracks the twiddle table held in LDS across jobs.  KFINE: the
-// kernel runs ETDRK4 fine jobs itself (run_fine_job), so jb is never one.
+// kernel runs the ETDRK4 fine jobs of this size itself (run_fine_job), so jb
+// is never one.
 template <typename T, int NX, bool KFINE>
 __device__ __forceinline__ int run_job(unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
                                        const void*& staged, int* diag, int jt, int* s_flag, bool skip, int& npub) {
@@ -438,10 +455,11 @@ __device__ __attribute__((noinline)) JobOut run_job_call(unsigned char* smem, Pi
   JobOut o;
   o.staged = staged;
   o.npub = 1;
-  o.pub = run_job<T, NX, true>(smem, jb, *p, o.staged, diag, jt, s_flag, skip, o.npub);
+  o.pub = run_job<T, NX, pipe_inline_fine<T, NX, true>()>(smem, jb, *p, o.staged, diag, jt, s_flag, skip, o.npub);
   return o;
 }
 
+// CALL: the job runs as a call (run_job_call), in a kernel for several sizes.
 template <typename T, bool CALL, int NX, int... REST>
 __device__ __forceinline__ int dispatch_job(int nx, unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
                                             const void*& staged, int* diag, int jt, int* s_flag, bool skip,
@@ -453,7 +471,7 @@ __device__ __forceinline__ int dispatch_job(int nx, unsigned char* smem, const P
       npub = o.npub;
       return o.pub;
     } else {
-      return run_job<T, NX, false>(smem, jb, p, staged, diag, jt, s_flag, skip, npub);
+      return run_job<T, NX, pipe_inline_fine<T, NX, false>()>(smem, jb, p, staged, diag, jt, s_flag, skip, npub);
     }
   }
   if constexpr (sizeof...(REST) > 0)
@@ -518,18 +536,14 @@ __global__ void __launch_bounds__(kPipeThreads) k_pipeline(const PipeJob* __rest
     const int nx = __builtin_amdgcn_readfirstlane(p.nx);
     const bool skip = __builtin_amdgcn_readfirstlane(s_skip) != 0;
     int np = 1;
-    // a kernel for several grid sizes runs ETDRK4 fine jobs inline, the other jobs as calls
+    // ETDRK4 fine jobs of the sizes pipe_inline_fine names run inline, the
+    // other jobs through dispatch_job (as calls in a kernel for several sizes)
     constexpr bool kMulti = sizeof...(NXS) > 1;
-    bool ran = false;
-    if constexpr (kMulti) {
-      if (!skip && jb.type == kJobFine && __builtin_amdgcn_readfirstlane(p.fine_kind) == 0) {
-        pub = __builtin_amdgcn_readfirstlane(dispatch_fine<T, NXS...>(nx, smem_raw, jb, p, staged, j, np));
-        ran = true;
-      }
-    }
-    if (!ran)
-      pub = __builtin_amdgcn_readfirstlane(
-          dispatch_job<T, kMulti, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip, np));
+    int r = kNotRun;
+    if (!skip && jb.type == kJobFine && __builtin_amdgcn_readfirstlane(p.fine_kind) == 0)
+      r = dispatch_fine<T, kMulti, NXS...>(nx, smem_raw, jb, p, staged, j, np);
+    if (r == kNotRun) r = dispatch_job<T, kMulti, NXS...>(nx, smem_raw, jb, p, staged, abort, j, &s_flag, skip, np);
+    pub = __builtin_amdgcn_readfirstlane(r);
     npub = __builtin_amdgcn_readfirstlane(np);
     pub_cnt = p.cnt;
     // Every wavefront waits for its stores of the job's results to reach the
