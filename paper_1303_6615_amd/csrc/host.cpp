@@ -1129,6 +1129,45 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     return hip_fail(e, "problem descriptor upload");
   if ((e = upload_if_changed(owner, owner->pp_rows, owner->pp_rows_host, as_bytes(rows))) != hipSuccess)
     return hip_fail(e, "residual table upload");
+  // Boundary transforms of a batch: one launch per grid size (and per
+  // kBoundaryBatch problems) instead of one per problem, the problems' states
+  // passed by value as the launch's argument.  The modal initial state also
+  // goes to U(K, 0), the last level's slice 0.  A single problem keeps the
+  // direct launches.
+  const bool bnd_batched = items.size() > 1;
+  struct BndLaunch {
+    int nx;
+    ap::BoundaryBatch b;
+  };
+  std::vector<BndLaunch> bnd_in, bnd_out;
+  if (bnd_batched) {
+    std::vector<int> sizes;
+    for (auto& it : items)
+      if (std::find(sizes.begin(), sizes.end(), it.q.nx) == sizes.end()) sizes.push_back(it.q.nx);
+    // appends problem `it` (states states) to the open launch of size nx in v
+    auto add = [](std::vector<BndLaunch>& v, int nx, const ap::BoundaryJob& jb, int states) {
+      if (v.empty() || v.back().nx != nx || v.back().b.n == ap::kBoundaryBatch) {
+        v.push_back(BndLaunch{nx, {}});
+        v.back().b.n = 0;
+        v.back().b.first[0] = 0;
+      }
+      ap::BoundaryBatch& b = v.back().b;
+      b.job[b.n] = jb;
+      b.first[b.n + 1] = b.first[b.n] + states;
+      b.n += 1;
+    };
+    for (int nx : sizes)
+      for (auto& it : items) {
+        if (it.q.nx != nx) continue;
+        ap_ctx* c = it.c;
+        cx<double>* U = c->pp_U.as<cx<double>>();
+        const size_t st = size_t(3) * c->KP;
+        cx<double>* UK0 = it.q.K > 0 ? U + size_t(it.q.K) * (it.q.Ns + 1) * st : nullptr;
+        add(bnd_in, nx, ap::BoundaryJob{it.u0, U, UK0, c->tabs.tw64, c->tabs.basis64}, 1);
+        const cx<double>* UK = U + size_t(it.q.K) * (it.q.Ns + 1) * st;
+        add(bnd_out, nx, ap::BoundaryJob{UK, it.U_out, nullptr, c->tabs.tw64, c->tabs.basis64}, it.q.Ns + 1);
+      }
+  }
   grid = std::max(1, std::min({grid, owner->pp_njobs, 1024}));   // progress record holds 1024 workgroups
   unsigned long long* trace = nullptr;
   if (owner->trace_on) {
@@ -1145,7 +1184,12 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
   auto enqueue = [&](hipStream_t st, bool time_it) -> int {
     auto run = [&](int cls, auto&& fn) { return time_it ? timed(owner, cls, st, fn) : fn(); };
     hipError_t err;
+    for (const BndLaunch& g : bnd_in) {
+      err = run(AP_K_TO_MODAL, [&] { return ap::launch_to_modal_batch(g.nx, g.b, st); });
+      if (err != hipSuccess) return hip_fail(err, "to_modal");
+    }
     for (auto& it : items) {
+      if (bnd_batched) break;
       ap_ctx* c = it.c;
       cx<double>* U = c->pp_U.as<cx<double>>();
       const size_t sb = state_bytes(c);
@@ -1177,8 +1221,13 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
           (err = ap::launch_select_level(c->pp_U.as<cx<double>>(), it.q.Ns, it.q.K, c->KP, stop, st)) !=
               hipSuccess)
         return hip_fail(err, "level selection");
+      if (bnd_batched) continue;
       const cx<double>* UK = c->pp_U.as<cx<double>>() + size_t(it.q.K) * (it.q.Ns + 1) * 3 * c->KP;
       err = run(AP_K_TO_PHYSICAL, [&] { return ap::launch_to_physical(c->N, UK, it.U_out, it.q.Ns + 1, c->tabs, st); });
+      if (err != hipSuccess) return hip_fail(err, "to_physical");
+    }
+    for (const BndLaunch& g : bnd_out) {
+      err = run(AP_K_TO_PHYSICAL, [&] { return ap::launch_to_physical_batch(g.nx, g.b, st); });
       if (err != hipSuccess) return hip_fail(err, "to_physical");
     }
     return AP_OK;

@@ -26,11 +26,13 @@
 namespace ap {
 
 // ------------------------------------------------- boundary transforms -----
-// physical [B][3][N] float64 -> modal [B][3][KP] complex float64 (projected)
+// One state in one workgroup: physical [3][N] float64 -> modal [3][KP]
+// complex float64 (projected), written to dst and, when dst2 is not null, to
+// dst2 as well.
 template <int NX, int NT>
-__global__ void __launch_bounds__(NT) k_to_modal(const double* __restrict__ phys, cx<double>* __restrict__ modal,
-                                                 const cx<double>* __restrict__ tw_g,
-                                                 const Basis<double>* __restrict__ basis) {
+__device__ __forceinline__ void to_modal_block(const double* __restrict__ src, cx<double>* __restrict__ dst,
+                                               cx<double>* __restrict__ dst2, const cx<double>* __restrict__ tw_g,
+                                               const Basis<double>* __restrict__ basis) {
   using G = Geo<NX>;
   using T = double;
   constexpr int P = G::P;
@@ -39,7 +41,6 @@ __global__ void __launch_bounds__(NT) k_to_modal(const double* __restrict__ phys
   cx<T>* a = tw + NX;
   cx<T>* b = a + 3 * P;
   for (int i = threadIdx.x; i < NX; i += NT) tw[i] = tw_g[i];
-  const double* src = phys + size_t(blockIdx.x) * 3 * NX;
   for (int i = threadIdx.x; i < 3 * P; i += NT) {
     const int f = i / P, n = i - f * P;
     a[f * P + n] = cx<T>{src[f * NX + 2 * n], src[f * NX + 2 * n + 1]};
@@ -47,7 +48,6 @@ __global__ void __launch_bounds__(NT) k_to_modal(const double* __restrict__ phys
   __syncthreads();
   cx<T>* R = fft_lds<T, P, -1, NT>(a, b, 3, tw);
   const T half_over_n = T(0.5) / T(NX);
-  cx<double>* dst = modal + size_t(blockIdx.x) * 3 * G::KP;
   for (int k = threadIdx.x; k < G::KP; k += NT) {
     const cx<T> w = tw[k];
     const int kc = (P - k) & (P - 1);
@@ -60,14 +60,45 @@ __global__ void __launch_bounds__(NT) k_to_modal(const double* __restrict__ phys
     cx<T> c[3];
     fields_to_modal<T>(X[0], X[1], X[2], basis[k], c);
     for (int al = 0; al < 3; ++al) dst[al * G::KP + k] = c[al];
+    if (dst2)
+      for (int al = 0; al < 3; ++al) dst2[al * G::KP + k] = c[al];
   }
 }
 
-// modal [B][3][KP] -> physical [B][3][N]
+// physical [B][3][N] float64 -> modal [B][3][KP] complex float64 (projected)
 template <int NX, int NT>
-__global__ void __launch_bounds__(NT) k_to_physical(const cx<double>* __restrict__ modal, double* __restrict__ phys,
-                                                    const cx<double>* __restrict__ tw_g,
-                                                    const Basis<double>* __restrict__ basis) {
+__global__ void __launch_bounds__(NT) k_to_modal(const double* __restrict__ phys, cx<double>* __restrict__ modal,
+                                                 const cx<double>* __restrict__ tw_g,
+                                                 const Basis<double>* __restrict__ basis) {
+  to_modal_block<NX, NT>(phys + size_t(blockIdx.x) * 3 * NX, modal + size_t(blockIdx.x) * 3 * Geo<NX>::KP, nullptr,
+                         tw_g, basis);
+}
+
+// The problem of a batch that workgroup `block` belongs to, and the state's
+// index within it.
+__device__ __forceinline__ int batch_problem(const BoundaryBatch& b, int block, int& state) {
+  int i = 0;
+  while (i + 1 < b.n && block >= b.first[i + 1]) ++i;
+  state = block - b.first[i];
+  return i;
+}
+
+// One state per workgroup over a batch of problems of one grid size.
+template <int NX, int NT>
+__global__ void __launch_bounds__(NT) k_to_modal_batch(const BoundaryBatch b) {
+  int j = 0;
+  const BoundaryJob& jb = b.job[batch_problem(b, blockIdx.x, j)];
+  constexpr size_t KS = size_t(3) * Geo<NX>::KP;
+  cx<double>* dst2 = jb.dst2 ? jb.dst2 + j * KS : nullptr;
+  to_modal_block<NX, NT>(static_cast<const double*>(jb.src) + j * size_t(3) * NX,
+                         static_cast<cx<double>*>(jb.dst) + j * KS, dst2, jb.tw, jb.basis);
+}
+
+// One state in one workgroup: modal [3][KP] -> physical [3][N].
+template <int NX, int NT>
+__device__ __forceinline__ void to_physical_block(const cx<double>* __restrict__ src, double* __restrict__ dst,
+                                                  const cx<double>* __restrict__ tw_g,
+                                                  const Basis<double>* __restrict__ basis) {
   using G = Geo<NX>;
   using T = double;
   constexpr int P = G::P;
@@ -80,7 +111,6 @@ __global__ void __launch_bounds__(NT) k_to_physical(const cx<double>* __restrict
   cx<T>* b = spec;
   for (int i = threadIdx.x; i < NX; i += NT) tw[i] = tw_g[i];
   zero_spec_tail<T, NX, NT>(spec, 1);
-  const cx<double>* src = modal + size_t(blockIdx.x) * 3 * G::KP;
   const T s = T(0.70710678118654752440);
   for (int k = threadIdx.x; k < G::KP; k += NT) {
     const cx<T> c0 = src[k], c1 = src[G::KP + k], c2 = src[2 * G::KP + k];
@@ -98,13 +128,29 @@ __global__ void __launch_bounds__(NT) k_to_physical(const cx<double>* __restrict
   }
   __syncthreads();
   cx<T>* R = fft_lds<T, P, +1, NT>(a, b, 3, tw);
-  double* dst = phys + size_t(blockIdx.x) * 3 * NX;
   for (int i = threadIdx.x; i < 3 * P; i += NT) {
     const int f = i / P, n = i - f * P;
     const cx<T> z = R[f * P + n];
     dst[f * NX + 2 * n] = z.x;
     dst[f * NX + 2 * n + 1] = z.y;
   }
+}
+
+// modal [B][3][KP] -> physical [B][3][N]
+template <int NX, int NT>
+__global__ void __launch_bounds__(NT) k_to_physical(const cx<double>* __restrict__ modal, double* __restrict__ phys,
+                                                    const cx<double>* __restrict__ tw_g,
+                                                    const Basis<double>* __restrict__ basis) {
+  to_physical_block<NX, NT>(modal + size_t(blockIdx.x) * 3 * Geo<NX>::KP, phys + size_t(blockIdx.x) * 3 * NX, tw_g,
+                            basis);
+}
+
+template <int NX, int NT>
+__global__ void __launch_bounds__(NT) k_to_physical_batch(const BoundaryBatch b) {
+  int j = 0;
+  const BoundaryJob& jb = b.job[batch_problem(b, blockIdx.x, j)];
+  to_physical_block<NX, NT>(static_cast<const cx<double>*>(jb.src) + j * size_t(3) * Geo<NX>::KP,
+                            static_cast<double*>(jb.dst) + j * size_t(3) * NX, jb.tw, jb.basis);
 }
 
 // ------------------------------------------------------- nonlinear term -----
@@ -282,6 +328,24 @@ static hipError_t to_physical_nx(const cx<double>* modal, double* phys, int batc
   return hipGetLastError();
 }
 
+template <int NX>
+static hipError_t to_modal_batch_nx(const BoundaryBatch& b, hipStream_t s) {
+  constexpr int NT = 256;
+  const size_t lds = (NX + 6 * Geo<NX>::P) * sizeof(cx<double>);
+  prep_lds(k_to_modal_batch<NX, NT>, lds);
+  hipLaunchKernelGGL((k_to_modal_batch<NX, NT>), dim3(b.first[b.n]), dim3(NT), lds, s, b);
+  return hipGetLastError();
+}
+
+template <int NX>
+static hipError_t to_physical_batch_nx(const BoundaryBatch& b, hipStream_t s) {
+  constexpr int NT = 256;
+  const size_t lds = (NX + 3 * (Geo<NX>::P + 1) + 3 * Geo<NX>::P) * sizeof(cx<double>);
+  prep_lds(k_to_physical_batch<NX, NT>, lds);
+  hipLaunchKernelGGL((k_to_physical_batch<NX, NT>), dim3(b.first[b.n]), dim3(NT), lds, s, b);
+  return hipGetLastError();
+}
+
 template <typename T, int NX>
 static hipError_t nonlinear_nx(const cx<double>* in, cx<double>* out, int batch, const DevTables& t, hipStream_t s) {
   constexpr int NT = fine_threads<T, NX>();
@@ -344,6 +408,14 @@ hipError_t launch_to_modal(int nx, const double* phys, cx<double>* modal, int ba
 hipError_t launch_to_physical(int nx, const cx<double>* modal, double* phys, int batch, const DevTables& t,
                               hipStream_t s) {
   AP_DISPATCH_NX(nx, to_physical_nx<NX>(modal, phys, batch, t, s));
+}
+hipError_t launch_to_modal_batch(int nx, const BoundaryBatch& b, hipStream_t s) {
+  if (b.n < 1 || b.n > kBoundaryBatch || b.first[b.n] <= 0) return hipErrorInvalidValue;
+  AP_DISPATCH_NX(nx, to_modal_batch_nx<NX>(b, s));
+}
+hipError_t launch_to_physical_batch(int nx, const BoundaryBatch& b, hipStream_t s) {
+  if (b.n < 1 || b.n > kBoundaryBatch || b.first[b.n] <= 0) return hipErrorInvalidValue;
+  AP_DISPATCH_NX(nx, to_physical_batch_nx<NX>(b, s));
 }
 hipError_t launch_nonlinear(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch,
                             const DevTables& t, hipStream_t s) {

@@ -94,8 +94,30 @@ struct PipeProb {
   const Basis<T>* basis;
 };
 
+// Boundary transforms of up to kBoundaryBatch problems of one grid size in
+// one launch, passed by value as the kernel's argument (no device table, so
+// nothing to upload or wait for).  Problem i covers workgroups first[i] ..
+// first[i+1] - 1, one state each: state j of problem i is read from src and
+// written to dst, each advanced by j states of its form.
+constexpr int kBoundaryBatch = 64;
+struct BoundaryJob {
+  const void* src;              // to modal: double [3][N] per state; to physical: cx<double> [3][KP]
+  void* dst;                    // the other form
+  cx<double>* dst2;             // to modal: a second copy of the modal state, or null
+  const cx<double>* tw;         // the problem's FP64 twiddles
+  const Basis<double>* basis;   // the problem's FP64 modal basis
+};
+struct BoundaryBatch {
+  int n;                              // problems
+  int first[kBoundaryBatch + 1];      // prefix sums of their workgroups
+  BoundaryJob job[kBoundaryBatch];
+};
+static_assert(sizeof(BoundaryBatch) <= 4096, "a kernel argument of at most 4 KiB");
+
 hipError_t launch_to_modal(int nx, const double* phys, cx<double>* modal, int batch, const DevTables& t,
                            hipStream_t s);
+hipError_t launch_to_modal_batch(int nx, const BoundaryBatch& b, hipStream_t s);
+hipError_t launch_to_physical_batch(int nx, const BoundaryBatch& b, hipStream_t s);
 hipError_t launch_to_physical(int nx, const cx<double>* modal, double* phys, int batch, const DevTables& t,
                               hipStream_t s);
 hipError_t launch_nonlinear(int nx, bool fp64, const cx<double>* in, cx<double>* out, int batch,

@@ -381,6 +381,34 @@ def test_batch_of_uneven_problems(torch_cuda, prec, tol, which):
             c.close()
 
 
+def test_batch_of_more_problems_of_one_size_than_one_boundary_launch_takes(torch_cuda):
+    # 70 problems at N = 64 and 2 at N = 128 in one batch: the boundary
+    # transforms of a batch run one launch per grid size and per 64 problems,
+    # so N = 64 takes two launches; every problem equals its solve alone
+    # bitwise, and two of them the oracle
+    from paper_1303_6615_amd.binding import solve_batch
+    torch = torch_cuda
+    probs = [_batch_problem(64, 0.1, 3 + i % 3, 2, 0.06, 8, 200 + i) for i in range(70)]
+    probs += [_batch_problem(128, 0.1, 4, 2, 0.06, 8, 300 + i) for i in range(2)]
+    ctxs = [_ctx(q["n"], q["eps"], q["nu"]) for q in probs]
+    try:
+        items = [(c, torch.tensor(q["u0"], device="cuda"), q["prm"]) for c, q in zip(ctxs, probs)]
+        got = solve_batch(items, precision=FP32)
+        torch.cuda.synchronize()
+        for i, (c, (_, u0, prm), (U, r), q) in enumerate(zip(ctxs, items, got, probs)):
+            Ua, ra = c.solve(u0, prm["T"], prm["slices"], prm["K"], prm["dt_fine"], prm["M"], precision=FP32)
+            torch.cuda.synchronize()
+            assert torch.equal(U, Ua) and torch.equal(r, ra), i
+            if i in (0, 69):
+                steps = int(np.ceil(prm["T"] / prm["slices"] / prm["dt_fine"] - 1e-9))
+                Uref, _, _ = O.parareal_solve(q["u0"], q["n"], q["eps"], 1.0, q["nu"], prm["T"], prm["slices"],
+                                              prm["K"], steps, prm["M"], prm["T"] / prm["slices"] / q["eps"])
+                assert _rel(U.cpu().numpy(), Uref) < 2e-5, i
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_large_solve_first_slices_match_serial_oracle(torch_cuda):
     # The full 1024-point, 256-slice, K = 10 solve as the benchmark times it:
     # after K iterations the first K slices equal the serial fine solution
