@@ -1144,7 +1144,8 @@ int plan_launch(ap_ctx* owner, std::vector<PlanItem>& items, hipStream_t s) {
     std::vector<int> sizes;
     for (auto& it : items)
       if (std::find(sizes.begin(), sizes.end(), it.q.nx) == sizes.end()) sizes.push_back(it.q.nx);
-    // appends problem `it` (states states) to the open launch of size nx in v
+    // appends a problem of `states` states (a workgroup each) to the open
+    // launch of size nx in v, opening a new one when needed
     auto add = [](std::vector<BndLaunch>& v, int nx, const ap::BoundaryJob& jb, int states) {
       if (v.empty() || v.back().nx != nx || v.back().b.n == ap::kBoundaryBatch) {
         v.push_back(BndLaunch{nx, {}});

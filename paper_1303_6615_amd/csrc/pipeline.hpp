@@ -234,13 +234,13 @@ constexpr bool pipe_inline_fine() {
 }
 
 // An ETDRK4 fine job (slices n .. n + J - 1 of level k) of grid size NX,
-// inlined into the pipeline kernel rather than called.  The
-// stepping loop keeps up to 256 VGPRs live; in a called function the calling
-// convention makes it save and restore every callee-saved one of them around
-// each job, some 200 KiB of scratch traffic each way per job at 512 threads.
-// A kernel saves none.  The engine's thread index is salted with the job
-// number jt, so that the job's per-thread values stay inside the job.
-// Returns the first fine counter to publish; npub = J.
+// inlined into the pipeline kernel rather than called.  The stepping loop
+// keeps up to 256 VGPRs live; in a called function the calling convention
+// makes it save and restore every callee-saved one of them around each job,
+// some 200 KiB of scratch traffic each way per job at 512 threads.  A kernel
+// saves none.  The engine's thread index is salted with the job number jt, so
+// that the job's per-thread values stay inside the job.  Returns the first
+// fine counter to publish; npub = J.
 template <typename T, int NX>
 __device__ __forceinline__ int run_fine_job(unsigned char* smem, const PipeJob& jb, const PipeProb<T>& p,
                                             const void*& staged, int jt, int& npub) {
